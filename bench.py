@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark of the Lazy SPCA hot path on one MI355X.
+
+One step = one Lazy SPCA fit of X (Algorithm 2: Omega, Y = X Omega, G, F,
+the small FP64 stage) followed by the projection Z = X V of the same X.
+Workload (default): X 1,000,000 x 4,096 FP32 low-rank-plus-noise (rank-256
+signal, sigma_i = i^-1/2, noise N(0, 0.05^2)), Gaussian Omega, k = 256.
+
+Printed: one JSON line with the X-stream throughput of the step (bytes of X
+the step streams, 2 |X|: once for the fit, once for the projection, over the
+step time), the per-phase device times, the dominant kernel's roofline and
+the FP64 CPU oracle timed on a bounded row sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAKS = {  # MI355X published dense peaks
+    "hbm_GBs": 8000.0,
+    "fp32_mfma_TFs": 157.3,
+    "fp64_mfma_TFs": 78.6,
+    "bf16_mfma_TFs": 2500.0,
+    "fp16_mfma_TFs": 2500.0,
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(cfg, X_dev, budget_s=15.0):
+    """FP64 oracle (numpy, BLAS threads) on a bounded row sample of the same
+    X: one fit plus one projection, scaled to X-stream GB/s."""
+    import numpy as np
+    from oracle import lspca_oracle as O
+    from oracle import philox as P
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    n, k = cfg["n"], cfg["k"]
+    om = P.omega(n, k, cfg["kind"], cfg["omega_seed"], cfg.get("p", 64), dtype=cfg["dtype"])
+    rows = 2048
+    while True:
+        Xh = X_dev[:rows].double().cpu().numpy()
+        t0 = time.perf_counter()
+        fit = O.streaming_lazy_fit(Xh, om, k, S=max(1, rows // 65536))
+        O.transform(Xh, fit["V"])
+        dt = time.perf_counter() - t0
+        if dt * 4 > budget_s or rows * 4 > X_dev.shape[0]:
+            break
+        rows *= 4
+    esz = X_dev.element_size()
+    gbs = 2 * rows * n * esz / dt / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"first {rows} rows of the same X (of {X_dev.shape[0]}): one FP64 oracle "
+                      f"fit (Algorithm 2, numpy/BLAS) plus Z = X V, {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--m", type=int, default=0, help="override rows (smaller runs)")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_1709_07175_amd as lib
+    from synth import config, lowrank_torch
+
+    lib.load()
+    cfg = config(args.config)
+    if args.m:
+        cfg["m"] = args.m
+    m, n, k = cfg["m"], cfg["n"], cfg["k"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"generating X {m}x{n} {cfg['dtype']} (seed {cfg['data_seed']})")
+    t0 = time.time()
+    X = lowrank_torch(m, n, cfg["r"], cfg["spectrum"], cfg["s"], cfg["data_seed"], cfg["dtype"],
+                      device=dev)
+    torch.cuda.synchronize()
+    log(f"generated in {time.time() - t0:.1f}s")
+    xbytes = X.numel() * X.element_size()
+    stream = torch.cuda.current_stream()
+
+    def step(timing):
+        V, s = lib.fit(X, k, cfg["kind"], cfg["omega_seed"], timing=timing, sparse_p=cfg.get("p", 64))
+        tf = lib.last_timings() if timing else None
+        Z = lib.transform(X, V, timing=timing)
+        tt = lib.last_timings() if timing else None
+        return V, s, Z, tf, tt
+
+    for i in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    phases = []
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        _, _, _, tf, tt = step(True)
+        phases.append((tf, tt))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f})")
+
+    def avg(key, which=0):
+        return sum(p[which][key] for p in phases) / len(phases)
+
+    fit_ms = avg("total_ms", 0)
+    tr_ms = avg("transform_ms", 1)
+    sketch_ms = avg("sketch_ms", 0)
+    factor_ms = avg("factor_ms", 0)
+    small_ms = avg("small_ms", 0)
+    value = 2 * xbytes / (ms_step * 1e-3) / 1e9
+
+    # dominant kernel: the sketch Y = X Omega (nt product, one launch per step)
+    flops_sketch = 2.0 * m * n * k
+    peak = PEAKS["fp64_mfma_TFs"] if cfg["dtype"] == "f64" else PEAKS["fp32_mfma_TFs"]
+    achieved = flops_sketch / (sketch_ms * 1e-3) / 1e12
+    out = {
+        "metric": "X-stream GB/s (% HBM/MFMA roofline) per Lazy SPCA fit vs SPCA; projection p99 ms",
+        "value": round(value, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32", "bf16": "bf16", "f16": "f16"}[cfg["dtype"]],
+        "data": "synthetic",
+        "config": {"workload": f"lazy-spca fit+projection, X {m}x{n} {cfg['dtype']} low-rank+noise, "
+                               f"{cfg['kind']} Omega, k={k}",
+                   "m": m, "n": n, "k": k, "x_bytes": xbytes, "parallelism": "single-gpu"},
+        "phases_ms": {"fit_total": round(fit_ms, 4), "omega": round(avg("omega_ms"), 4),
+                      "sketch": round(sketch_ms, 4), "factor_F_G": round(factor_ms, 4),
+                      "reduce": round(avg("reduce_ms"), 4), "small_fp64": round(small_ms, 4),
+                      "transform": round(tr_ms, 4)},
+        "fit_x_stream_GBs": round(xbytes / (fit_ms * 1e-3) / 1e9, 3),
+        "fit_pass_x_stream_GBs": round(xbytes / ((sketch_ms + factor_ms + avg('reduce_ms')) * 1e-3) / 1e9, 3),
+        "transform_x_stream_GBs": round(xbytes / (tr_ms * 1e-3) / 1e9, 3),
+        "roofline": {"kernel": "k_nt (sketch Y = X Omega)", "bound": "mfma",
+                     "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "algorithmic": f"2 m n k = {flops_sketch:.4g} flop per launch"},
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle on a row sample)")
+        out["cpu_baseline"] = cpu_baseline(cfg, X)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

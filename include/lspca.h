@@ -1,0 +1,210 @@
+/*
+ * lspca.h -- C ABI of the MI355X (gfx950) Lazy SPCA library, liblspca.so.
+ *
+ * Method: M. Wojnowicz, D. Nguyen, L. Li, X. Zhao, "Lazy stochastic principal
+ * component analysis", arXiv 1709.07175. Lazy SPCA (Algorithm 2; streaming
+ * form Algorithm 4) sketches the data X (m samples x n features) as
+ * U = X Omega (eq. (rp), c = 1), forms the k x n factor F = U^T X
+ * (eq. (simplified_approx_svd)) and returns the right singular vectors V of F:
+ * the dimensionality-reduction map pi(x) = V^T x (eq. (dim_reduction_maps)).
+ * SPCA (Algorithm 1) orthonormalises U by a QR first; both span the same
+ * subspace (Proposition 2) and give identical pairwise distances
+ * (Proposition 3). The library uses l = k (the paper's experiments do).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers named X, Omega, F, G, V, sigma, sigma_x and Z are DEVICE
+ *    pointers (HIP global memory) owned by the caller; the library never
+ *    frees caller memory. Host buffers are not accepted.
+ *  - Matrices are row-major. X has leading dimension ldx >= n (elements):
+ *    row i (one sample) starts at X + i*ldx. V is n x k, F is k x n, G is
+ *    k x k, Z is r x k, all dense (leading dimension = number of columns).
+ *  - Status: every call returns LSPCA_OK (0) or a negative lspca_status.
+ *    No C++ exception crosses the ABI. On an error no output is written
+ *    except where stated; lspca_last_error() gives a thread-local message.
+ *  - Work is queued on opts->stream (a hipStream_t; NULL = the null stream).
+ *    lspca_fit, spca_fit and lspca_factor return after the device work is
+ *    complete (their status depends on it). lspca_accumulate, lspca_omega
+ *    and lspca_transform only enqueue: outputs are ready when the stream is.
+ *  - The library keeps a per-device workspace (grown on demand, freed at
+ *    process exit). Calls that overlap on one device from several host
+ *    threads are serialised by a lock.
+ *  - X is never centred (Sec. I-B: the SPCA subspace does not need it).
+ */
+#ifndef LSPCA_H
+#define LSPCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(LSPCA_BUILDING)
+#define LSPCA_API __attribute__((visibility("default")))
+#else
+#define LSPCA_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage / compute type of X. F, G, V and sigma are always FP64. */
+typedef enum {
+  LSPCA_F64 = 0,  /* FP64 X, FP64 matrix-core products (v_mfma_f64) */
+  LSPCA_F32 = 1,  /* FP32 X, FP32 matrix-core products, FP32 accumulation */
+  LSPCA_BF16 = 2, /* BF16 X, BF16 products, FP32 accumulation */
+  LSPCA_F16 = 3   /* FP16 X, FP16 products, FP32 accumulation */
+} lspca_dtype;
+
+/* Random test matrix Omega (n x k) of eq. (rp); Sec. I-A lists both kinds. */
+typedef enum {
+  LSPCA_OMEGA_GAUSSIAN = 0,    /* Omega_ij iid N(0,1) */
+  LSPCA_OMEGA_VERY_SPARSE = 1  /* {-1,0,+1} w.p. {1/(2p), 1-1/p, 1/(2p)} */
+} lspca_omega_kind;
+
+typedef enum {
+  LSPCA_OK = 0,
+  LSPCA_EINVAL = -1,    /* bad argument (NULL pointer, size, ldx, kind, dtype) */
+  LSPCA_ENOMEM = -2,    /* device workspace could not be allocated */
+  LSPCA_EHIP = -3,      /* a HIP runtime call failed */
+  LSPCA_ERANK = -4,     /* the sketch or F is rank deficient (see below) */
+  LSPCA_E2BIG = -5,     /* request larger than a configured limit */
+  LSPCA_EAGAIN = -6,    /* server: no capacity right now; retry */
+  LSPCA_ENOTSUP = -7,   /* combination not supported */
+  LSPCA_ETIMEDOUT = -8, /* server: wait timed out */
+  LSPCA_ENOTFOUND = -9  /* server: unknown or already collected ticket */
+} lspca_status;
+
+/*
+ * Omega specification (seeded, counter based; the paper names no generator).
+ * Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) with
+ * key = (seed & 0xffffffff, seed >> 32).
+ *  Gaussian: one call with counter (q, j & 0xffffffff, j >> 32, 0x47415553)
+ *    gives words x0..x3; u1 = ((x1*2^32+x0) >> 11) * 2^-53 + 2^-54,
+ *    u2 = ((x3*2^32+x2) >> 11) * 2^-53, r = sqrt(-2 ln u1);
+ *    Omega[j][2q] = r cos(2 pi u2), Omega[j][2q+1] = r sin(2 pi u2) (FP64).
+ *  Very sparse (p a power of two, 1 <= p <= 2^30): one call with counter
+ *    (q, j & 0xffffffff, j >> 32, 0x53505253) gives Omega[j][4q+t] from word
+ *    x_t: +1 if x_t < 2^32/(2p), -1 if x_t < 2^32/p, else 0.
+ *  Type: Gaussian values are rounded FP64 -> FP32 for FP32 data, and
+ *    FP64 -> FP32 -> BF16/FP16 for 16-bit data (round to nearest even).
+ *  The very sparse kind is never materialised by the fit: each workgroup
+ *  regenerates the nonzeros it needs from the seed.
+ */
+
+typedef struct lspca_opts {
+  uint32_t struct_size; /* sizeof(lspca_opts); older/smaller structs accepted */
+  uint32_t sparse_p;    /* p of the very sparse kind; 0 means 64 */
+  int32_t refine;       /* 16-bit X only: -1 default (on), 0 off, 1 on. On:
+                           F = Y_hi^T X + Y_lo^T X with Y = Y_hi + Y_lo split
+                           into two 16-bit parts, X read once */
+  int32_t timing;       /* nonzero: record per-phase device times, read back
+                           with lspca_last_timings() */
+  void *stream;         /* hipStream_t; NULL = null stream */
+} lspca_opts;
+
+/* Per-phase device times (ms) of the last call on this thread that had
+ * opts->timing set; phases not run are 0. */
+typedef struct lspca_timings {
+  double omega_ms;      /* Omega generation (Gaussian kind) */
+  double sketch_ms;     /* Y = X Omega (Algorithm 2 step 1) */
+  double factor_ms;     /* F += Y^T X, G += Y^T Y (step 2) */
+  double reduce_ms;     /* FP64 reduction of partial F, G */
+  double small_ms;      /* small FP64 stage (truncated SVD of F; step 3) */
+  double qr_ms;         /* spca_fit: tall-skinny Householder QR of Y */
+  double pass2_ms;      /* spca_fit: F = Q^T X */
+  double transform_ms;  /* Z = X V */
+  double total_ms;      /* whole call */
+} lspca_timings;
+
+/* Version string, e.g. "lspca 0.1 gfx950". */
+LSPCA_API const char *lspca_version(void);
+/* Static text for a status code. */
+LSPCA_API const char *lspca_strerror(int status);
+/* Thread-local message describing the last failure on this thread. */
+LSPCA_API const char *lspca_last_error(void);
+/* Copies the timings of the last timed call on this thread. */
+LSPCA_API int lspca_last_timings(lspca_timings *out);
+
+/*
+ * lspca_omega -- materialise Omega (n x k, row-major) in the type `dtype`
+ * as the fit uses it (specification above; eq. (rp), Sec. I-A).
+ *  Omega: device buffer of n*k elements of `dtype` (FP64, FP32, BF16, FP16).
+ *  p: sparse p (power of two; 0 means 64); ignored for the Gaussian kind.
+ *  Errors: EINVAL (n < 1, k < 1, bad kind/dtype/p, Omega NULL).
+ */
+LSPCA_API int lspca_omega(int64_t n, int32_t k, lspca_omega_kind kind, uint64_t seed,
+                uint32_t p, lspca_dtype dtype, void *Omega, void *stream);
+
+/*
+ * lspca_accumulate -- one step of Algorithm 4 (Streaming Lazy SPCA) for the
+ * horizontal slice X (m x n): U_s = X Omega, F += U_s^T X and G += U_s^T U_s.
+ *  F: k x n FP64 (device), accumulated in place (caller zeroes it first).
+ *  G: k x k FP64 (device) or NULL to skip the Gram. G feeds sigma_x.
+ *  Products run in the type of X with FP32 accumulation (FP64 for F64);
+ *  the slice's partial sums are added into F and G in FP64 in a fixed order,
+ *  so results are deterministic for a given input and device.
+ *  Errors: EINVAL (m < 1, n < 1, k < 1, k > n, ldx < n, NULL X/F, bad kind),
+ *  ENOMEM, EHIP. Asynchronous on opts->stream.
+ */
+LSPCA_API int lspca_accumulate(const void *X, lspca_dtype xdt, int64_t m, int64_t n,
+                     int64_t ldx, int32_t k, lspca_omega_kind kind,
+                     uint64_t seed, const lspca_opts *opts, double *F,
+                     double *G);
+
+/*
+ * lspca_factor -- the final step of Algorithms 2 and 4: truncated SVD of the
+ * k x n factor F (FP64, on the device), F = U~ D V^T.
+ *  V: n x k FP64 right singular vectors, columns in decreasing order of D,
+ *     each column's largest-magnitude entry positive (lowest index on ties).
+ *  sigma: k FP64, D (singular values of F = U^T X).
+ *  sigma_x: k FP64 or NULL. When given (and G given), the approximate
+ *     singular values Sigma^s of X (eq. (approx_svd)), from the k x k route
+ *     R = chol(G), Q^T X = R^-T F (no tall QR).
+ *  Errors: EINVAL, ENOMEM, EHIP, ERANK if F is numerically rank deficient
+ *  (D_k <= 64 * n * eps * D_1) or, when sigma_x is requested, if chol(G)
+ *  fails (Lemma of the footnote to Corollary 1 assumes rank(U) = k).
+ *  Synchronous.
+ */
+LSPCA_API int lspca_factor(const double *F, const double *G, int32_t k, int64_t n,
+                 const lspca_opts *opts, double *V, double *sigma,
+                 double *sigma_x);
+
+/*
+ * lspca_fit -- Lazy SPCA (Algorithm 2), one pass over X resident on the
+ * device: lspca_accumulate over all of X, then lspca_factor.
+ * Arguments as above; 1 <= k <= min(m, n) (Corollary 1 requires
+ * l <= min{m, n}). Synchronous. Errors as lspca_accumulate/lspca_factor.
+ */
+LSPCA_API int lspca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n,
+              int64_t ldx, int32_t k, lspca_omega_kind kind, uint64_t seed,
+              const lspca_opts *opts, double *V, double *sigma,
+              double *sigma_x);
+
+/*
+ * spca_fit -- SPCA (Algorithm 1), the non-lazy baseline: Y = X Omega (pass 1,
+ * stored m x k), tall-skinny Householder QR Y = Q R with explicit thin Q,
+ * F = Q^T X (pass 2), truncated SVD of F.
+ *  V: n x k FP64 (V^s); sigma: k FP64 (Sigma^s). Same conventions as
+ *  lspca_fit. Synchronous. Errors: EINVAL, ENOMEM, EHIP, ERANK.
+ */
+LSPCA_API int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n,
+             int64_t ldx, int32_t k, lspca_omega_kind kind, uint64_t seed,
+             const lspca_opts *opts, double *V, double *sigma);
+
+/*
+ * lspca_transform -- Z = X V, the map pi(x) = V^T x of eq.
+ * (dim_reduction_maps) applied to each of the r rows of X.
+ *  V: n x k FP64 (device). Z: r x k, FP64 for F64 data, FP32 otherwise.
+ *  BF16/FP16 X use V split in two 16-bit parts (V = V_hi + V_lo, two
+ *  products into one FP32 accumulator); FP32 X uses V rounded to FP32.
+ *  Each output row depends only on its input row, with a fixed reduction
+ *  order, so a row's result does not depend on r or on the other rows.
+ *  r = 0 is allowed (no work). Errors: EINVAL, ENOMEM, EHIP. Asynchronous.
+ */
+LSPCA_API int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t n,
+                    int64_t ldx, const double *V, int32_t k, void *Z,
+                    const lspca_opts *opts);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSPCA_H */

@@ -1,0 +1,239 @@
+"""Python binding of liblspca.so (MI355X Lazy SPCA), by ctypes.
+
+The functions here only marshal arguments: device tensors are passed as raw
+pointers, the current torch stream as the HIP stream. Every computation runs
+in the library's HIP kernels. There is no fallback: if the library is not
+built, or no GPU is present, calls raise.
+
+Names mirror the C ABI of include/lspca.h: omega, accumulate, factor, fit,
+spca_fit, transform, plus the projection server.
+"""
+import ctypes
+import os
+
+__all__ = [
+    "load", "LspcaError", "F64", "F32", "BF16", "F16", "GAUSSIAN", "VERY_SPARSE",
+    "version", "omega", "accumulate", "factor", "fit", "spca_fit", "transform",
+    "last_timings", "exported_symbols", "LIB_PATH",
+]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblspca.so")
+
+F64, F32, BF16, F16 = 0, 1, 2, 3
+GAUSSIAN, VERY_SPARSE = 0, 1
+KIND = {"gaussian": GAUSSIAN, "sparse": VERY_SPARSE, GAUSSIAN: GAUSSIAN, VERY_SPARSE: VERY_SPARSE}
+
+STATUS = {0: "LSPCA_OK", -1: "LSPCA_EINVAL", -2: "LSPCA_ENOMEM", -3: "LSPCA_EHIP",
+          -4: "LSPCA_ERANK", -5: "LSPCA_E2BIG", -6: "LSPCA_EAGAIN", -7: "LSPCA_ENOTSUP",
+          -8: "LSPCA_ETIMEDOUT", -9: "LSPCA_ENOTFOUND"}
+
+# Every symbol include/lspca.h declares.
+EXPORTS = ["lspca_version", "lspca_strerror", "lspca_last_error", "lspca_last_timings",
+           "lspca_omega", "lspca_accumulate", "lspca_factor", "lspca_fit", "spca_fit",
+           "lspca_transform"]
+
+
+class LspcaError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class lspca_opts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("sparse_p", ctypes.c_uint32),
+                ("refine", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
+
+
+class lspca_timings(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("omega_ms", "sketch_ms", "factor_ms", "reduce_ms", "small_ms", "qr_ms",
+                 "pass2_ms", "transform_ms", "total_ms")]
+
+
+_lib = None
+_P, _I64, _I32, _U64, _U32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                              ctypes.c_uint64, ctypes.c_uint32)
+_SIGS = {
+    "lspca_version": ([], ctypes.c_char_p),
+    "lspca_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "lspca_last_error": ([], ctypes.c_char_p),
+    "lspca_last_timings": ([ctypes.POINTER(lspca_timings)], ctypes.c_int),
+    "lspca_omega": ([_I64, _I32, ctypes.c_int, _U64, _U32, ctypes.c_int, _P, _P], ctypes.c_int),
+    "lspca_accumulate": ([_P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
+                          ctypes.POINTER(lspca_opts), _P, _P], ctypes.c_int),
+    "lspca_factor": ([_P, _P, _I32, _I64, ctypes.POINTER(lspca_opts), _P, _P, _P], ctypes.c_int),
+    "lspca_fit": ([_P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
+                   ctypes.POINTER(lspca_opts), _P, _P, _P], ctypes.c_int),
+    "spca_fit": ([_P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
+                  ctypes.POINTER(lspca_opts), _P, _P], ctypes.c_int),
+    "lspca_transform": ([_P, ctypes.c_int, _I64, _I64, _I64, _P, _I32, _P,
+                         ctypes.POINTER(lspca_opts)], ctypes.c_int),
+}
+
+
+def load(path=LIB_PATH):
+    """Load the built library (no build is attempted here)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built: run __graft_entry__.build() or "
+                           "python paper_1709_07175_amd/build.py")
+    lib = ctypes.CDLL(path)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def exported_symbols(path=LIB_PATH):
+    lib = ctypes.CDLL(path)
+    return [n for n in EXPORTS if hasattr(lib, n)]
+
+
+def version():
+    return load().lspca_version().decode()
+
+
+def _check(status):
+    if status != 0:
+        msg = load().lspca_last_error().decode(errors="replace")
+        raise LspcaError(status, msg)
+
+
+# ------------------------------------------------------------ torch glue --
+def _torch():
+    import torch
+    return torch
+
+
+_DT = None
+
+
+def _dtype_code(t):
+    torch = _torch()
+    global _DT
+    if _DT is None:
+        _DT = {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}
+    if t.dtype not in _DT:
+        raise TypeError(f"unsupported dtype {t.dtype}")
+    return _DT[t.dtype]
+
+
+def _dev(t, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    return t
+
+
+def _rowmajor(X, name="X"):
+    _dev(X, name)
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError(f"{name} must be 2-D with unit column stride")
+    return X.stride(0)
+
+
+def _opts(stream=None, sparse_p=0, refine=-1, timing=False):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o = lspca_opts()
+    o.struct_size = ctypes.sizeof(lspca_opts)
+    o.sparse_p = sparse_p
+    o.refine = refine
+    o.timing = 1 if timing else 0
+    o.stream = ctypes.c_void_p(stream.cuda_stream)
+    return o
+
+
+def _f64_out(shape, device):
+    torch = _torch()
+    return torch.empty(shape, dtype=torch.float64, device=device)
+
+
+def omega(n, k, kind, seed, dtype, p=0, device="cuda"):
+    """Omega (n x k) as the fit uses it (lspca_omega)."""
+    torch = _torch()
+    tdt = {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}[dtype]
+    out = torch.empty((n, k), dtype=tdt, device=device)
+    _check(load().lspca_omega(n, k, KIND[kind], seed, p, dtype, out.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream))
+    return out
+
+
+def accumulate(X, k, kind, seed, F, G=None, **kw):
+    """Algorithm 4 step 2 for the slice X: F += U^T X, G += U^T U (in place)."""
+    ldx = _rowmajor(X)
+    o = _opts(**kw)
+    _check(load().lspca_accumulate(X.data_ptr(), _dtype_code(X), X.shape[0], X.shape[1], ldx, k,
+                                   KIND[kind], seed, ctypes.byref(o), _dev(F, "F").data_ptr(),
+                                   _dev(G, "G").data_ptr() if G is not None else None))
+    return F, G
+
+
+def factor(F, G=None, want_sigma_x=False, **kw):
+    """Truncated SVD of F (k x n): returns V (n x k), D (k) and, if asked,
+    Sigma^s (k) from G."""
+    k, n = F.shape
+    V = _f64_out((n, k), F.device)
+    s = _f64_out((k,), F.device)
+    sx = _f64_out((k,), F.device) if want_sigma_x else None
+    o = _opts(**kw)
+    _check(load().lspca_factor(_dev(F, "F").data_ptr(), G.data_ptr() if G is not None else None,
+                               k, n, ctypes.byref(o), V.data_ptr(), s.data_ptr(),
+                               sx.data_ptr() if sx is not None else None))
+    return (V, s, sx) if want_sigma_x else (V, s)
+
+
+def fit(X, k, kind="gaussian", seed=0, want_sigma_x=False, **kw):
+    """Lazy SPCA (Algorithm 2): returns V (n x k), D (k) [, Sigma^s (k)]."""
+    ldx = _rowmajor(X)
+    m, n = X.shape
+    V = _f64_out((n, k), X.device)
+    s = _f64_out((k,), X.device)
+    sx = _f64_out((k,), X.device) if want_sigma_x else None
+    o = _opts(**kw)
+    _check(load().lspca_fit(X.data_ptr(), _dtype_code(X), m, n, ldx, k, KIND[kind], seed,
+                            ctypes.byref(o), V.data_ptr(), s.data_ptr(),
+                            sx.data_ptr() if sx is not None else None))
+    return (V, s, sx) if want_sigma_x else (V, s)
+
+
+def spca_fit(X, k, kind="gaussian", seed=0, **kw):
+    """SPCA (Algorithm 1) with a tall-skinny Householder QR: V^s, Sigma^s."""
+    ldx = _rowmajor(X)
+    m, n = X.shape
+    V = _f64_out((n, k), X.device)
+    s = _f64_out((k,), X.device)
+    o = _opts(**kw)
+    _check(load().spca_fit(X.data_ptr(), _dtype_code(X), m, n, ldx, k, KIND[kind], seed,
+                           ctypes.byref(o), V.data_ptr(), s.data_ptr()))
+    return V, s
+
+
+def transform(X, V, Z=None, **kw):
+    """Z = X V (FP64 for FP64 X, FP32 otherwise)."""
+    torch = _torch()
+    ldx = _rowmajor(X)
+    r, n = X.shape
+    k = V.shape[1]
+    if V.dtype != torch.float64 or not V.is_contiguous():
+        raise ValueError("V must be a contiguous FP64 device tensor")
+    zdt = torch.float64 if X.dtype == torch.float64 else torch.float32
+    if Z is None:
+        Z = torch.empty((r, k), dtype=zdt, device=X.device)
+    o = _opts(**kw)
+    _check(load().lspca_transform(X.data_ptr(), _dtype_code(X), r, n, ldx, _dev(V, "V").data_ptr(),
+                                  k, Z.data_ptr(), ctypes.byref(o)))
+    return Z
+
+
+def last_timings():
+    t = lspca_timings()
+    _check(load().lspca_last_timings(ctypes.byref(t)))
+    return {n: getattr(t, n) for n, _ in lspca_timings._fields_}

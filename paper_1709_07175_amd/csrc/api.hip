@@ -1,0 +1,409 @@
+// C ABI entry points of liblspca.so (declared in include/lspca.h).
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+
+#include "common.h"
+
+namespace lspca {
+
+// ------------------------------------------------------------- errors ------
+static thread_local char g_err[1024] = "";
+static thread_local lspca_timings g_timings = {};
+
+void set_error(const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+const char *get_error() { return g_err; }
+
+size_t dtype_size(lspca_dtype dt) {
+  switch (dt) {
+    case LSPCA_F64: return 8;
+    case LSPCA_F32: return 4;
+    case LSPCA_BF16:
+    case LSPCA_F16: return 2;
+  }
+  return 0;
+}
+
+// ----------------------------------------------------------- workspace -----
+int Workspace::ensure(size_t bytes) {
+  used = 0;
+  if (bytes <= cap) return LSPCA_OK;
+  if (base) {
+    LSPCA_HIP(hipDeviceSynchronize());
+    LSPCA_HIP(hipFree(base));
+    base = nullptr;
+    cap = 0;
+  }
+  size_t want = bytes + bytes / 8 + (1 << 20);
+  if (hipMalloc(&base, want) != hipSuccess) {
+    (void)hipGetLastError();
+    base = nullptr;
+    set_error("workspace: hipMalloc of %zu bytes failed", want);
+    return LSPCA_ENOMEM;
+  }
+  cap = want;
+  return LSPCA_OK;
+}
+
+struct DeviceState {
+  std::mutex mu;
+  Workspace ws;
+};
+
+static DeviceState &device_state(int dev) {
+  static std::mutex g_mu;
+  static std::map<int, DeviceState *> g_states;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_states.find(dev);
+  if (it != g_states.end()) return *it->second;
+  DeviceState *st = new DeviceState();  // lives until process exit
+  st->ws.device = dev;
+  g_states[dev] = st;
+  return *st;
+}
+
+// ------------------------------------------------------------- timing -------
+void PhaseTimer::begin(bool enabled, hipStream_t s) {
+  on = enabled;
+  stream = s;
+  n = 0;
+  if (!on) return;
+  if (hipEventCreate(&ev[0]) != hipSuccess || hipEventRecord(ev[0], s) != hipSuccess) {
+    on = false;
+    return;
+  }
+  slot[0] = PH_START;
+  n = 1;
+}
+void PhaseTimer::mark(int phase) {
+  if (!on || n >= 24) return;
+  if (hipEventCreate(&ev[n]) != hipSuccess) return;
+  if (hipEventRecord(ev[n], stream) != hipSuccess) {
+    (void)hipEventDestroy(ev[n]);
+    return;
+  }
+  slot[n++] = phase;
+}
+int PhaseTimer::finish(lspca_timings *out) {
+  if (!on) return LSPCA_OK;
+  memset(out, 0, sizeof(*out));
+  LSPCA_HIP(hipEventSynchronize(ev[n - 1]));
+  double *fields[] = {&out->omega_ms, &out->sketch_ms, &out->factor_ms, &out->reduce_ms,
+                      &out->small_ms, &out->qr_ms, &out->pass2_ms, &out->transform_ms};
+  for (int i = 1; i < n; ++i) {
+    float ms = 0;
+    LSPCA_HIP(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
+    if (slot[i] >= 0 && slot[i] < 8) *fields[slot[i]] += ms;
+  }
+  float tot = 0;
+  LSPCA_HIP(hipEventElapsedTime(&tot, ev[0], ev[n - 1]));
+  out->total_ms = tot;
+  return LSPCA_OK;
+}
+PhaseTimer::~PhaseTimer() {
+  for (int i = 0; i < n; ++i) (void)hipEventDestroy(ev[i]);
+}
+
+// ------------------------------------------------------------ helpers ------
+struct Opts {
+  uint32_t p = 64;
+  int refine = -1;
+  int timing = 0;
+  hipStream_t stream = nullptr;
+};
+
+static int read_opts(const lspca_opts *o, Opts &out) {
+  out = Opts();
+  if (!o) return LSPCA_OK;
+  uint32_t sz = o->struct_size;
+  if (sz < offsetof(lspca_opts, sparse_p) + sizeof(uint32_t)) return LSPCA_OK;
+  if (o->sparse_p) out.p = o->sparse_p;
+  if (sz >= offsetof(lspca_opts, refine) + sizeof(int32_t)) out.refine = o->refine;
+  if (sz >= offsetof(lspca_opts, timing) + sizeof(int32_t)) out.timing = o->timing;
+  if (sz >= offsetof(lspca_opts, stream) + sizeof(void *)) out.stream = (hipStream_t)o->stream;
+  return LSPCA_OK;
+}
+
+static bool valid_p(uint32_t p) { return p >= 1 && p <= (1u << 30) && (p & (p - 1)) == 0; }
+static bool valid_dtype(int dt) { return dt >= LSPCA_F64 && dt <= LSPCA_F16; }
+static bool valid_kind(int kind) {
+  return kind == LSPCA_OMEGA_GAUSSIAN || kind == LSPCA_OMEGA_VERY_SPARSE;
+}
+
+static int check_pass_args(const void *X, int dt, int64_t m, int64_t n, int64_t ldx, int k,
+                           int kind, const Opts &o) {
+  if (!X) { set_error("X is NULL"); return LSPCA_EINVAL; }
+  if (!valid_dtype(dt)) { set_error("unknown dtype %d", dt); return LSPCA_EINVAL; }
+  if (m < 1 || n < 1) { set_error("m and n must be >= 1 (m=%lld n=%lld)", (long long)m, (long long)n); return LSPCA_EINVAL; }
+  if (n > (1 << 30)) { set_error("n too large"); return LSPCA_EINVAL; }
+  if (ldx < n) { set_error("ldx (%lld) < n (%lld)", (long long)ldx, (long long)n); return LSPCA_EINVAL; }
+  if (k < 1 || k > n) { set_error("k must satisfy 1 <= k <= n (k=%d n=%lld)", k, (long long)n); return LSPCA_EINVAL; }
+  if (k > 4096) { set_error("k > 4096 is not supported"); return LSPCA_ENOTSUP; }
+  if (!valid_kind(kind)) { set_error("unknown omega kind %d", kind); return LSPCA_EINVAL; }
+  if (kind == LSPCA_OMEGA_VERY_SPARSE && !valid_p(o.p)) { set_error("sparse p must be a power of two in [1, 2^30] (p=%u)", o.p); return LSPCA_EINVAL; }
+  return LSPCA_OK;
+}
+
+static int current_device(int *dev) {
+  LSPCA_HIP(hipGetDevice(dev));
+  return LSPCA_OK;
+}
+
+__global__ void k_zero_f64(double *p, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0.0;
+}
+static int zero_f64(double *p, int64_t count, hipStream_t s) {
+  if (count <= 0) return LSPCA_OK;
+  hipLaunchKernelGGL(k_zero_f64, (unsigned)((count + 255) / 256), 256, 0, s, p, count);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+// --------------------------------------------------------- the pass --------
+// Stripe plan for one pass: Y for a stripe of rows is kept in the workspace.
+struct PassPlan {
+  lspca_dtype cdt;      // compute type of the products
+  size_t esz;           // bytes per element of Y / partials
+  int64_t stripe;       // rows per stripe
+  int splits_f, splits_g;
+  size_t bytes;
+};
+
+static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool want_g) {
+  PassPlan p;
+  p.cdt = xdt;
+  p.esz = xdt == LSPCA_F64 ? 8 : 4;
+  const int64_t budget = (int64_t)2 << 30;              // Y stripe bytes
+  int64_t rows = budget / ((int64_t)k * p.esz);
+  rows = rows < 1024 ? 1024 : rows;
+  p.stripe = m < rows ? m : rows;
+  p.splits_f = tn_pick_splits(p.stripe, k, (int)n);
+  p.splits_g = want_g ? tn_pick_splits(p.stripe, k, k) : 0;
+  p.bytes = ws_bytes<char>(dtype_size(xdt) * (size_t)n * k)              // Omega^T
+            + ws_bytes<char>(p.esz * (size_t)p.stripe * k)                // Y stripe
+            + ws_bytes<char>(p.esz * tn_partial_elems(k, (int)n, p.splits_f))
+            + (want_g ? ws_bytes<char>(p.esz * tn_partial_elems(k, k, p.splits_g)) : 0);
+  return p;
+}
+
+// Algorithm 4 step 2 over all rows of X (stripe by stripe): F += Y^T X,
+// G += Y^T Y. Workspace must hold plan.bytes (already ensured).
+static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, int k,
+                    int kind, uint64_t seed, const Opts &o, double *F, double *G,
+                    const PassPlan &pl, Workspace &ws, PhaseTimer &tm) {
+  hipStream_t s = o.stream;
+  const size_t xs = dtype_size(xdt);
+  if (xdt == LSPCA_BF16 || xdt == LSPCA_F16) {
+    set_error("16-bit data: not built in this version");
+    return LSPCA_ENOTSUP;
+  }
+  if (kind == LSPCA_OMEGA_VERY_SPARSE && xdt != LSPCA_F64 && xdt != LSPCA_F32) {
+    set_error("sparse omega: dtype not supported");
+    return LSPCA_ENOTSUP;
+  }
+  void *OmT = ws.take<char>(xs * (size_t)n * k);
+  void *Y = ws.take<char>(pl.esz * (size_t)pl.stripe * k);
+  void *PF = ws.take<char>(pl.esz * tn_partial_elems(k, (int)n, pl.splits_f));
+  void *PG = G ? ws.take<char>(pl.esz * tn_partial_elems(k, k, pl.splits_g)) : nullptr;
+
+  // Omega^T (k x n) in the compute type: OmT[c][j] = Omega[j][c].
+  LSPCA_TRY(launch_omega(n, k, kind, seed, o.p, xdt, OmT, 1, n, s));
+  tm.mark(PH_OMEGA);
+  for (int64_t r0 = 0; r0 < m; r0 += pl.stripe) {
+    const int64_t rows = (m - r0) < pl.stripe ? (m - r0) : pl.stripe;
+    const char *Xs = (const char *)X + (size_t)r0 * ldx * xs;
+    // Y_s = X_s Omega (Algorithm 4 step 2a)
+    LSPCA_TRY(launch_nt(pl.cdt, Xs, ldx, OmT, n, Y, k, rows, k, (int)n, s));
+    tm.mark(PH_SKETCH);
+    // F += Y_s^T X_s (step 2b); G += Y_s^T Y_s
+    const int sf = tn_pick_splits(rows, k, (int)n);
+    LSPCA_TRY(launch_tn(pl.cdt, Y, k, Xs, ldx, PF, rows, k, (int)n, sf, s));
+    int sg = 0;
+    if (G) {
+      sg = tn_pick_splits(rows, k, k);
+      LSPCA_TRY(launch_tn(pl.cdt, Y, k, Y, k, PG, rows, k, k, sg, s));
+    }
+    tm.mark(PH_FACTOR);
+    LSPCA_TRY(launch_reduce_add(pl.cdt, PF, sf, (int64_t)k * n, F, 1, s));
+    if (G) LSPCA_TRY(launch_reduce_add(pl.cdt, PG, sg, (int64_t)k * k, G, 1, s));
+    tm.mark(PH_REDUCE);
+  }
+  return LSPCA_OK;
+}
+
+static size_t factor_bytes(int64_t n, int k) {
+  const int splits = tn_pick_splits(n, k, k);
+  const size_t kk = (size_t)k * k;
+  return 4 * ws_bytes<double>((size_t)n * k) + ws_bytes<double>(tn_partial_elems(k, k, splits)) +
+         6 * ws_bytes<double>(kk) + 2 * ws_bytes<double>(k) + ws_bytes<int>(4) +
+         ws_bytes<double>(4 * kk) +
+         ws_bytes<double>(3 * 128 * 128);
+}
+
+struct Locked {
+  DeviceState *st = nullptr;
+  std::unique_lock<std::mutex> lk;
+};
+static int lock_device(Locked &L) {
+  int dev = 0;
+  LSPCA_TRY(current_device(&dev));
+  L.st = &device_state(dev);
+  L.lk = std::unique_lock<std::mutex>(L.st->mu);
+  return LSPCA_OK;
+}
+
+}  // namespace lspca
+
+using namespace lspca;
+
+// ====================================================================== ABI ==
+extern "C" {
+
+const char *lspca_version(void) { return "lspca 0.1 gfx950"; }
+
+const char *lspca_strerror(int status) {
+  switch (status) {
+    case LSPCA_OK: return "ok";
+    case LSPCA_EINVAL: return "invalid argument";
+    case LSPCA_ENOMEM: return "out of device memory";
+    case LSPCA_EHIP: return "HIP runtime error";
+    case LSPCA_ERANK: return "rank deficient";
+    case LSPCA_E2BIG: return "request too large";
+    case LSPCA_EAGAIN: return "no capacity, retry";
+    case LSPCA_ENOTSUP: return "not supported";
+    case LSPCA_ETIMEDOUT: return "timed out";
+    case LSPCA_ENOTFOUND: return "unknown ticket";
+  }
+  return "unknown status";
+}
+
+const char *lspca_last_error(void) { return get_error(); }
+
+int lspca_last_timings(lspca_timings *out) {
+  if (!out) return LSPCA_EINVAL;
+  *out = g_timings;
+  return LSPCA_OK;
+}
+
+int lspca_omega(int64_t n, int32_t k, lspca_omega_kind kind, uint64_t seed, uint32_t p,
+                lspca_dtype dtype, void *Omega, void *stream) {
+  if (!Omega) { set_error("Omega is NULL"); return LSPCA_EINVAL; }
+  if (n < 1 || k < 1) { set_error("n and k must be >= 1"); return LSPCA_EINVAL; }
+  if (!valid_kind(kind)) { set_error("unknown omega kind %d", (int)kind); return LSPCA_EINVAL; }
+  if (!valid_dtype(dtype)) { set_error("unknown dtype %d", (int)dtype); return LSPCA_EINVAL; }
+  if (p == 0) p = 64;
+  if (kind == LSPCA_OMEGA_VERY_SPARSE && !valid_p(p)) { set_error("bad sparse p %u", p); return LSPCA_EINVAL; }
+  return launch_omega(n, k, kind, seed, p, dtype, Omega, k, 1, (hipStream_t)stream);
+}
+
+int lspca_accumulate(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx,
+                     int32_t k, lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts,
+                     double *F, double *G) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  LSPCA_TRY(check_pass_args(X, xdt, m, n, ldx, k, kind, o));
+  if (!F) { set_error("F is NULL"); return LSPCA_EINVAL; }
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  PassPlan pl = plan_pass(xdt, m, n, k, G != nullptr);
+  LSPCA_TRY(L.st->ws.ensure(pl.bytes));
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, o.stream);
+  LSPCA_TRY(run_pass(X, xdt, m, n, ldx, k, kind, seed, o, F, G, pl, L.st->ws, tm));
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int lspca_factor(const double *F, const double *G, int32_t k, int64_t n, const lspca_opts *opts,
+                 double *V, double *sigma, double *sigma_x) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  if (!F || !V || !sigma) { set_error("F, V and sigma must not be NULL"); return LSPCA_EINVAL; }
+  if (sigma_x && !G) { set_error("sigma_x needs G"); return LSPCA_EINVAL; }
+  if (n < 1 || k < 1 || k > n) { set_error("need 1 <= k <= n (k=%d n=%lld)", k, (long long)n); return LSPCA_EINVAL; }
+  if (k > 4096) { set_error("k > 4096 is not supported"); return LSPCA_ENOTSUP; }
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  LSPCA_TRY(L.st->ws.ensure(factor_bytes(n, k)));
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, o.stream);
+  int rank_flag = 0;
+  LSPCA_TRY(small_factor(F, G, k, n, V, sigma, sigma_x, L.st->ws, o.stream, &rank_flag));
+  tm.mark(PH_SMALL);
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int lspca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, int32_t k,
+              lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts, double *V,
+              double *sigma, double *sigma_x) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  LSPCA_TRY(check_pass_args(X, xdt, m, n, ldx, k, kind, o));
+  if (!V || !sigma) { set_error("V and sigma must not be NULL"); return LSPCA_EINVAL; }
+  if (k > m) { set_error("k must satisfy k <= min(m, n) (k=%d m=%lld)", k, (long long)m); return LSPCA_EINVAL; }
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  const bool want_g = sigma_x != nullptr;
+  PassPlan pl = plan_pass(xdt, m, n, k, want_g);
+  const size_t fg = ws_bytes<double>((size_t)k * n) + ws_bytes<double>((size_t)k * k);
+  const size_t fb = factor_bytes(n, k);
+  LSPCA_TRY(L.st->ws.ensure(fg + (pl.bytes > fb ? pl.bytes : fb)));
+  Workspace &ws = L.st->ws;
+  double *F = ws.take<double>((size_t)k * n);
+  double *G = ws.take<double>((size_t)k * k);
+  const size_t mark = ws.used;
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, o.stream);
+  LSPCA_TRY(zero_f64(F, (int64_t)k * n, o.stream));
+  LSPCA_TRY(zero_f64(G, (int64_t)k * k, o.stream));
+  LSPCA_TRY(run_pass(X, xdt, m, n, ldx, k, kind, seed, o, F, want_g ? G : nullptr, pl, ws, tm));
+  ws.used = mark;                                    // the pass's slots are free again
+  int rank_flag = 0;
+  LSPCA_TRY(small_factor(F, want_g ? G : nullptr, k, n, V, sigma, sigma_x, ws, o.stream, &rank_flag));
+  tm.mark(PH_SMALL);
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t n, int64_t ldx,
+                    const double *V, int32_t k, void *Z, const lspca_opts *opts) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  if (!valid_dtype(xdt)) { set_error("unknown dtype %d", (int)xdt); return LSPCA_EINVAL; }
+  if (r < 0 || n < 1 || k < 1 || ldx < n) { set_error("bad sizes (r=%lld n=%lld k=%d ldx=%lld)", (long long)r, (long long)n, k, (long long)ldx); return LSPCA_EINVAL; }
+  if (r == 0) return LSPCA_OK;
+  if (!X || !V || !Z) { set_error("X, V and Z must not be NULL"); return LSPCA_EINVAL; }
+  if (xdt == LSPCA_BF16 || xdt == LSPCA_F16) { set_error("16-bit data: not built in this version"); return LSPCA_ENOTSUP; }
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  const size_t es = dtype_size(xdt);
+  LSPCA_TRY(L.st->ws.ensure(ws_bytes<char>(es * (size_t)n * k)));
+  void *VT = L.st->ws.take<char>(es * (size_t)n * k);
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, o.stream);
+  LSPCA_TRY(launch_convert_vt(V, n, k, xdt, VT, nullptr, o.stream));
+  LSPCA_TRY(launch_nt(xdt, X, ldx, VT, n, Z, k, r, k, (int)n, o.stream));
+  tm.mark(PH_TRANSFORM);
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, int32_t k,
+             lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts, double *V,
+             double *sigma) {
+  (void)X; (void)xdt; (void)m; (void)n; (void)ldx; (void)k; (void)kind; (void)seed; (void)opts;
+  (void)V; (void)sigma;
+  set_error("spca_fit: not built in this version");
+  return LSPCA_ENOTSUP;
+}
+
+}  // extern "C"

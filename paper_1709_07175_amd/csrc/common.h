@@ -1,0 +1,134 @@
+// Internal declarations shared by the library's translation units.
+// Not part of the public ABI (that is include/lspca.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+
+#include "lspca.h"
+
+namespace lspca {
+
+// ------------------------------------------------------------ vector types --
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// 16-bit storage types are moved around as raw bits.
+struct bf16_t { uint16_t bits; };
+struct f16_t { uint16_t bits; };
+
+// ------------------------------------------------------ rounding helpers --
+// FP32 -> BF16, round to nearest even (finite inputs; NaN kept quiet).
+__host__ __device__ inline uint16_t f32_to_bf16_bits(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return (uint16_t)((u >> 16) | 0x40);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf16_bits_to_f32(uint16_t b) {
+  return __builtin_bit_cast(float, (uint32_t)b << 16);
+}
+__device__ inline uint16_t f32_to_f16_bits(float f) {
+  _Float16 h = (_Float16)f;  // v_cvt_f16_f32: round to nearest even
+  return __builtin_bit_cast(uint16_t, h);
+}
+__device__ inline float f16_bits_to_f32(uint16_t b) {
+  return (float)__builtin_bit_cast(_Float16, b);
+}
+
+// ------------------------------------------------------------- errors ------
+void set_error(const char *fmt, ...);
+const char *get_error();
+
+#define LSPCA_HIP(call)                                                      \
+  do {                                                                       \
+    hipError_t e_ = (call);                                                  \
+    if (e_ != hipSuccess) {                                                  \
+      ::lspca::set_error("%s failed: %s (%s:%d)", #call,                     \
+                         hipGetErrorString(e_), __FILE__, __LINE__);         \
+      return LSPCA_EHIP;                                                     \
+    }                                                                        \
+  } while (0)
+
+#define LSPCA_TRY(expr)                                                      \
+  do {                                                                       \
+    int s_ = (expr);                                                         \
+    if (s_ != LSPCA_OK) return s_;                                           \
+  } while (0)
+
+// ----------------------------------------------------------- workspace -----
+// A per-device grow-only arena. Callers hold the device lock (see api.hip)
+// while they use it. Slots are carved out of one allocation per call.
+struct Workspace {
+  char *base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  int device = -1;
+  int ensure(size_t bytes);          // grows (device sync + realloc) if needed
+  void reset() { used = 0; }
+  template <typename T> T *take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    T *p = (T *)(base + used);
+    used += bytes;
+    return p;
+  }
+};
+template <typename T> inline size_t ws_bytes(size_t count) {
+  return (count * sizeof(T) + 255) & ~(size_t)255;
+}
+
+// ------------------------------------------------------------- timing -------
+struct PhaseTimer {
+  bool on = false;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[24];
+  int slot[24];
+  int n = 0;
+  void begin(bool enabled, hipStream_t s);
+  void mark(int phase);              // records an event ending `phase`
+  int finish(lspca_timings *out);    // syncs, fills times, destroys events
+  ~PhaseTimer();
+};
+enum Phase { PH_START = -1, PH_OMEGA = 0, PH_SKETCH, PH_FACTOR, PH_REDUCE, PH_SMALL,
+             PH_QR, PH_PASS2, PH_TRANSFORM };
+
+// ---------------------------------------------------------- launchers ------
+// Omega generation (omega.hip). out has the layout out[j*ld_j + c*ld_c].
+int launch_omega(int64_t n, int k, int kind, uint64_t seed, uint32_t p,
+                 lspca_dtype dt, void *out, int64_t ld_j, int64_t ld_c,
+                 hipStream_t s);
+
+// Dense products (gemm.hip). All matrices row-major.
+//  nt: C[M x N] = A[M x K] * B[N x K]^T   (A, B: K contiguous)
+//  tn: P[s][M x N] = sum_{r in chunk s} A[r][i] * B[r][j]  (split over r)
+//  Epilogue: C = alpha * product + beta * C (tn: beta and ldp need splits 1).
+int launch_nt(lspca_dtype dt, const void *A, int64_t lda, const void *B,
+              int64_t ldb, void *C, int64_t ldc, int64_t M, int N, int K,
+              hipStream_t s, double alpha = 1.0, double beta = 0.0);
+int launch_tn(lspca_dtype dt, const void *A, int64_t lda, const void *B,
+              int64_t ldb, void *P, int64_t M_rows, int Mi, int Nj, int splits,
+              hipStream_t s, int64_t ldp = 0, double alpha = 1.0, double beta = 0.0);
+int tn_pick_splits(int64_t rows, int Mi, int Nj);
+size_t tn_partial_elems(int Mi, int Nj, int splits);
+
+// Reductions and small FP64 stage (small.hip).
+int launch_reduce_add(lspca_dtype pdt, const void *P, int splits, int64_t count,
+                      double *out, int accumulate, hipStream_t s);
+int small_factor(const double *F, const double *G, int k, int64_t n,
+                 double *V, double *sigma, double *sigma_x, Workspace &ws,
+                 hipStream_t s, int *rank_flag);
+int launch_transpose_f64(const double *src, int64_t rows, int cols,
+                         double *dst, hipStream_t s);
+int launch_convert_vt(const double *V, int64_t n, int k, lspca_dtype dt,
+                      void *hi, void *lo, hipStream_t s);
+
+size_t dtype_size(lspca_dtype dt);
+
+}  // namespace lspca

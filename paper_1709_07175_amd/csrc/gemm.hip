@@ -1,0 +1,383 @@
+// Dense matrix-core products for FP32 and FP64 data on gfx950.
+//
+//  k_nt: C[M x N] = A[M x K] * B[N x K]^T, both operands K-contiguous.
+//        Used for the sketch Y = X Omega (B = Omega^T, Algorithm 2 step 1),
+//        the projection Z = X V (eq. (dim_reduction_maps)) and the n x k by
+//        k x k products of the small stage.
+//  k_tn: P[s][M x N] = sum over rows r of chunk s of A[r][i] * B[r][j],
+//        a split over the long row dimension with one partial per split.
+//        Used for F = Y^T X and G = Y^T Y (Algorithm 2 step 2 / Algorithm 4
+//        step 2a-2b: each split is a horizontal slice X_s), and for Gram
+//        matrices in the small stage.
+//
+// Both stage K-tiles of A and B through LDS (double buffered, one barrier
+// per tile) and run v_mfma_f32_32x32x2f32 (FP32) or v_mfma_f64_16x16x4f64
+// (FP64) on fragments read from LDS. 256 threads = 4 waves of 64 lanes.
+#include "common.h"
+
+namespace lspca {
+
+template <typename T> struct Mfma;
+
+// v_mfma_f32_32x32x2f32: lane l holds A[l%32][l/32] and B[l/32][l%32];
+// result element v of lane l is D[8*(v/4) + 4*(l/32) + v%4][l%32].
+template <> struct Mfma<float> {
+  static constexpr int MB = 32, KB = 2, NV = 16;
+  typedef f32x16 acc_t;
+  __device__ static inline acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) {
+    return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+  }
+};
+
+// v_mfma_f64_16x16x4f64: lane l holds A[l%16][l/16] and B[l/16][l%16];
+// result element v of lane l is D[l/16 + 4*v][l%16] (checked on gfx950).
+template <> struct Mfma<double> {
+  static constexpr int MB = 16, KB = 4, NV = 4;
+  typedef f64x4 acc_t;
+  __device__ static inline acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { typedef f32x4 type; static constexpr int W = 4; };
+template <> struct Vec16<double> { typedef f64x2 type; static constexpr int W = 2; };
+
+// --------------------------------------------------------------------- NT --
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, bool VEC>
+__global__ __launch_bounds__(256) void k_nt(const T *__restrict__ A, int64_t lda,
+                                            const T *__restrict__ B, int64_t ldb,
+                                            T *__restrict__ C, int64_t ldc,
+                                            int64_t M, int N, int K, T alpha, T beta) {
+  typedef Mfma<T> MF;
+  constexpr int MB = MF::MB, KB = MF::KB;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / MB, TN = WN / MB;
+  constexpr int LD = BK + 1;                           // padded row of a tile
+  constexpr int VW = VEC ? Vec16<T>::W : 1;
+  constexpr int AV = BM * BK / VW / 256, BV = BN * BK / VW / 256;
+  static_assert(WGM * WGN == 4, "4 waves");
+  static_assert(AV * VW * 256 == BM * BK && BV * VW * 256 == BN * BK, "tile/threads");
+
+  __shared__ T As[2][BM * LD];
+  __shared__ T Bs[2][BN * LD];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const int n0 = blockIdx.y * BN;
+
+  T ra[AV * VW], rb[BV * VW];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      int idx = tid + v * 256;
+      int r = idx / (BK / VW), kc = (idx % (BK / VW)) * VW;
+      int64_t gr = m0 + r;
+      if constexpr (VEC) {
+        typename Vec16<T>::type x = {};
+        if (gr < M && k0 + kc < K) x = *(const typename Vec16<T>::type *)(A + gr * lda + k0 + kc);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) ra[v * VW + e] = x[e];
+      } else {
+        ra[v] = (gr < M && k0 + kc < K) ? A[gr * lda + k0 + kc] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      int idx = tid + v * 256;
+      int r = idx / (BK / VW), kc = (idx % (BK / VW)) * VW;
+      int gn = n0 + r;
+      if constexpr (VEC) {
+        typename Vec16<T>::type x = {};
+        if (gn < N && k0 + kc < K) x = *(const typename Vec16<T>::type *)(B + (int64_t)gn * ldb + k0 + kc);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) rb[v * VW + e] = x[e];
+      } else {
+        rb[v] = (gn < N && k0 + kc < K) ? B[(int64_t)gn * ldb + k0 + kc] : (T)0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      int idx = tid + v * 256;
+      int r = idx / (BK / VW), kc = (idx % (BK / VW)) * VW;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) As[buf][r * LD + kc + e] = ra[v * VW + e];
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      int idx = tid + v * 256;
+      int r = idx / (BK / VW), kc = (idx % (BK / VW)) * VW;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) Bs[buf][r * LD + kc + e] = rb[v * VW + e];
+    }
+  };
+
+  typename MF::acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = {};
+
+  const int nk = (K + BK - 1) / BK;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load((kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += KB) {
+      T a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[cur][(wm0 + i * MB + lane % MB) * LD + kk + lane / MB];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = Bs[cur][(wn0 + j * MB + lane % MB) * LD + kk + lane / MB];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
+    }
+    if (kt + 1 < nk) store(cur ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < MF::NV; ++v) {
+        int64_t r = m0 + wm0 + i * MB + MF::row(lane, v);
+        int c = n0 + wn0 + j * MB + lane % MB;
+        if (r < M && c < N) {
+          T val = alpha * acc[i][j][v];
+          if (beta != (T)0) val += beta * C[r * ldc + c];
+          C[r * ldc + c] = val;
+        }
+      }
+}
+
+// --------------------------------------------------------------------- TN --
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, bool VEC>
+__global__ __launch_bounds__(256) void k_tn(const T *__restrict__ A, int64_t lda,
+                                            const T *__restrict__ B, int64_t ldb,
+                                            T *__restrict__ P, int64_t ldp, int64_t rows,
+                                            int Mi, int Nj, int64_t chunk, T alpha, T beta) {
+  typedef Mfma<T> MF;
+  constexpr int MB = MF::MB, KB = MF::KB;
+  constexpr int WM = BM / WGM, WN = BN / WGN;
+  constexpr int TM = WM / MB, TN = WN / MB;
+  constexpr int VW = VEC ? Vec16<T>::W : 1;
+  constexpr int AV = BM * BK / VW / 256, BV = BN * BK / VW / 256;
+  static_assert(WGM * WGN == 4, "4 waves");
+  static_assert(AV * VW * 256 == BM * BK && BV * VW * 256 == BN * BK, "tile/threads");
+
+  __shared__ T As[2][BK * BM];
+  __shared__ T Bs[2][BK * BN];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
+  const int j0 = blockIdx.x * BN, i0 = blockIdx.y * BM;
+  const int64_t rbeg = (int64_t)blockIdx.z * chunk;
+  const int64_t rend = rbeg + chunk < rows ? rbeg + chunk : rows;
+
+  T ra[AV * VW], rb[BV * VW];
+  auto load = [&](int64_t r0) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      int idx = tid + v * 256;
+      int kr = idx / (BM / VW), c = (idx % (BM / VW)) * VW;
+      int64_t gr = r0 + kr;
+      if constexpr (VEC) {
+        typename Vec16<T>::type x = {};
+        if (gr < rend && i0 + c < Mi) x = *(const typename Vec16<T>::type *)(A + gr * lda + i0 + c);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) ra[v * VW + e] = x[e];
+      } else {
+        ra[v] = (gr < rend && i0 + c < Mi) ? A[gr * lda + i0 + c] : (T)0;
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      int idx = tid + v * 256;
+      int kr = idx / (BN / VW), c = (idx % (BN / VW)) * VW;
+      int64_t gr = r0 + kr;
+      if constexpr (VEC) {
+        typename Vec16<T>::type x = {};
+        if (gr < rend && j0 + c < Nj) x = *(const typename Vec16<T>::type *)(B + gr * ldb + j0 + c);
+#pragma unroll
+        for (int e = 0; e < VW; ++e) rb[v * VW + e] = x[e];
+      } else {
+        rb[v] = (gr < rend && j0 + c < Nj) ? B[gr * ldb + j0 + c] : (T)0;
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      int idx = tid + v * 256;
+      int kr = idx / (BM / VW), c = (idx % (BM / VW)) * VW;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) As[buf][kr * BM + c + e] = ra[v * VW + e];
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      int idx = tid + v * 256;
+      int kr = idx / (BN / VW), c = (idx % (BN / VW)) * VW;
+#pragma unroll
+      for (int e = 0; e < VW; ++e) Bs[buf][kr * BN + c + e] = rb[v * VW + e];
+    }
+  };
+
+  typename MF::acc_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = {};
+
+  const int64_t nt = rend > rbeg ? (rend - rbeg + BK - 1) / BK : 0;
+  if (nt > 0) {
+    load(rbeg);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t t = 0; t < nt; ++t) {
+    const int cur = (int)(t & 1);
+    if (t + 1 < nt) load(rbeg + (t + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += KB) {
+      T a[TM], b[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) a[i] = As[cur][(kk + lane / MB) * BM + wm0 + i * MB + lane % MB];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) b[j] = Bs[cur][(kk + lane / MB) * BN + wn0 + j * MB + lane % MB];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
+    }
+    if (t + 1 < nt) store(cur ^ 1);
+    __syncthreads();
+  }
+
+  T *Pz = P + (int64_t)blockIdx.z * Mi * ldp;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < MF::NV; ++v) {
+        int r = i0 + wm0 + i * MB + MF::row(lane, v);
+        int c = j0 + wn0 + j * MB + lane % MB;
+        if (r < Mi && c < Nj) {
+          T val = alpha * acc[i][j][v];
+          if (beta != (T)0) val += beta * Pz[(int64_t)r * ldp + c];
+          Pz[(int64_t)r * ldp + c] = val;
+        }
+      }
+}
+
+// ---------------------------------------------------------------- launch --
+template <typename T> static bool vec_ok(const void *p, int64_t ld, int64_t extent) {
+  constexpr int W = Vec16<T>::W;
+  return ((uintptr_t)p % 16 == 0) && (ld % W == 0) && (extent % W == 0);
+}
+
+template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+static int nt_typed(const T *A, int64_t lda, const T *B, int64_t ldb, T *C, int64_t ldc,
+                    int64_t M, int N, int K, T alpha, T beta, hipStream_t s) {
+  dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN));
+  if (grid.x == 0 || grid.y == 0) return LSPCA_OK;
+  if ((M + BM - 1) / BM > 0x7fffffff) {
+    set_error("nt product: too many row tiles");
+    return LSPCA_EINVAL;
+  }
+  if (vec_ok<T>(A, lda, K) && vec_ok<T>(B, ldb, K))
+    hipLaunchKernelGGL((k_nt<T, BM, BN, BK, WGM, WGN, true>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, alpha, beta);
+  else
+    hipLaunchKernelGGL((k_nt<T, BM, BN, BK, WGM, WGN, false>), grid, dim3(256), 0, s, A, lda, B, ldb, C, ldc, M, N, K, alpha, beta);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+int launch_nt(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb,
+              void *C, int64_t ldc, int64_t M, int N, int K, hipStream_t s, double alpha,
+              double beta) {
+  if (M <= 0 || N <= 0) return LSPCA_OK;
+  switch (dt) {
+    case LSPCA_F32:
+      return nt_typed<float, 128, 128, 16, 2, 2>((const float *)A, lda, (const float *)B, ldb,
+                                                 (float *)C, ldc, M, N, K, (float)alpha,
+                                                 (float)beta, s);
+    case LSPCA_F64:
+      return nt_typed<double, 64, 64, 16, 2, 2>((const double *)A, lda, (const double *)B, ldb,
+                                                (double *)C, ldc, M, N, K, alpha, beta, s);
+    default:
+      set_error("nt product: dtype %d not handled here", (int)dt);
+      return LSPCA_ENOTSUP;
+  }
+}
+
+// Split count: enough blocks to fill 256 CUs several times over, at least
+// 128 rows per split.
+int tn_pick_splits(int64_t rows, int Mi, int Nj) {
+  const int BM = 128, BN = 128;
+  int64_t tiles = (int64_t)((Mi + BM - 1) / BM) * ((Nj + BN - 1) / BN);
+  int64_t want = (2048 + tiles - 1) / tiles;
+  int64_t maxs = (rows + 127) / 128;
+  int64_t s = want < maxs ? want : maxs;
+  if (s < 1) s = 1;
+  if (s > 4096) s = 4096;
+  return (int)s;
+}
+
+size_t tn_partial_elems(int Mi, int Nj, int splits) {
+  return (size_t)Mi * Nj * splits;
+}
+
+template <typename T, int BM, int BN, int BK, int WGM, int WGN>
+static int tn_typed(const T *A, int64_t lda, const T *B, int64_t ldb, T *P, int64_t ldp,
+                    int64_t rows, int Mi, int Nj, int splits, T alpha, T beta, hipStream_t s) {
+  int64_t chunk = (rows + splits - 1) / splits;
+  chunk = (chunk + BK - 1) / BK * BK;
+  dim3 grid((unsigned)((Nj + BN - 1) / BN), (unsigned)((Mi + BM - 1) / BM), (unsigned)splits);
+  if (vec_ok<T>(A, lda, Mi) && vec_ok<T>(B, ldb, Nj))
+    hipLaunchKernelGGL((k_tn<T, BM, BN, BK, WGM, WGN, true>), grid, dim3(256), 0, s, A, lda, B, ldb, P, ldp, rows, Mi, Nj, chunk, alpha, beta);
+  else
+    hipLaunchKernelGGL((k_tn<T, BM, BN, BK, WGM, WGN, false>), grid, dim3(256), 0, s, A, lda, B, ldb, P, ldp, rows, Mi, Nj, chunk, alpha, beta);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+int launch_tn(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb,
+              void *P, int64_t rows, int Mi, int Nj, int splits, hipStream_t s, int64_t ldp,
+              double alpha, double beta) {
+  if (Mi <= 0 || Nj <= 0 || splits <= 0) return LSPCA_OK;
+  if (ldp <= 0) ldp = Nj;
+  if (splits > 1 && (ldp != Nj || beta != 0.0)) {
+    set_error("tn product: ldp/beta need splits == 1");
+    return LSPCA_EINVAL;
+  }
+  switch (dt) {
+    case LSPCA_F32:
+      return tn_typed<float, 128, 128, 16, 2, 2>((const float *)A, lda, (const float *)B, ldb,
+                                                 (float *)P, ldp, rows, Mi, Nj, splits,
+                                                 (float)alpha, (float)beta, s);
+    case LSPCA_F64:
+      return tn_typed<double, 64, 64, 16, 2, 2>((const double *)A, lda, (const double *)B, ldb,
+                                                (double *)P, ldp, rows, Mi, Nj, splits, alpha,
+                                                beta, s);
+    default:
+      set_error("tn product: dtype %d not handled here", (int)dt);
+      return LSPCA_ENOTSUP;
+  }
+}
+
+}  // namespace lspca

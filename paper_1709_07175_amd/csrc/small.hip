@@ -1,0 +1,748 @@
+// Small FP64 stage: the truncated SVD of the k x n factor F (final step of
+// Algorithms 2 and 4), plus the k x k route to Sigma^s, all on the GPU.
+//
+// Route (own design; the paper only asks for a truncated SVD of F, or its
+// eigensolution route via F F^T in the note of the algorithm table):
+//   1. F^T = Q R by Cholesky QR on the n x k matrix F^T, repeated until Q is
+//      orthonormal to working precision (two passes; a shifted first pass is
+//      added when the first Cholesky factorisation fails).
+//   2. One-sided (Hestenes) Jacobi on the k x k factor R: R W = U_R Sigma.
+//      Then F = R^T Q^T = W Sigma (Q U_R)^T, so V = Q U_R and D = Sigma.
+//      The subspace span(V) = span(Q) = span(F^T) is fixed by step 1 alone,
+//      and the rotations of step 2 keep V orthonormal to rounding.
+//   3. sigma_x: with G = R_G^T R_G (Cholesky), R_G^-T F = (R R_G^-1)^T Q^T,
+//      so Sigma^s are the singular values of the k x k matrix R R_G^-1 (the
+//      Q^T X of eq. (approx_svd) without a tall QR).
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+namespace lspca {
+
+// 16-lane all-reduce of a double with DPP moves inside one row of a wave:
+// quad_perm xor 1, quad_perm xor 2, row_half_mirror, row_mirror.
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+template <int CTRL> __device__ inline double dpp_move(double v) {
+  i32x2 p = __builtin_bit_cast(i32x2, v);
+  p.x = __builtin_amdgcn_update_dpp(0, p.x, CTRL, 0xF, 0xF, false);
+  p.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, p);
+}
+__device__ inline double sum16(double v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x141>(v);
+  v += dpp_move<0x140>(v);
+  return v;
+}
+
+// 8-lane all-reduce inside a DPP row (quad xor 1, quad xor 2, half mirror).
+__device__ inline double sum8(double v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x141>(v);
+  return v;
+}
+
+
+// ----------------------------------------------------------- reductions ----
+template <typename PT>
+__global__ void k_reduce_add(const PT *__restrict__ P, int splits, int64_t count,
+                             double *__restrict__ out, int accumulate) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  double s = accumulate ? out[e] : 0.0;
+  double part = 0.0;
+  for (int z = 0; z < splits; ++z) part += (double)P[(int64_t)z * count + e];
+  out[e] = s + part;
+}
+
+int launch_reduce_add(lspca_dtype pdt, const void *P, int splits, int64_t count, double *out,
+                      int accumulate, hipStream_t s) {
+  if (count <= 0) return LSPCA_OK;
+  const unsigned grid = (unsigned)((count + 255) / 256);
+  if (pdt == LSPCA_F64)
+    hipLaunchKernelGGL(k_reduce_add<double>, grid, 256, 0, s, (const double *)P, splits, count, out, accumulate);
+  else
+    hipLaunchKernelGGL(k_reduce_add<float>, grid, 256, 0, s, (const float *)P, splits, count, out, accumulate);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+__global__ void k_transpose_f64(const double *__restrict__ src, int64_t rows, int cols,
+                                double *__restrict__ dst) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32;
+  const int c0 = blockIdx.x * 32;
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    int64_t r = r0 + i;
+    int c = c0 + threadIdx.x;
+    if (r < rows && c < cols) tile[i][threadIdx.x] = src[r * cols + c];
+  }
+  __syncthreads();
+  for (int i = threadIdx.y; i < 32; i += 8) {
+    int c = c0 + i;
+    int64_t r = r0 + threadIdx.x;
+    if (r < rows && c < cols) dst[(int64_t)c * rows + r] = tile[threadIdx.x][i];
+  }
+}
+
+int launch_transpose_f64(const double *src, int64_t rows, int cols, double *dst, hipStream_t s) {
+  dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32));
+  hipLaunchKernelGGL(k_transpose_f64, grid, dim3(32, 8), 0, s, src, rows, cols, dst);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+// ------------------------------------------------------- k x k kernels -----
+// Add shift * I to the k x k matrix M, where shift = c * trace(M).
+__global__ void k_shift_diag(double *M, int k, double c) {
+  __shared__ double tr;
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int i = 0; i < k; ++i) t += M[(int64_t)i * k + i];
+    tr = t;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += blockDim.x) M[(int64_t)i * k + i] += c * tr;
+}
+
+// In-place Cholesky M = R^T R of a symmetric n x n block (leading
+// dimension ld, n <= 128) held in LDS (padded stride n + 1); R is left in
+// the upper triangle, the block's lower triangle is zeroed. Right-looking:
+// pivot, scale row j, rank-1 update of the trailing upper triangle.
+// fail[0] is set when a pivot is not positive and finite.
+__global__ __launch_bounds__(1024) void k_chol_lds(double *Mg, int n, int64_t ld, int *fail) {
+  __shared__ double M[128 * 129];
+  __shared__ double dj;
+  __shared__ int bad;
+  const int tid = threadIdx.x, nt = blockDim.x, s = n + 1;
+  const int tx = tid & 31, ty = tid >> 5;
+  for (int e = tid; e < n * n; e += nt) M[(e / n) * s + e % n] = Mg[(int64_t)(e / n) * ld + e % n];
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      double d = M[j * s + j];
+      if (!(d > 0.0) || !isfinite(d)) {
+        bad = 1;
+        d = 1.0;
+      }
+      dj = sqrt(d);
+      M[j * s + j] = dj;
+    }
+    __syncthreads();
+    if (bad) break;
+    const double inv = 1.0 / dj;
+    for (int c = j + 1 + tid; c < n; c += nt) M[j * s + c] *= inv;
+    __syncthreads();
+    for (int a = j + 1 + ty; a < n; a += 32) {
+      const double ra = M[j * s + a];
+      for (int b = a + tx; b < n; b += 32) M[a * s + b] -= ra * M[j * s + b];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += nt) {
+    const int a = e / n, b = e % n;
+    Mg[(int64_t)a * ld + b] = b < a ? 0.0 : M[a * s + b];
+  }
+  if (tid == 0 && bad) fail[0] = 1;
+}
+
+// Inverse X = R^-1 of an upper triangular n x n block (n <= 128) in LDS,
+// column by column: X[j][j] = 1/R[j][j] and, for i < j,
+// X[i][j] = -(sum_{p=i}^{j-1} X[i][p] R[p][j]) / R[j][j], 8 lanes per
+// row i. Writes XT[c][i] = X[i][c] (ld ldxt) and, if X != NULL, X itself
+// (ld ldx).
+__global__ __launch_bounds__(1024) void k_trinv_lds(const double *R, int n, int64_t ldr, double *XT,
+                                                    int64_t ldxt, double *X, int64_t ldx) {
+  __shared__ double A[128 * 129];
+  const int tid = threadIdx.x, nt = blockDim.x, s = n + 1;
+  const int i = tid >> 3, sub = tid & 7;
+  for (int e = tid; e < n * n; e += nt) {
+    const int a = e / n, b = e % n;
+    A[a * s + b] = b < a ? 0.0 : R[(int64_t)a * ldr + b];
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double d = 1.0 / A[j * s + j];
+    double t = 0.0;
+    if (i < j)
+      for (int p = i + sub; p < j; p += 8) t += A[i * s + p] * A[p * s + j];
+    t = sum8(t);
+    __syncthreads();
+    if (i < j && sub == 0) A[i * s + j] = -t * d;
+    if (tid == 0) A[j * s + j] = d;
+    __syncthreads();
+  }
+  for (int e = tid; e < n * n; e += nt) {
+    const int a = e / n, b = e % n;
+    XT[(int64_t)b * ldxt + a] = A[a * s + b];
+    if (X) X[(int64_t)a * ldx + b] = A[a * s + b];
+  }
+}
+
+__global__ void k_zero_lower(double *M, int k) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)k * k) return;
+  if (e % k < e / k) M[e] = 0.0;
+}
+
+// Copy the k x k row-major matrix A into column storage Wc[c][i] = A[i][c].
+__global__ void k_to_cols(const double *__restrict__ A, int k, double *__restrict__ Wc) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)k * k) return;
+  const int i = (int)(e / k), c = (int)(e % k);
+  Wc[(int64_t)c * k + i] = A[e];
+}
+
+
+
+// ------------------------------------------------ one-sided Jacobi ------
+// Columns live in LDS with a padded stride (len + 1 doubles) so that the
+// groups of one wave, each reading a different column, hit different banks.
+constexpr int kLdsDoubles = 16384;   // problem size limit: k*k or 2b*k doubles
+constexpr int kLdsAlloc = 16640;     // allocation incl. padding (130 KB)
+
+// Orthogonalise columns ap and aq (length len <= 16 * ROWS, in LDS) with
+// the 16 lanes of one DPP row (gl = lane within the row). The rotation is
+// skipped when |a_p.a_q| <= tol |a_p| |a_q|; otherwise Rutishauser's
+// formulas give c, s with (c a_p - s a_q).(s a_p + c a_q) = 0.
+template <int ROWS>
+__device__ inline bool rotate_pair(double *ap, double *aq, int len, int gl, double tol) {
+  double x[ROWS], y[ROWS];
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    const int r = gl + 16 * i;
+    x[i] = r < len ? ap[r] : 0.0;
+    y[i] = r < len ? aq[r] : 0.0;
+  }
+  double al = 0, be = 0, ga = 0;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    al += x[i] * x[i];
+    be += y[i] * y[i];
+    ga += x[i] * y[i];
+  }
+  al = sum16(al);
+  be = sum16(be);
+  ga = sum16(ga);
+  // |ga| > tol sqrt(al be), squared (al, be >= 0)
+  if (!(ga != 0.0 && ga * ga > (tol * tol) * (al * be))) return false;
+  // Rutishauser's t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
+  // zeta = (be - al) / (2 ga), multiplied through by 2|ga|:
+  // t = 2 ga sgn(be - al) / (|be - al| + sqrt((be - al)^2 + 4 ga^2)).
+  const double d = be - al;
+  const double t = (d >= 0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
+  const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    const int r = gl + 16 * i;
+    if (r < len) {
+      ap[r] = c * x[i] - sn * y[i];
+      aq[r] = sn * x[i] + c * y[i];
+    }
+  }
+  return true;
+}
+
+__device__ inline bool rotate_any(double *ap, double *aq, int len, int gl, double tol) {
+  if (len <= 32) return rotate_pair<2>(ap, aq, len, gl, tol);
+  if (len <= 64) return rotate_pair<4>(ap, aq, len, gl, tol);
+  if (len <= 128) return rotate_pair<8>(ap, aq, len, gl, tol);
+  return rotate_pair<16>(ap, aq, len, gl, tol);
+}
+
+// Round-robin pair (i-th of round s) over nc' = even(nc) columns:
+// column L = nc'-1 meets s, (s+i) mod L meets (s-i) mod L.
+__device__ inline void rr_pair(int s, int i, int L, int &p, int &q) {
+  if (i == 0) {
+    p = s;
+    q = L;
+  } else {           // s, i < L: both sums lie in [0, 2L)
+    p = s + i;
+    p -= p >= L ? L : 0;
+    q = s - i + L;
+    q -= q >= L ? L : 0;
+  }
+}
+
+// One cyclic sweep over all pairs of the nc columns in LDS (column c at
+// cols + c * ld). Every pair of a round runs at once, 16 lanes per pair.
+// Adds the number of rotations to *counter.
+__device__ void lds_sweep_all(double *cols, int nc, int len, int ld, double tol, int *counter) {
+  const int ncp = (nc + 1) & ~1, L = ncp - 1, npairs = ncp / 2;
+  const int g = threadIdx.x >> 4, gl = threadIdx.x & 15, ng = blockDim.x >> 4;
+  for (int s = 0; s < L; ++s) {
+    for (int i = g; i < npairs; i += ng) {
+      int p, q;
+      rr_pair(s, i, L, p, q);
+      if (p < nc && q < nc) {
+        if (rotate_any(cols + (int64_t)min(p, q) * ld, cols + (int64_t)max(p, q) * ld, len, gl, tol) &&
+            gl == 0)
+          atomicAdd(counter, 1);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Whole k x k problem in one workgroup (k*k <= kLdsDoubles): Wc (column
+// storage, global) is loaded into LDS, swept to convergence, written back.
+__global__ __launch_bounds__(1024) void k_jacobi_lds(double *Wc, int k, double tol, int max_sweeps,
+                                                     int *sweeps_out) {
+  __shared__ double cols[kLdsAlloc];
+  __shared__ int counter;
+  const int ld = k + 1;
+  const int64_t kk = (int64_t)k * k;
+  for (int64_t e = threadIdx.x; e < kk; e += blockDim.x) cols[(e / k) * ld + e % k] = Wc[e];
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (threadIdx.x == 0) counter = 0;
+    __syncthreads();
+    lds_sweep_all(cols, k, k, ld, tol, &counter);
+    const int n = counter;
+    __syncthreads();
+    if (n == 0) break;
+  }
+  for (int64_t e = threadIdx.x; e < kk; e += blockDim.x) Wc[e] = cols[(e / k) * ld + e % k];
+  if (threadIdx.x == 0 && sweeps_out) *sweeps_out = sweep;
+}
+
+// Block one-sided Jacobi step for k too large for one workgroup: the k
+// columns form nb (even) blocks of b; in outer round `round` the blocks pair
+// up in round-robin order and workgroup w takes pair (I, J), loads its
+// columns into LDS and rotates every pair (p in I, q in J) once (b rounds
+// of b disjoint pairs: p = i, q = (i + s) mod b). In round 0 it first
+// rotates the pairs inside I and inside J, so one outer sweep (nb - 1
+// rounds) visits every column pair exactly once. Rotations set flag[0].
+__global__ __launch_bounds__(1024) void k_jacobi_block(double *Wc, int k, int b, int nb, int round,
+                                                       double tol, int *flag) {
+  __shared__ double cols[kLdsAlloc];
+  __shared__ int counter;
+  const int L = nb - 1, ld = k + 1;
+  int I, J;
+  rr_pair(round, blockIdx.x, L, I, J);
+  const int i0 = I * b, j0 = J * b;
+  const int ni = max(0, min(k, i0 + b) - i0), nj = max(0, min(k, j0 + b) - j0);
+  const int nc = ni + nj;
+  for (int64_t e = threadIdx.x; e < (int64_t)nc * k; e += blockDim.x) {
+    const int c = (int)(e / k), r = (int)(e % k);
+    const int gc = c < ni ? i0 + c : j0 + (c - ni);
+    cols[c * ld + r] = Wc[(int64_t)gc * k + r];
+  }
+  if (threadIdx.x == 0) counter = 0;
+  __syncthreads();
+  const int g = threadIdx.x >> 4, gl = threadIdx.x & 15, ng = blockDim.x >> 4;
+  if (round == 0) {
+    // pairs inside I and inside J: two interleaved round-robins
+    const int bp = (max(ni, nj) + 1) & ~1, Lb = bp - 1, half = bp / 2;
+    for (int s = 0; s < Lb; ++s) {
+      for (int x = g; x < 2 * half; x += ng) {
+        const int side = x >= half, i = x - (side ? half : 0);
+        const int nside = side ? nj : ni, base = side ? ni : 0;
+        int p, q;
+        rr_pair(s, i, Lb, p, q);
+        if (p < nside && q < nside) {
+          if (rotate_any(cols + (base + min(p, q)) * ld, cols + (base + max(p, q)) * ld, k, gl, tol) &&
+              gl == 0)
+            atomicAdd(&counter, 1);
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int bb = max(ni, nj);
+  for (int s = 0; s < bb; ++s) {
+    for (int i = g; i < bb; i += ng) {
+      const int j = i + s - (i + s >= bb ? bb : 0);
+      if (i < ni && j < nj) {
+        if (rotate_any(cols + i * ld, cols + (ni + j) * ld, k, gl, tol) && gl == 0)
+          atomicAdd(&counter, 1);
+      }
+    }
+    __syncthreads();
+  }
+  for (int64_t e = threadIdx.x; e < (int64_t)nc * k; e += blockDim.x) {
+    const int c = (int)(e / k), r = (int)(e % k);
+    const int gc = c < ni ? i0 + c : j0 + (c - ni);
+    Wc[(int64_t)gc * k + r] = cols[c * ld + r];
+  }
+  if (threadIdx.x == 0 && counter) atomicOr(flag, 1);
+}
+
+// Column norms sigma_c = |Wc[c]|, ranks by decreasing sigma (ties: lower c
+// first), and the sorted, normalised columns written as rows of UT:
+// UT[pos][i] = Wc[c][i] / sigma_c (so UT = U_R^T with sorted columns).
+// UT may be NULL (values only).
+__global__ __launch_bounds__(1024) void k_jacobi_finish(const double *Wc, int k, double *UT,
+                                                        double *sigma) {
+  extern __shared__ double sm[];  // 2k doubles: norms, then positions
+  double *nrm = sm;
+  int *pos = (int *)(sm + k);
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double s = 0;
+    for (int i = 0; i < k; ++i) {
+      const double x = Wc[(int64_t)c * k + i];
+      s += x * x;
+    }
+    nrm[c] = sqrt(s);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    int r = 0;
+    for (int d = 0; d < k; ++d) r += (nrm[d] > nrm[c]) || (nrm[d] == nrm[c] && d < c);
+    pos[c] = r;
+    sigma[r] = nrm[c];
+  }
+  __syncthreads();
+  if (UT) {
+    for (int64_t e = threadIdx.x; e < (int64_t)k * k; e += blockDim.x) {
+      const int c = (int)(e / k), i = (int)(e % k);
+      const double s = nrm[c];
+      UT[(int64_t)pos[c] * k + i] = s > 0 ? Wc[e] / s : 0.0;
+    }
+  }
+}
+
+// Sign convention: the largest-magnitude entry of each column of V (n x k)
+// is made positive; the lowest row index wins ties. One block per column.
+__global__ __launch_bounds__(256) void k_sign_fix(double *V, int64_t n, int k) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  const int c = blockIdx.x;
+  double best = -1.0;
+  int64_t bidx = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double a = fabs(V[i * k + c]);
+    if (a > best) {
+      best = a;
+      bidx = i;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bidx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      const double a = bv[threadIdx.x + o];
+      const int64_t ai = bi[threadIdx.x + o];
+      if (a > bv[threadIdx.x] || (a == bv[threadIdx.x] && ai < bi[threadIdx.x])) {
+        bv[threadIdx.x] = a;
+        bi[threadIdx.x] = ai;
+      }
+    }
+    __syncthreads();
+  }
+  const bool flip = V[bi[0] * k + c] < 0.0;
+  __syncthreads();
+  if (flip)
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) V[i * k + c] = -V[i * k + c];
+}
+
+// ------------------------------------------------------------- driver ------
+__global__ void k_zero_i32(int *p, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+int zero_i32(int *p, int count, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i32, (count + 255) / 256, 256, 0, s, p, count);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+namespace {
+
+// M (k x k) = A^T A for A (rows x k, row-major), FP64.
+int gram(const double *A, int64_t rows, int k, double *M, double *part, int splits,
+         hipStream_t s) {
+  LSPCA_TRY(launch_tn(LSPCA_F64, A, k, A, k, part, rows, k, k, splits, s));
+  return launch_reduce_add(LSPCA_F64, part, splits, (int64_t)k * k, M, 0, s);
+}
+
+constexpr int kBlk = 128;   // diagonal block size of the blocked k x k kernels
+
+// Cholesky M = R^T R (k x k, symmetric, full storage), R left in the upper
+// triangle. k <= 128: one LDS kernel. Larger k: right-looking blocked form
+// with 128-blocks: R_JJ = chol(M_JJ); R_J,rest = R_JJ^-T M_J,rest;
+// M_rest,rest -= R_J,rest^T R_J,rest. scratch: 2 * 128 * 128 doubles.
+int chol(double *M, int k, int *dflag, double *scratch, hipStream_t s) {
+  if (k <= kBlk) {
+    hipLaunchKernelGGL(k_chol_lds, 1, 1024, 0, s, M, k, (int64_t)k, dflag);
+    LSPCA_HIP(hipGetLastError());
+    return LSPCA_OK;
+  }
+  double *XT = scratch;
+  for (int j0 = 0; j0 < k; j0 += kBlk) {
+    const int jb = std::min(kBlk, k - j0);
+    double *Mjj = M + (int64_t)j0 * k + j0;
+    hipLaunchKernelGGL(k_chol_lds, 1, 1024, 0, s, Mjj, jb, (int64_t)k, dflag);
+    LSPCA_HIP(hipGetLastError());
+    const int r0 = j0 + jb, rn = k - r0;
+    if (rn <= 0) break;
+    hipLaunchKernelGGL(k_trinv_lds, 1, 1024, 0, s, Mjj, jb, (int64_t)k, XT, (int64_t)jb, nullptr, (int64_t)0);
+    LSPCA_HIP(hipGetLastError());
+    // R_J,rest[r][c] = sum_p XT[r][p] M[r0+c][j0+p]  (M symmetric)
+    LSPCA_TRY(launch_nt(LSPCA_F64, XT, jb, M + (int64_t)r0 * k + j0, k, M + (int64_t)j0 * k + r0, k,
+                        jb, rn, jb, s));
+    // M_rest,rest -= R_J,rest^T R_J,rest
+    LSPCA_TRY(launch_tn(LSPCA_F64, M + (int64_t)j0 * k + r0, k, M + (int64_t)j0 * k + r0, k,
+                        M + (int64_t)r0 * k + r0, jb, rn, rn, 1, s, k, -1.0, 1.0));
+  }
+  hipLaunchKernelGGL(k_zero_lower, (unsigned)(((int64_t)k * k + 255) / 256), 256, 0, s, M, k);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+// XT = (R^-1)^T for upper triangular R (k x k). k <= 128: one LDS kernel.
+// Larger k: diagonal blocks in LDS, then for each block column J and I < J
+// XT_JI = -XT_JJ sum_{P=I}^{J-1} R_PJ^T XT_PI (two products).
+// scratch: 3 * 128 * 128 doubles.
+int trinv_t(const double *R, int k, double *XT, double *scratch, hipStream_t s) {
+  if (k <= kBlk) {
+    hipLaunchKernelGGL(k_trinv_lds, 1, 1024, 0, s, R, k, (int64_t)k, XT, (int64_t)k, nullptr, (int64_t)0);
+    LSPCA_HIP(hipGetLastError());
+    return LSPCA_OK;
+  }
+  const int nb = (k + kBlk - 1) / kBlk;
+  double *Xd = scratch, *S = scratch + kBlk * kBlk;
+  hipLaunchKernelGGL(k_zero_i32, (unsigned)(((int64_t)k * k * 2 + 255) / 256), 256, 0, s, (int *)XT, k * k * 2);
+  LSPCA_HIP(hipGetLastError());
+  for (int J = 0; J < nb; ++J) {
+    const int j0 = J * kBlk, jb = std::min(kBlk, k - j0);
+    hipLaunchKernelGGL(k_trinv_lds, 1, 1024, 0, s, R + (int64_t)j0 * k + j0, jb, (int64_t)k,
+                       XT + (int64_t)j0 * k + j0, (int64_t)k, Xd, (int64_t)jb);
+    LSPCA_HIP(hipGetLastError());
+    for (int I = 0; I < J; ++I) {
+      const int i0 = I * kBlk, ib = std::min(kBlk, k - i0);
+      // S[r][c] = sum over rows p in [i0, j0) of R[p][j0+r] XT[p][i0+c]
+      LSPCA_TRY(launch_tn(LSPCA_F64, R + (int64_t)i0 * k + j0, k, XT + (int64_t)i0 * k + i0, k, S,
+                          j0 - i0, jb, ib, 1, s, ib, 1.0, 0.0));
+      // XT_JI = -XT_JJ S:  C[r][c] = -sum_p X_JJ[p][r] S[p][c]
+      LSPCA_TRY(launch_tn(LSPCA_F64, Xd, jb, S, ib, XT + (int64_t)j0 * k + i0, jb, jb, ib, 1, s, k,
+                          -1.0, 0.0));
+    }
+  }
+  return LSPCA_OK;
+}
+
+static bool debug_on() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("LSPCA_DEBUG");
+    v = (e && *e && *e != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
+
+// Threads for one round of n_pairs pairs at 16 lanes each (whole waves).
+static int round_threads(int n_pairs) {
+  int t = ((16 * n_pairs + 63) / 64) * 64;
+  return t < 64 ? 64 : (t > 1024 ? 1024 : t);
+}
+
+// One-sided Jacobi SVD of a k x k matrix A (singular values and left
+// singular vectors). A is row-major, or already in column storage
+// (Wc[c][i] = A[i][c]) when `cols_given`. Writes the sorted singular
+// values to sigma and, if UT != NULL, U^T (sorted rows).
+int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, double *sigma,
+               int *dflag, hipStream_t s) {
+  const int64_t kk = (int64_t)k * k;
+  if (cols_given)
+    LSPCA_HIP(hipMemcpyAsync(Wc, A, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
+  else {
+    hipLaunchKernelGGL(k_to_cols, (unsigned)((kk + 255) / 256), 256, 0, s, A, k, Wc);
+    LSPCA_HIP(hipGetLastError());
+  }
+  const double tol = 8.0 * (double)std::max(k, 16) * 0x1p-53;
+  int sweeps = 0;
+  if ((int64_t)k * (k + 1) <= kLdsAlloc) {
+    hipLaunchKernelGGL(k_jacobi_lds, 1, round_threads((k + 1) / 2), 0, s, Wc, k, tol, 60, dflag);
+    LSPCA_HIP(hipGetLastError());
+    if (debug_on()) {
+      LSPCA_HIP(hipMemcpyAsync(&sweeps, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+      LSPCA_HIP(hipStreamSynchronize(s));
+    }
+  } else {
+    // blocks of b columns, nb even, 2b padded columns of length k fit in LDS
+    const int bmax = kLdsAlloc / (2 * (k + 1));
+    if (bmax < 1) {
+      set_error("jacobi: k = %d too large for the block kernel", k);
+      return LSPCA_ENOTSUP;
+    }
+    const int nb = 2 * ((k + 2 * bmax - 1) / (2 * bmax));
+    const int b = (k + nb - 1) / nb;
+    int hflag = 0;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+      LSPCA_TRY(zero_i32(dflag, 1, s));
+      for (int round = 0; round < nb - 1; ++round) {
+        hipLaunchKernelGGL(k_jacobi_block, nb / 2, round_threads(b), 0, s, Wc, k, b, nb, round, tol, dflag);
+        LSPCA_HIP(hipGetLastError());
+      }
+      LSPCA_HIP(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+      LSPCA_HIP(hipStreamSynchronize(s));
+      sweeps = sweep + 1;
+      if (!hflag) break;
+    }
+  }
+  if (debug_on()) fprintf(stderr, "[lspca] jacobi k=%d sweeps=%d\n", k, sweeps);
+  hipLaunchKernelGGL(k_jacobi_finish, 1, 1024, (size_t)k * (sizeof(double) + sizeof(int)) + 16, s,
+                     Wc, k, UT, sigma);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+}  // namespace
+
+int small_factor(const double *F, const double *G, int k, int64_t n, double *V, double *sigma,
+                 double *sigma_x, Workspace &ws, hipStream_t s, int *rank_flag) {
+  const int64_t kk = (int64_t)k * k;
+  const int splits = tn_pick_splits(n, k, k);
+  double *Ft = ws.take<double>((size_t)n * k);
+  double *Qa = ws.take<double>((size_t)n * k);
+  double *Qb = ws.take<double>((size_t)n * k);
+  double *part = ws.take<double>(tn_partial_elems(k, k, splits));
+  double *M = ws.take<double>(kk);
+  double *Rall = ws.take<double>(kk);
+  double *Rtmp = ws.take<double>(kk);
+  double *XT = ws.take<double>(kk);
+  double *Wc = ws.take<double>(kk);
+  double *UT = ws.take<double>(kk);
+  double *sx = ws.take<double>(k);
+  double *Vw = ws.take<double>((size_t)n * k);
+  double *scr = ws.take<double>(3 * 128 * 128);
+  double *prebuf = ws.take<double>(4 * kk);
+  double *sw = ws.take<double>(k);
+  int *dflag = ws.take<int>(4);
+  int hflag[4];
+
+  LSPCA_TRY(launch_transpose_f64(F, k, (int)n, Ft, s));   // F (k x n) -> F^T (n x k)
+
+  // Cholesky QR passes on F^T: Q <- Q R_p^-1, R <- R_p R.
+  const double *Qin = Ft;
+  double *Qout = Qa;
+  bool shifted = false;
+  int passes = 0;
+  for (int attempt = 0; attempt < 2 && passes == 0; ++attempt) {
+    const int npass = shifted ? 3 : 2;
+    Qin = Ft;
+    Qout = Qa;
+    bool failed = false;
+    for (int pss = 0; pss < npass; ++pss) {
+      LSPCA_TRY(zero_i32(dflag, 4, s));
+      LSPCA_TRY(gram(Qin, n, k, M, part, splits, s));
+      if (shifted && pss == 0) {
+        // shift = 11 (n k + k (k + 1)) u ||F||_F^2 (shifted Cholesky QR;
+        // Fukaya et al., SIAM J. Sci. Comput. 42, 2020)
+        const double c = 11.0 * ((double)n * k + (double)k * (k + 1)) * 0x1p-53;
+        hipLaunchKernelGGL(k_shift_diag, 1, 256, 0, s, M, k, c);
+        LSPCA_HIP(hipGetLastError());
+      }
+      LSPCA_TRY(chol(M, k, dflag, scr, s));
+      LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+      LSPCA_HIP(hipStreamSynchronize(s));
+      if (hflag[0]) {
+        failed = true;
+        break;
+      }
+      LSPCA_TRY(trinv_t(M, k, XT, scr, s));
+      LSPCA_TRY(launch_nt(LSPCA_F64, Qin, k, XT, k, Qout, k, n, k, k, s));
+      if (pss == 0) {
+        LSPCA_HIP(hipMemcpyAsync(Rall, M, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
+      } else {
+        // Rall <- M * Rall  (nt with B = Rall^T)
+        LSPCA_TRY(launch_transpose_f64(Rall, k, k, Rtmp, s));
+        LSPCA_TRY(launch_nt(LSPCA_F64, M, k, Rtmp, k, Rall, k, k, k, k, s));
+      }
+      Qin = Qout;
+      Qout = (Qout == Qa) ? Qb : Qa;
+    }
+    if (!failed) passes = npass;
+    else if (!shifted) shifted = true;
+    else break;
+  }
+  if (passes == 0) {
+    set_error("factor: Cholesky QR of F^T failed (F is numerically rank deficient)");
+    *rank_flag = 1;
+    return LSPCA_ERANK;
+  }
+  const double *Q = Qin;
+
+  // SVD of R: R W = U_R Sigma; V = Q U_R. Preconditioning: with
+  // R^T = Q2 R2 (Cholesky QR twice on the k x k matrix R^T), R2^T has the
+  // same left singular vectors U_R and singular values as R, and one-sided
+  // Jacobi on the columns of R2^T (= the rows of R2) needs far fewer sweeps
+  // than on R (Drmac and Veselic, SIAM J. Matrix Anal. Appl. 29, 2008).
+  bool pre = !shifted;
+  if (pre) {
+    double *T = prebuf;                              // 4 k x k scratch matrices
+    double *S1 = T + kk, *P = T + 2 * kk, *R2 = T + 3 * kk;
+    LSPCA_TRY(launch_transpose_f64(Rall, k, k, T, s));            // T = R^T
+    for (int pss = 0; pss < 2 && pre; ++pss) {
+      const double *Tin = pss == 0 ? T : P;
+      LSPCA_TRY(zero_i32(dflag, 1, s));
+      LSPCA_TRY(gram(Tin, k, k, M, part, tn_pick_splits(k, k, k), s));
+      LSPCA_TRY(chol(M, k, dflag, scr, s));
+      LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+      LSPCA_HIP(hipStreamSynchronize(s));
+      if (hflag[0]) { pre = false; break; }
+      LSPCA_TRY(trinv_t(M, k, XT, scr, s));
+      double *Pout = pss == 0 ? P : S1;              // P = T S^-1
+      LSPCA_TRY(launch_nt(LSPCA_F64, Tin, k, XT, k, Pout, k, k, k, k, s));
+      if (pss == 0) {
+        LSPCA_HIP(hipMemcpyAsync(R2, M, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
+      } else {
+        // R2 <- S2 R2  (nt with B = R2^T)
+        LSPCA_TRY(launch_transpose_f64(R2, k, k, Rtmp, s));
+        LSPCA_TRY(launch_nt(LSPCA_F64, M, k, Rtmp, k, R2, k, k, k, k, s));
+      }
+    }
+    // the rows of R2 are the columns of R2^T: column storage as is
+    if (pre) LSPCA_TRY(jacobi_svd(R2, true, k, Wc, UT, sw, dflag + 1, s));
+  }
+  if (!pre) LSPCA_TRY(jacobi_svd(Rall, false, k, Wc, UT, sw, dflag + 1, s));
+  LSPCA_TRY(launch_nt(LSPCA_F64, Q, k, UT, k, Vw, k, n, k, k, s));
+  hipLaunchKernelGGL(k_sign_fix, k, 256, 0, s, Vw, n, k);
+  LSPCA_HIP(hipGetLastError());
+
+  if (sigma_x) {
+    // Sigma^s = singular values of R R_G^-1, G = R_G^T R_G.
+    LSPCA_TRY(zero_i32(dflag, 1, s));
+    LSPCA_HIP(hipMemcpyAsync(M, G, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    LSPCA_TRY(chol(M, k, dflag, scr, s));
+    LSPCA_TRY(trinv_t(M, k, XT, scr, s));
+    LSPCA_TRY(launch_nt(LSPCA_F64, Rall, k, XT, k, Rtmp, k, k, k, k, s));
+    LSPCA_TRY(jacobi_svd(Rtmp, false, k, Wc, nullptr, sx, dflag + 2, s));
+    LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    LSPCA_HIP(hipStreamSynchronize(s));
+    if (hflag[0]) {
+      set_error("factor: Cholesky of G failed (the sketch U = X Omega is rank deficient)");
+      *rank_flag = 1;
+      return LSPCA_ERANK;
+    }
+  }
+
+  // Rank check on D: D_k <= 64 n eps D_1 means F is numerically rank deficient.
+  std::vector<double> hs(k);
+  LSPCA_HIP(hipMemcpyAsync(hs.data(), sw, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  LSPCA_HIP(hipStreamSynchronize(s));
+  if (!(hs[k - 1] > 64.0 * (double)n * 0x1p-52 * hs[0])) {
+    set_error("factor: F is numerically rank deficient (D_k = %g, D_1 = %g)", hs[k - 1], hs[0]);
+    *rank_flag = 1;
+    return LSPCA_ERANK;
+  }
+  // Outputs are written only now that every check passed.
+  LSPCA_HIP(hipMemcpyAsync(V, Vw, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
+  LSPCA_HIP(hipMemcpyAsync(sigma, sw, k * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (sigma_x)
+    LSPCA_HIP(hipMemcpyAsync(sigma_x, sx, k * sizeof(double), hipMemcpyDeviceToDevice, s));
+  LSPCA_HIP(hipStreamSynchronize(s));
+  return LSPCA_OK;
+}
+
+}  // namespace lspca

@@ -100,6 +100,16 @@ def lowrank_np(m, n, r, spectrum="inv", s=0.01, seed=0, dtype="f64", scale=1.0):
 _TORCH_DT = {"f64": "float64", "f32": "float32", "bf16": "bfloat16", "f16": "float16"}
 
 
+def _orthonormal_torch(rows, cols, g, device):
+    """Gaussian rows x cols matrix with orthonormal columns, by one Cholesky
+    QR pass in FP64 on the device (the cols x cols factor on the host)."""
+    import torch
+    A = torch.randn(rows, cols, generator=g, device=device, dtype=torch.float64)
+    Gm = (A.t() @ A).cpu().numpy()
+    Linv = np.linalg.inv(np.linalg.cholesky(Gm))
+    return A @ torch.from_numpy(Linv.T.copy()).to(device)
+
+
 def lowrank_torch(m, n, r, spectrum="inv", s=0.01, seed=0, dtype="f32",
                   device="cuda", scale=1.0, chunk_rows=65_536, out=None):
     """The same model, drawn with torch's generator on `device`, written
@@ -110,12 +120,10 @@ def lowrank_torch(m, n, r, spectrum="inv", s=0.01, seed=0, dtype="f32",
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
     r = min(r, m, n)
-    A = torch.randn(m, r, generator=g, device=device, dtype=torch.float32)
-    A, _ = torch.linalg.qr(A)
-    Bm = torch.randn(n, r, generator=g, device=device, dtype=torch.float64)
-    Bm, _ = torch.linalg.qr(Bm)
-    sig = torch.as_tensor(sigmas(spectrum, r, scale), device=device, dtype=torch.float32)
-    Bs = (Bm.to(torch.float32) * sig).t().contiguous()        # r x n
+    A = _orthonormal_torch(m, r, g, device).to(torch.float32)
+    Bm = _orthonormal_torch(n, r, g, device)
+    sig = torch.as_tensor(sigmas(spectrum, r, scale), device=device, dtype=torch.float64)
+    Bs = (Bm * sig).t().contiguous().to(torch.float32)        # r x n
     X = out if out is not None else torch.empty(m, n, device=device, dtype=tdt)
     for r0 in range(0, m, chunk_rows):
         r1 = min(m, r0 + chunk_rows)

@@ -1,0 +1,247 @@
+"""GPU-vs-oracle parity for Omega, the pass (F, G), the small stage, the
+Lazy SPCA fit and the projection, through the C ABI (Python binding)."""
+import numpy as np
+import pytest
+
+from oracle import lspca_oracle as O
+from oracle import philox as P
+from synth import lowrank_np, random_orthonormal_np, storage_to_f64
+from tests.helpers import U32, U64, pass_bound, subspace_tol, to_device
+
+pytestmark = pytest.mark.gpu
+
+TORCH_DT = {"f64": "float64", "f32": "float32", "bf16": "bfloat16", "f16": "float16"}
+CODE = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+
+# (m, n, k, dtype): ragged sizes that span several tiles, with odd n (scalar
+# load path) and n a multiple of 4 (vector load path)
+PASS_CASES = [
+    (1037, 203, 17, "f64"),
+    (2000, 256, 32, "f64"),
+    (1037, 203, 17, "f32"),
+    (3001, 516, 64, "f32"),
+]
+
+
+def _data(m, n, k, dtype, seed=11, spectrum="invsqrt", s=0.05):
+    Xs = lowrank_np(m, n, k, spectrum, s, seed, dtype)
+    return Xs, storage_to_f64(Xs, dtype)
+
+
+# ------------------------------------------------------------------ Omega --
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "f16"])
+@pytest.mark.parametrize("kind", ["gaussian", "sparse"])
+def test_omega_matches_specification(gpu_lib, dtype, kind):
+    import torch
+    n, k, seed = 333, 70, (1 << 33) + 77
+    dev = gpu_lib.omega(n, k, kind, seed, CODE[dtype], p=16)
+    got = dev.to(torch.float64).cpu().numpy()
+    want = P.omega(n, k, kind, seed, p=16, dtype=dtype)
+    if kind == "sparse":
+        assert np.array_equal(got, want)                     # integer work: exact
+    elif dtype == "f64":
+        # both sides evaluate log/sqrt/cos/sin in FP64 (device vs host libm)
+        assert np.max(np.abs(got - want) / np.maximum(1, np.abs(want))) < 8 * U64
+    else:
+        # rounding the FP64 value to FP32/16-bit: identical unless the two FP64
+        # values straddle a rounding boundary (probability ~1e-8 per entry)
+        mism = np.count_nonzero(got != want)
+        assert mism <= 2
+        ulp = {"f32": 2.0 ** -23, "bf16": 2.0 ** -7, "f16": 2.0 ** -10}[dtype]
+        assert np.all(np.abs(got - want) <= ulp * np.maximum(np.abs(want), 2.0 ** -14) + 1e-300)
+
+
+# ------------------------------------------------------------------- pass --
+
+@pytest.mark.parametrize("m,n,k,dtype", PASS_CASES)
+def test_accumulate_matches_oracle_within_bound(gpu_lib, m, n, k, dtype):
+    import torch
+    Xs, X64 = _data(m, n, k, dtype)
+    om = P.omega(n, k, "gaussian", 99, dtype=dtype)
+    X = to_device(Xs, dtype)
+    F = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+    G = torch.zeros((k, k), dtype=torch.float64, device="cuda")
+    gpu_lib.accumulate(X, k, "gaussian", 99, F, G)
+    torch.cuda.synchronize()
+    ref = O.streaming_lazy_fit(X64, om, k)
+    bF, bG = pass_bound(X64, om, dtype)
+    eF = np.abs(F.cpu().numpy() - ref["F"])
+    eG = np.abs(G.cpu().numpy() - ref["G"])
+    assert np.all(eF <= bF), float(np.max(eF / bF))
+    assert np.all(eG <= bG), float(np.max(eG / bG))
+
+
+def test_accumulate_over_slices_equals_one_pass(gpu_lib):
+    """Algorithm 4: any horizontal slicing accumulates the same F."""
+    import torch
+    m, n, k, dtype = 2999, 260, 24, "f32"
+    Xs, X64 = _data(m, n, k, dtype)
+    X = to_device(Xs, dtype)
+    F1 = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+    gpu_lib.accumulate(X, k, "gaussian", 5, F1)
+    F3 = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+    for r0, r1 in [(0, 1000), (1000, 1001), (1001, m)]:
+        gpu_lib.accumulate(X[r0:r1], k, "gaussian", 5, F3)
+    torch.cuda.synchronize()
+    om = P.omega(n, k, "gaussian", 5, dtype=dtype)
+    bF, _ = pass_bound(X64, om, dtype)
+    assert np.all(np.abs(F1.cpu().numpy() - F3.cpu().numpy()) <= 2 * bF)
+
+
+def test_strided_rows(gpu_lib):
+    """ldx > n: X is a column slice of a wider matrix."""
+    import torch
+    m, n, k = 700, 130, 12
+    Xs, X64 = _data(m, n + 7, k, "f64")
+    X = to_device(Xs, "f64")[:, :n]
+    assert X.stride(0) == n + 7
+    V, s = gpu_lib.fit(X, k, "gaussian", 3)
+    ref = O.lazy_fit(X64[:, :n], P.omega(n, k, "gaussian", 3), k)
+    assert O.principal_sines(ref["V"], V.cpu().numpy()).max() < 1e-10
+    assert np.allclose(s.cpu().numpy(), ref["sigma"], rtol=1e-10)
+
+
+# --------------------------------------------------------------------- fit --
+
+@pytest.mark.parametrize("m,n,k,dtype", PASS_CASES)
+def test_fit_matches_oracle(gpu_lib, m, n, k, dtype):
+    Xs, X64 = _data(m, n, k, dtype)
+    om = P.omega(n, k, "gaussian", 21, dtype=dtype)
+    V, s, sx = gpu_lib.fit(to_device(Xs, dtype), k, "gaussian", 21, want_sigma_x=True)
+    V, s, sx = V.cpu().numpy(), s.cpu().numpy(), sx.cpu().numpy()
+    ref = O.lazy_fit(X64, om, k)
+    sp = O.spca_fit(X64, om, k)
+    # orthonormal columns (the Jacobi stage stops at cosines <= 8 k u),
+    # canonical order
+    assert np.max(np.abs(V.T @ V - np.eye(k))) < 16 * max(k, 16) * U64
+    assert np.all(np.diff(s) <= 0)
+    if dtype == "f64":
+        tol_s = tol_v = 1e-10
+    else:
+        bF, _ = pass_bound(X64, om, dtype)
+        err = np.linalg.norm(bF)
+        tol_s = err / ref["sigma"][-1] + 1e-12
+        tol_v = subspace_tol(ref["sigma"][-1], err) + 1e-12
+    assert np.max(np.abs(s - ref["sigma"]) / ref["sigma"]) <= max(tol_s, 1e-13)
+    assert O.principal_sines(ref["V"], V).max() <= tol_v
+    # Proposition 2 across implementations: the GPU Lazy basis spans the
+    # oracle's SPCA subspace; sigma_x matches the oracle's Sigma^s
+    assert O.principal_sines(sp["V"], V).max() <= max(tol_v, 1e-10)
+    rel_sx = np.max(np.abs(sx - sp["sigma"]) / sp["sigma"])
+    assert rel_sx <= (1e-10 if dtype == "f64" else 20 * tol_s), rel_sx
+
+
+def test_fit_full_first_config_f64(gpu_lib):
+    """20,000 x 1,000 FP64, sigma_i = 1/i (i <= 50), noise 0.01, Gaussian
+    Omega, k = 50: every output within 1e-10 relative of the oracle."""
+    from synth import config
+    c = config(1)
+    Xs = lowrank_np(c["m"], c["n"], c["r"], c["spectrum"], c["s"], c["data_seed"], "f64")
+    V, s, sx = gpu_lib.fit(to_device(Xs, "f64"), c["k"], "gaussian", c["omega_seed"], want_sigma_x=True)
+    V, s, sx = V.cpu().numpy(), s.cpu().numpy(), sx.cpu().numpy()
+    om = P.omega(c["n"], c["k"], "gaussian", c["omega_seed"])
+    ref = O.lazy_fit(Xs, om, c["k"])
+    sp = O.spca_fit(Xs, om, c["k"])
+    assert O.principal_sines(ref["V"], V).max() < 1e-10
+    assert np.max(np.abs(s - ref["sigma"]) / ref["sigma"]) < 1e-10
+    assert np.max(np.abs(sx - sp["sigma"]) / sp["sigma"]) < 1e-10
+    # individual columns where the spectrum separates them
+    gaps = np.minimum(np.r_[np.inf, -np.diff(ref["sigma"])], np.r_[-np.diff(ref["sigma"]), np.inf])
+    sep = gaps > 1e-3 * ref["sigma"][0]
+    assert np.max(np.abs(V[:, sep] - ref["V"][:, sep])) < 1e-10
+    # Proposition 3 across implementations: pairwise distances
+    rng = np.random.default_rng(0)
+    pairs = rng.integers(0, c["m"], size=(2000, 2))
+    dg = O.pairwise_distances(Xs @ V, pairs)
+    ds = O.pairwise_distances(Xs @ sp["V"], pairs)
+    assert np.max(np.abs(dg - ds) / np.maximum(ds, 1e-300)) < 1e-10
+
+
+def test_fit_is_deterministic(gpu_lib):
+    Xs, _ = _data(3001, 516, 64, "f32")
+    X = to_device(Xs, "f32")
+    V1, s1 = gpu_lib.fit(X, 64, "gaussian", 8)
+    V2, s2 = gpu_lib.fit(X, 64, "gaussian", 8)
+    assert np.array_equal(V1.cpu().numpy(), V2.cpu().numpy())
+    assert np.array_equal(s1.cpu().numpy(), s2.cpu().numpy())
+
+
+def test_rank_deficient_X_gives_erank(gpu_lib):
+    """The sketch of a rank-3 X cannot have rank k = 6 (footnote to
+    Corollary 1: U = X Omega is full rank only when rank(X) >= l)."""
+    import torch
+    Xs = lowrank_np(500, 40, 3, "inv", 0.0, 4, "f64")
+    with pytest.raises(gpu_lib.LspcaError) as e:
+        gpu_lib.fit(to_device(Xs, "f64"), 6, "gaussian", 1)
+    assert e.value.name == "LSPCA_ERANK"
+    torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------ small stage --
+
+@pytest.mark.parametrize("k,n", [(1, 9), (7, 40), (50, 1000), (128, 1500), (130, 700), (256, 4096)])
+def test_factor_matches_oracle_svd(gpu_lib, k, n):
+    """Truncated SVD of a generated F = U diag(d) W^T with known, separated
+    singular values (condition 1e3): V columns and D to 1e-10."""
+    import torch
+    rng = np.random.default_rng(k)
+    Uf = random_orthonormal_np(k, k, rng)
+    W = random_orthonormal_np(n, k, rng)
+    d = np.geomspace(1e3, 1.0, k) if k > 1 else np.array([3.0])
+    F = (Uf * d) @ W.T
+    V, s = gpu_lib.factor(torch.from_numpy(F).cuda())
+    V, s = V.cpu().numpy(), s.cpu().numpy()
+    Vr, dr = O.truncated_svd(F, k)
+    assert np.max(np.abs(s - dr) / dr) < 1e-12
+    assert np.max(np.abs(V - Vr)) < 1e-10
+    assert np.max(np.abs(V.T @ V - np.eye(k))) < 16 * max(k, 16) * U64
+
+
+def test_factor_ill_conditioned_uses_shifted_path(gpu_lib):
+    """Condition 1e9: the first Cholesky of F F^T fails in FP64, the shifted
+    pass takes over. Any backward-stable SVD (the oracle's LAPACK one too)
+    fixes the row space of F only to about c u kappa(F) (Wedin with a
+    backward error c u ||F||), so the two agree to 64 u kappa = 7e-6."""
+    import torch
+    k, n = 12, 300
+    rng = np.random.default_rng(3)
+    F = (random_orthonormal_np(k, k, rng) * np.geomspace(1e9, 1.0, k)) @ random_orthonormal_np(n, k, rng).T
+    V, s = gpu_lib.factor(torch.from_numpy(F).cuda())
+    Vr, dr = O.truncated_svd(F, k)
+    s = s.cpu().numpy()
+    kappa = dr[0] / dr[-1]
+    assert np.max(np.abs(s - dr) / dr) < 64 * U64 * kappa
+    assert O.principal_sines(Vr, V.cpu().numpy()).max() < 64 * U64 * kappa
+
+
+# -------------------------------------------------------------- transform --
+
+@pytest.mark.parametrize("r,n,k,dtype", [(1, 50, 5, "f64"), (777, 203, 17, "f64"),
+                                         (777, 203, 17, "f32"), (4099, 512, 64, "f32")])
+def test_transform_matches_oracle(gpu_lib, r, n, k, dtype):
+    Xs, X64 = _data(r, n, min(k, r), dtype, seed=2)
+    V = random_orthonormal_np(n, k, np.random.default_rng(1))
+    import torch
+    Z = gpu_lib.transform(to_device(Xs, dtype), torch.from_numpy(V).cuda())
+    Z = Z.double().cpu().numpy()
+    Vq = V if dtype == "f64" else P.round_f32(V)
+    ref = O.transform(X64, Vq)
+    u = U64 if dtype == "f64" else U32
+    bound = (n * u / (1 - n * u)) * (np.abs(X64) @ np.abs(Vq))
+    assert np.all(np.abs(Z - ref) <= bound + 1e-300)
+    if dtype == "f64":
+        assert np.linalg.norm(Z - O.transform(X64, V)) <= 1e-10 * np.linalg.norm(O.transform(X64, V))
+
+
+def test_transform_rows_are_independent(gpu_lib):
+    """A row's projection is bitwise the same alone, in a batch, or at any
+    offset: fixed per-row reduction order."""
+    import torch
+    Xs, _ = _data(1500, 300, 20, "f32", seed=9)
+    X = to_device(Xs, "f32")
+    V = torch.from_numpy(random_orthonormal_np(300, 20, np.random.default_rng(2))).cuda()
+    Zall = gpu_lib.transform(X, V).cpu().numpy()
+    for r0, r1 in [(0, 1), (17, 18), (100, 357), (1499, 1500)]:
+        Zp = gpu_lib.transform(X[r0:r1], V).cpu().numpy()
+        assert np.array_equal(Zp, Zall[r0:r1])
