@@ -170,27 +170,35 @@ static int zero_f64(double *p, int64_t count, hipStream_t s) {
 // --------------------------------------------------------- the pass --------
 // Stripe plan for one pass: Y for a stripe of rows is kept in the workspace.
 struct PassPlan {
-  lspca_dtype cdt;      // compute type of the products
-  size_t esz;           // bytes per element of Y / partials
+  bool h16;             // 16-bit data: nt16/tn16 products, G = F Omega in FP64
+  size_t esz;           // bytes per element of Y / partials (4 or 8)
   int64_t stripe;       // rows per stripe
   int splits_f, splits_g;
   size_t bytes;
 };
 
+static bool is16(lspca_dtype dt) { return dt == LSPCA_BF16 || dt == LSPCA_F16; }
+
 static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool want_g) {
   PassPlan p;
-  p.cdt = xdt;
+  p.h16 = is16(xdt);
   p.esz = xdt == LSPCA_F64 ? 8 : 4;
   const int64_t budget = (int64_t)2 << 30;              // Y stripe bytes
   int64_t rows = budget / ((int64_t)k * p.esz);
   rows = rows < 1024 ? 1024 : rows;
   p.stripe = m < rows ? m : rows;
   p.splits_f = tn_pick_splits(p.stripe, k, (int)n);
-  p.splits_g = want_g ? tn_pick_splits(p.stripe, k, k) : 0;
+  p.splits_g = (want_g && !p.h16) ? tn_pick_splits(p.stripe, k, k) : 0;
   p.bytes = ws_bytes<char>(dtype_size(xdt) * (size_t)n * k)              // Omega^T
             + ws_bytes<char>(p.esz * (size_t)p.stripe * k)                // Y stripe
             + ws_bytes<char>(p.esz * tn_partial_elems(k, (int)n, p.splits_f))
-            + (want_g ? ws_bytes<char>(p.esz * tn_partial_elems(k, k, p.splits_g)) : 0);
+            + (p.splits_g ? ws_bytes<char>(p.esz * tn_partial_elems(k, k, p.splits_g)) : 0);
+  if (p.h16) {
+    p.bytes += ws_bytes<unsigned>(k) + ws_bytes<float>(k) + ws_bytes<double>(k);  // FP16 scales
+    if (want_g)
+      p.bytes += ws_bytes<double>((size_t)n * k)      // Omega^T in FP64 (the values used)
+                 + ws_bytes<double>((size_t)n * k);   // this call's F
+  }
   return p;
 }
 
@@ -201,39 +209,69 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
                     const PassPlan &pl, Workspace &ws, PhaseTimer &tm) {
   hipStream_t s = o.stream;
   const size_t xs = dtype_size(xdt);
-  if (xdt == LSPCA_BF16 || xdt == LSPCA_F16) {
-    set_error("16-bit data: not built in this version");
-    return LSPCA_ENOTSUP;
-  }
-  if (kind == LSPCA_OMEGA_VERY_SPARSE && xdt != LSPCA_F64 && xdt != LSPCA_F32) {
-    set_error("sparse omega: dtype not supported");
-    return LSPCA_ENOTSUP;
-  }
+  const bool refine = o.refine != 0;                 // default (-1) and 1: on
   void *OmT = ws.take<char>(xs * (size_t)n * k);
   void *Y = ws.take<char>(pl.esz * (size_t)pl.stripe * k);
   void *PF = ws.take<char>(pl.esz * tn_partial_elems(k, (int)n, pl.splits_f));
-  void *PG = G ? ws.take<char>(pl.esz * tn_partial_elems(k, k, pl.splits_g)) : nullptr;
+  void *PG = pl.splits_g ? ws.take<char>(pl.esz * tn_partial_elems(k, k, pl.splits_g)) : nullptr;
+  unsigned *colmax = nullptr;
+  float *scale = nullptr;
+  double *inv = nullptr, *OmT64 = nullptr, *Fs = nullptr;
+  if (pl.h16) {
+    colmax = ws.take<unsigned>(k);
+    scale = ws.take<float>(k);
+    inv = ws.take<double>(k);
+    if (G) {
+      OmT64 = ws.take<double>((size_t)n * k);
+      Fs = ws.take<double>((size_t)n * k);
+    }
+  }
+  const bool fp16 = xdt == LSPCA_F16;
 
   // Omega^T (k x n) in the compute type: OmT[c][j] = Omega[j][c].
   LSPCA_TRY(launch_omega(n, k, kind, seed, o.p, xdt, OmT, 1, n, s));
+  if (OmT64) LSPCA_TRY(launch_omega(n, k, kind, seed, o.p, LSPCA_F64, OmT64, 1, n, s, xdt));
   tm.mark(PH_OMEGA);
+  double *Fdst = Fs ? Fs : F;                        // 16-bit with G: this call's F first
+  const int acc = Fs ? 0 : 1;
   for (int64_t r0 = 0; r0 < m; r0 += pl.stripe) {
     const int64_t rows = (m - r0) < pl.stripe ? (m - r0) : pl.stripe;
     const char *Xs = (const char *)X + (size_t)r0 * ldx * xs;
-    // Y_s = X_s Omega (Algorithm 4 step 2a)
-    LSPCA_TRY(launch_nt(pl.cdt, Xs, ldx, OmT, n, Y, k, rows, k, (int)n, s));
-    tm.mark(PH_SKETCH);
-    // F += Y_s^T X_s (step 2b); G += Y_s^T Y_s
     const int sf = tn_pick_splits(rows, k, (int)n);
-    LSPCA_TRY(launch_tn(pl.cdt, Y, k, Xs, ldx, PF, rows, k, (int)n, sf, s));
-    int sg = 0;
-    if (G) {
-      sg = tn_pick_splits(rows, k, k);
-      LSPCA_TRY(launch_tn(pl.cdt, Y, k, Y, k, PG, rows, k, k, sg, s));
+    if (!pl.h16) {
+      // Y_s = X_s Omega (Algorithm 4 step 2a)
+      LSPCA_TRY(launch_nt(xdt, Xs, ldx, OmT, n, Y, k, rows, k, (int)n, s));
+      tm.mark(PH_SKETCH);
+      // F += Y_s^T X_s (step 2b); G += Y_s^T Y_s
+      LSPCA_TRY(launch_tn(xdt, Y, k, Xs, ldx, PF, rows, k, (int)n, sf, s));
+      int sg = 0;
+      if (G) {
+        sg = tn_pick_splits(rows, k, k);
+        LSPCA_TRY(launch_tn(xdt, Y, k, Y, k, PG, rows, k, k, sg, s));
+      }
+      tm.mark(PH_FACTOR);
+      LSPCA_TRY(launch_reduce_add(xdt, PF, sf, (int64_t)k * n, F, 1, s));
+      if (G) LSPCA_TRY(launch_reduce_add(xdt, PG, sg, (int64_t)k * k, G, 1, s));
+      tm.mark(PH_REDUCE);
+    } else {
+      if (fp16) LSPCA_TRY(zero_i32((int *)colmax, k, s));
+      LSPCA_TRY(launch_nt16(xdt, Xs, ldx, OmT, nullptr, n, (float *)Y, k, rows, k, (int)n,
+                            fp16 ? colmax : nullptr, s));
+      if (fp16) LSPCA_TRY(launch_col_scales(colmax, k, scale, inv, s));
+      tm.mark(PH_SKETCH);
+      LSPCA_TRY(launch_tn16(xdt, (const float *)Y, k, Xs, ldx, (float *)PF, rows, k, (int)n, sf,
+                            refine, fp16 ? scale : nullptr, s));
+      tm.mark(PH_FACTOR);
+      const int accum = (r0 > 0) ? 1 : acc;
+      LSPCA_TRY(launch_reduce_add(LSPCA_F32, PF, sf, (int64_t)k * n, Fdst, accum, s,
+                                  fp16 ? inv : nullptr, (int)n));
+      tm.mark(PH_REDUCE);
     }
-    tm.mark(PH_FACTOR);
-    LSPCA_TRY(launch_reduce_add(pl.cdt, PF, sf, (int64_t)k * n, F, 1, s));
-    if (G) LSPCA_TRY(launch_reduce_add(pl.cdt, PG, sg, (int64_t)k * k, G, 1, s));
+  }
+  if (Fs) {
+    // G += F_s Omega (= Y^T X Omega = Y^T Y), F += F_s, both in FP64
+    LSPCA_TRY(launch_nt(LSPCA_F64, Fs, n, OmT64, n, G, k, k, k, (int)n, s, 1.0, 1.0));
+    LSPCA_TRY(launch_reduce_add(LSPCA_F64, Fs, 1, (int64_t)k * n, F, 1, s));
     tm.mark(PH_REDUCE);
   }
   return LSPCA_OK;
@@ -382,16 +420,20 @@ int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t n, int64_
   if (r < 0 || n < 1 || k < 1 || ldx < n) { set_error("bad sizes (r=%lld n=%lld k=%d ldx=%lld)", (long long)r, (long long)n, k, (long long)ldx); return LSPCA_EINVAL; }
   if (r == 0) return LSPCA_OK;
   if (!X || !V || !Z) { set_error("X, V and Z must not be NULL"); return LSPCA_EINVAL; }
-  if (xdt == LSPCA_BF16 || xdt == LSPCA_F16) { set_error("16-bit data: not built in this version"); return LSPCA_ENOTSUP; }
   Locked L;
   LSPCA_TRY(lock_device(L));
   const size_t es = dtype_size(xdt);
-  LSPCA_TRY(L.st->ws.ensure(ws_bytes<char>(es * (size_t)n * k)));
+  const bool h16 = is16(xdt);
+  LSPCA_TRY(L.st->ws.ensure((h16 ? 2 : 1) * ws_bytes<char>(es * (size_t)n * k)));
   void *VT = L.st->ws.take<char>(es * (size_t)n * k);
+  void *VTlo = h16 ? L.st->ws.take<char>(es * (size_t)n * k) : nullptr;
   PhaseTimer tm;
   tm.begin(o.timing != 0, o.stream);
-  LSPCA_TRY(launch_convert_vt(V, n, k, xdt, VT, nullptr, o.stream));
-  LSPCA_TRY(launch_nt(xdt, X, ldx, VT, n, Z, k, r, k, (int)n, o.stream));
+  LSPCA_TRY(launch_convert_vt(V, n, k, xdt, VT, VTlo, o.stream));
+  if (h16)
+    LSPCA_TRY(launch_nt16(xdt, X, ldx, VT, VTlo, n, (float *)Z, k, r, k, (int)n, nullptr, o.stream));
+  else
+    LSPCA_TRY(launch_nt(xdt, X, ldx, VT, n, Z, k, r, k, (int)n, o.stream));
   tm.mark(PH_TRANSFORM);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;

@@ -101,9 +101,10 @@ enum Phase { PH_START = -1, PH_OMEGA = 0, PH_SKETCH, PH_FACTOR, PH_REDUCE, PH_SM
 
 // ---------------------------------------------------------- launchers ------
 // Omega generation (omega.hip). out has the layout out[j*ld_j + c*ld_c].
+// f64_of: with dt == LSPCA_F64, store the value rounded to that type.
 int launch_omega(int64_t n, int k, int kind, uint64_t seed, uint32_t p,
                  lspca_dtype dt, void *out, int64_t ld_j, int64_t ld_c,
-                 hipStream_t s);
+                 hipStream_t s, int f64_of = LSPCA_F64);
 
 // Dense products (gemm.hip). All matrices row-major.
 //  nt: C[M x N] = A[M x K] * B[N x K]^T   (A, B: K contiguous)
@@ -116,11 +117,24 @@ int launch_tn(lspca_dtype dt, const void *A, int64_t lda, const void *B,
               int64_t ldb, void *P, int64_t M_rows, int Mi, int Nj, int splits,
               hipStream_t s, int64_t ldp = 0, double alpha = 1.0, double beta = 0.0);
 int tn_pick_splits(int64_t rows, int Mi, int Nj);
+// 16-bit products (gemm16.hip): C/P FP32; B_lo may be NULL; colmax may be
+// NULL (else max |C| per column, as float bits, atomically).
+int launch_nt16(lspca_dtype dt, const void *A, int64_t lda, const void *Bh,
+                const void *Bl, int64_t ldb, float *C, int64_t ldc, int64_t M,
+                int N, int K, unsigned *colmax, hipStream_t s);
+int launch_tn16(lspca_dtype dt, const float *Y, int64_t ldy, const void *X,
+                int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
+                bool refine, const float *scale, hipStream_t s);
+int launch_col_scales(const unsigned *colmax, int k, float *scale, double *inv,
+                      hipStream_t s);
 size_t tn_partial_elems(int Mi, int Nj, int splits);
 
 // Reductions and small FP64 stage (small.hip).
+// out[e] (+)= rowscale[e / ncols] * sum_s P[s][e] (rowscale may be NULL).
 int launch_reduce_add(lspca_dtype pdt, const void *P, int splits, int64_t count,
-                      double *out, int accumulate, hipStream_t s);
+                      double *out, int accumulate, hipStream_t s,
+                      const double *rowscale = nullptr, int ncols = 1);
+int zero_i32(int *p, int count, hipStream_t s);
 int small_factor(const double *F, const double *G, int k, int64_t n,
                  double *V, double *sigma, double *sigma_x, Workspace &ws,
                  hipStream_t s, int *rank_flag);

@@ -24,6 +24,20 @@ template <> __device__ inline void put<bf16_t>(void *out, int64_t idx, double v)
 template <> __device__ inline void put<f16_t>(void *out, int64_t idx, double v) {
   ((uint16_t *)out)[idx] = f32_to_f16_bits((float)v);
 }
+// FP64 storage of the value the given type holds (for FP64 products with
+// the exact Omega a lower-precision pass used).
+struct f64_of_f32 {};
+struct f64_of_bf16 {};
+struct f64_of_f16 {};
+template <> __device__ inline void put<f64_of_f32>(void *out, int64_t idx, double v) {
+  ((double *)out)[idx] = (double)(float)v;
+}
+template <> __device__ inline void put<f64_of_bf16>(void *out, int64_t idx, double v) {
+  ((double *)out)[idx] = (double)bf16_bits_to_f32(f32_to_bf16_bits((float)v));
+}
+template <> __device__ inline void put<f64_of_f16>(void *out, int64_t idx, double v) {
+  ((double *)out)[idx] = (double)f16_bits_to_f32(f32_to_f16_bits((float)v));
+}
 
 // One thread per (row j, column block q): Gaussian blocks hold 2 columns,
 // sparse blocks 4. out[j*ld_j + c*ld_c].
@@ -55,7 +69,7 @@ __global__ void k_omega(int64_t n, int k, int kind, uint32_t key0, uint32_t key1
 }
 
 int launch_omega(int64_t n, int k, int kind, uint64_t seed, uint32_t p, lspca_dtype dt,
-                 void *out, int64_t ld_j, int64_t ld_c, hipStream_t s) {
+                 void *out, int64_t ld_j, int64_t ld_c, hipStream_t s, int f64_of) {
   const int per = kind == LSPCA_OMEGA_GAUSSIAN ? 2 : 4;
   const int64_t total = n * ((k + per - 1) / per);
   if (total <= 0) return LSPCA_OK;
@@ -64,6 +78,21 @@ int launch_omega(int64_t n, int k, int kind, uint64_t seed, uint32_t p, lspca_dt
   const uint64_t t_minus = (1ull << 32) / (uint64_t)p;
   const int threads = 256;
   const unsigned grid = (unsigned)((total + threads - 1) / threads);
+  if (dt == LSPCA_F64 && f64_of != LSPCA_F64) {
+    switch (f64_of) {
+      case LSPCA_F32:
+        hipLaunchKernelGGL(k_omega<f64_of_f32>, grid, threads, 0, s, n, k, kind, key0, key1, t_plus, t_minus, out, ld_j, ld_c);
+        break;
+      case LSPCA_BF16:
+        hipLaunchKernelGGL(k_omega<f64_of_bf16>, grid, threads, 0, s, n, k, kind, key0, key1, t_plus, t_minus, out, ld_j, ld_c);
+        break;
+      default:
+        hipLaunchKernelGGL(k_omega<f64_of_f16>, grid, threads, 0, s, n, k, kind, key0, key1, t_plus, t_minus, out, ld_j, ld_c);
+        break;
+    }
+    LSPCA_HIP(hipGetLastError());
+    return LSPCA_OK;
+  }
   switch (dt) {
     case LSPCA_F64:
       hipLaunchKernelGGL(k_omega<double>, grid, threads, 0, s, n, k, kind, key0, key1, t_plus, t_minus, out, ld_j, ld_c);

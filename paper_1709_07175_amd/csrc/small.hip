@@ -52,23 +52,25 @@ __device__ inline double sum8(double v) {
 // ----------------------------------------------------------- reductions ----
 template <typename PT>
 __global__ void k_reduce_add(const PT *__restrict__ P, int splits, int64_t count,
-                             double *__restrict__ out, int accumulate) {
+                             double *__restrict__ out, int accumulate,
+                             const double *__restrict__ rowscale, int ncols) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= count) return;
   double s = accumulate ? out[e] : 0.0;
   double part = 0.0;
   for (int z = 0; z < splits; ++z) part += (double)P[(int64_t)z * count + e];
+  if (rowscale) part *= rowscale[e / ncols];
   out[e] = s + part;
 }
 
 int launch_reduce_add(lspca_dtype pdt, const void *P, int splits, int64_t count, double *out,
-                      int accumulate, hipStream_t s) {
+                      int accumulate, hipStream_t s, const double *rowscale, int ncols) {
   if (count <= 0) return LSPCA_OK;
   const unsigned grid = (unsigned)((count + 255) / 256);
   if (pdt == LSPCA_F64)
-    hipLaunchKernelGGL(k_reduce_add<double>, grid, 256, 0, s, (const double *)P, splits, count, out, accumulate);
+    hipLaunchKernelGGL(k_reduce_add<double>, grid, 256, 0, s, (const double *)P, splits, count, out, accumulate, rowscale, ncols);
   else
-    hipLaunchKernelGGL(k_reduce_add<float>, grid, 256, 0, s, (const float *)P, splits, count, out, accumulate);
+    hipLaunchKernelGGL(k_reduce_add<float>, grid, 256, 0, s, (const float *)P, splits, count, out, accumulate, rowscale, ncols);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }

@@ -20,6 +20,10 @@ PASS_CASES = [
     (2000, 256, 32, "f64"),
     (1037, 203, 17, "f32"),
     (3001, 516, 64, "f32"),
+    (1037, 203, 17, "bf16"),
+    (3001, 520, 136, "bf16"),
+    (1037, 203, 17, "f16"),
+    (2999, 512, 64, "f16"),
 ]
 
 
@@ -218,17 +222,24 @@ def test_factor_ill_conditioned_uses_shifted_path(gpu_lib):
 # -------------------------------------------------------------- transform --
 
 @pytest.mark.parametrize("r,n,k,dtype", [(1, 50, 5, "f64"), (777, 203, 17, "f64"),
-                                         (777, 203, 17, "f32"), (4099, 512, 64, "f32")])
+                                         (777, 203, 17, "f32"), (4099, 512, 64, "f32"),
+                                         (777, 203, 17, "bf16"), (4099, 512, 256, "bf16"),
+                                         (777, 203, 17, "f16"), (1025, 512, 128, "f16")])
 def test_transform_matches_oracle(gpu_lib, r, n, k, dtype):
     Xs, X64 = _data(r, n, min(k, r), dtype, seed=2)
     V = random_orthonormal_np(n, k, np.random.default_rng(1))
     import torch
     Z = gpu_lib.transform(to_device(Xs, dtype), torch.from_numpy(V).cuda())
     Z = Z.double().cpu().numpy()
-    Vq = V if dtype == "f64" else P.round_f32(V)
+    Vq = V if dtype != "f32" else P.round_f32(V)
     ref = O.transform(X64, Vq)
     u = U64 if dtype == "f64" else U32
     bound = (n * u / (1 - n * u)) * (np.abs(X64) @ np.abs(Vq))
+    if dtype in ("bf16", "f16"):
+        # V = V_hi + V_lo in 16-bit parts: |V - V_hi - V_lo| <= u16^2 |V|,
+        # plus V rounded to FP32 first (u32), plus the second product's sum
+        u16 = 2.0 ** -8 if dtype == "bf16" else 2.0 ** -11
+        bound = 2 * bound + (1.01 * u16 ** 2 + U32 + 2.0 ** -24) * (np.abs(X64) @ np.abs(V))
     assert np.all(np.abs(Z - ref) <= bound + 1e-300)
     if dtype == "f64":
         assert np.linalg.norm(Z - O.transform(X64, V)) <= 1e-10 * np.linalg.norm(O.transform(X64, V))
@@ -245,3 +256,46 @@ def test_transform_rows_are_independent(gpu_lib):
     for r0, r1 in [(0, 1), (17, 18), (100, 357), (1499, 1500)]:
         Zp = gpu_lib.transform(X[r0:r1], V).cpu().numpy()
         assert np.array_equal(Zp, Zall[r0:r1])
+
+
+# --------------------------------------------------------------- 16-bit --
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_refinement_shrinks_the_factor_error(gpu_lib, dtype):
+    """One refinement pass (F = Y_hi^T X + Y_lo^T X, X read once) against
+    Y_hi alone: both within their bound, the refined error far smaller."""
+    import torch
+    m, n, k = 4000, 384, 48
+    Xs, X64 = _data(m, n, k, dtype)
+    om = P.omega(n, k, "gaussian", 31, dtype=dtype)
+    ref = O.streaming_lazy_fit(X64, om, k)["F"]
+    errs = {}
+    for refine in (1, 0):
+        F = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+        gpu_lib.accumulate(to_device(Xs, dtype), k, "gaussian", 31, F, refine=refine)
+        torch.cuda.synchronize()
+        e = np.abs(F.cpu().numpy() - ref)
+        bF, _ = pass_bound(X64, om, dtype, refine=bool(refine))
+        assert np.all(e <= bF), (refine, float(np.max(e / bF)))
+        errs[refine] = np.linalg.norm(e) / np.linalg.norm(ref)
+    # BF16 (u16 = 2^-8): refinement removes the split error, which dominates;
+    # FP16 (u16 = 2^-11): the unrefined split error is closer to the FP32
+    # accumulation floor that remains after refinement
+    assert errs[1] < errs[0] / (20 if dtype == "bf16" else 4), errs
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_sparse_omega_fit_16bit(gpu_lib, dtype):
+    """Very sparse Omega (p = 64) with 16-bit data and refinement: the max
+    principal-angle sine against the FP64 oracle stays far below 1e-3."""
+    m, n, k = 6000, 1024, 64
+    Xs, X64 = _data(m, n, k, dtype)
+    V, s = gpu_lib.fit(to_device(Xs, dtype), k, "sparse", 77, sparse_p=64)
+    om = P.omega(n, k, "sparse", 77, p=64, dtype=dtype)
+    ref = O.lazy_fit(X64, om, k)
+    sine = O.principal_sines(ref["V"], V.cpu().numpy()).max()
+    bF, _ = pass_bound(X64, om, dtype)
+    err = np.linalg.norm(bF)
+    assert sine <= subspace_tol(ref["sigma"][-1], err) + 1e-12
+    assert sine < 1e-3
+    assert np.max(np.abs(s.cpu().numpy() - ref["sigma"]) / ref["sigma"]) <= err / ref["sigma"][-1] + 1e-12
