@@ -171,6 +171,8 @@ static int zero_f64(double *p, int64_t count, hipStream_t s) {
 // Stripe plan for one pass: Y for a stripe of rows is kept in the workspace.
 struct PassPlan {
   bool h16;             // 16-bit data: nt16/tn16 products, G = F Omega in FP64
+  bool gather;          // very sparse Omega applied by gather-adds (no Omega^T)
+  int cap;              // LDS list capacity of the gather kernel
   size_t esz;           // bytes per element of Y / partials (4 or 8)
   int64_t stripe;       // rows per stripe
   int splits_f, splits_g;
@@ -179,9 +181,12 @@ struct PassPlan {
 
 static bool is16(lspca_dtype dt) { return dt == LSPCA_BF16 || dt == LSPCA_F16; }
 
-static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool want_g) {
+static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool want_g, int kind,
+                          uint32_t sp) {
   PassPlan p;
   p.h16 = is16(xdt);
+  p.cap = 0;
+  p.gather = kind == LSPCA_OMEGA_VERY_SPARSE && sparse_sketch_ok(xdt, n, k, sp, &p.cap);
   p.esz = xdt == LSPCA_F64 ? 8 : 4;
   const int64_t budget = (int64_t)2 << 30;              // Y stripe bytes
   int64_t rows = budget / ((int64_t)k * p.esz);
@@ -195,6 +200,7 @@ static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool wan
             + (p.splits_g ? ws_bytes<char>(p.esz * tn_partial_elems(k, k, p.splits_g)) : 0);
   if (p.h16) {
     p.bytes += ws_bytes<unsigned>(k) + ws_bytes<float>(k) + ws_bytes<double>(k);  // FP16 scales
+    p.bytes += ws_bytes<int>(4);                                                 // flags
     if (want_g)
       p.bytes += ws_bytes<double>((size_t)n * k)      // Omega^T in FP64 (the values used)
                  + ws_bytes<double>((size_t)n * k);   // this call's F
@@ -217,10 +223,12 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
   unsigned *colmax = nullptr;
   float *scale = nullptr;
   double *inv = nullptr, *OmT64 = nullptr, *Fs = nullptr;
+  int *flags = nullptr;
   if (pl.h16) {
     colmax = ws.take<unsigned>(k);
     scale = ws.take<float>(k);
     inv = ws.take<double>(k);
+    flags = ws.take<int>(4);
     if (G) {
       OmT64 = ws.take<double>((size_t)n * k);
       Fs = ws.take<double>((size_t)n * k);
@@ -228,8 +236,9 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
   }
   const bool fp16 = xdt == LSPCA_F16;
 
-  // Omega^T (k x n) in the compute type: OmT[c][j] = Omega[j][c].
-  LSPCA_TRY(launch_omega(n, k, kind, seed, o.p, xdt, OmT, 1, n, s));
+  // Omega^T (k x n) in the compute type: OmT[c][j] = Omega[j][c]. The
+  // gather path regenerates Omega inside the sketch kernel instead.
+  if (!pl.gather) LSPCA_TRY(launch_omega(n, k, kind, seed, o.p, xdt, OmT, 1, n, s));
   if (OmT64) LSPCA_TRY(launch_omega(n, k, kind, seed, o.p, LSPCA_F64, OmT64, 1, n, s, xdt));
   tm.mark(PH_OMEGA);
   double *Fdst = Fs ? Fs : F;                        // 16-bit with G: this call's F first
@@ -255,8 +264,14 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
       tm.mark(PH_REDUCE);
     } else {
       if (fp16) LSPCA_TRY(zero_i32((int *)colmax, k, s));
-      LSPCA_TRY(launch_nt16(xdt, Xs, ldx, OmT, nullptr, n, (float *)Y, k, rows, k, (int)n,
-                            fp16 ? colmax : nullptr, s));
+      if (pl.gather) {
+        LSPCA_TRY(zero_i32(flags, 1, s));
+        LSPCA_TRY(launch_sparse_sketch(xdt, Xs, rows, n, ldx, k, seed, o.p, pl.cap, (float *)Y, k,
+                                       fp16 ? colmax : nullptr, flags, s));
+      } else {
+        LSPCA_TRY(launch_nt16(xdt, Xs, ldx, OmT, nullptr, n, (float *)Y, k, rows, k, (int)n,
+                              fp16 ? colmax : nullptr, s));
+      }
       if (fp16) LSPCA_TRY(launch_col_scales(colmax, k, scale, inv, s));
       tm.mark(PH_SKETCH);
       LSPCA_TRY(launch_tn16(xdt, (const float *)Y, k, Xs, ldx, (float *)PF, rows, k, (int)n, sf,
@@ -351,7 +366,7 @@ int lspca_accumulate(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64
   if (!F) { set_error("F is NULL"); return LSPCA_EINVAL; }
   Locked L;
   LSPCA_TRY(lock_device(L));
-  PassPlan pl = plan_pass(xdt, m, n, k, G != nullptr);
+  PassPlan pl = plan_pass(xdt, m, n, k, G != nullptr, kind, o.p);
   LSPCA_TRY(L.st->ws.ensure(pl.bytes));
   PhaseTimer tm;
   tm.begin(o.timing != 0, o.stream);
@@ -391,7 +406,7 @@ int lspca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx,
   Locked L;
   LSPCA_TRY(lock_device(L));
   const bool want_g = sigma_x != nullptr;
-  PassPlan pl = plan_pass(xdt, m, n, k, want_g);
+  PassPlan pl = plan_pass(xdt, m, n, k, want_g, kind, o.p);
   const size_t fg = ws_bytes<double>((size_t)k * n) + ws_bytes<double>((size_t)k * k);
   const size_t fb = factor_bytes(n, k);
   LSPCA_TRY(L.st->ws.ensure(fg + (pl.bytes > fb ? pl.bytes : fb)));

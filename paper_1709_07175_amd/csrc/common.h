@@ -125,6 +125,11 @@ int launch_nt16(lspca_dtype dt, const void *A, int64_t lda, const void *Bh,
 int launch_tn16(lspca_dtype dt, const float *Y, int64_t ldy, const void *X,
                 int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
                 bool refine, const float *scale, hipStream_t s);
+// Very sparse sketch by gather-adds (sparse.hip).
+bool sparse_sketch_ok(lspca_dtype dt, int64_t n, int k, uint32_t p, int *cap_out);
+int launch_sparse_sketch(lspca_dtype dt, const void *X, int64_t m, int64_t n, int64_t ldx, int k,
+                         uint64_t seed, uint32_t p, int cap, float *Y, int64_t ldy,
+                         unsigned *colmax, int *overflow, hipStream_t s);
 int launch_col_scales(const unsigned *colmax, int k, float *scale, double *inv,
                       hipStream_t s);
 size_t tn_partial_elems(int Mi, int Nj, int splits);

@@ -299,3 +299,41 @@ def test_sparse_omega_fit_16bit(gpu_lib, dtype):
     assert sine <= subspace_tol(ref["sigma"][-1], err) + 1e-12
     assert sine < 1e-3
     assert np.max(np.abs(s.cpu().numpy() - ref["sigma"]) / ref["sigma"]) <= err / ref["sigma"][-1] + 1e-12
+
+
+@pytest.mark.parametrize("dtype,p", [("bf16", 64), ("f16", 64), ("bf16", 1), ("bf16", 8)])
+def test_sparse_sketch_accumulate_matches_oracle(gpu_lib, dtype, p):
+    """Gather-add sketch (Omega regenerated per workgroup, never stored):
+    F and G within the componentwise bound of the oracle's, on ragged
+    sizes (m not a multiple of the 4-row tile, n not of 8)."""
+    import torch
+    m, n, k = 2001, 517, 40
+    Xs, X64 = _data(m, n, k, dtype)
+    om = P.omega(n, k, "sparse", 1234, p=p, dtype=dtype)
+    F = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+    G = torch.zeros((k, k), dtype=torch.float64, device="cuda")
+    gpu_lib.accumulate(to_device(Xs, dtype), k, "sparse", 1234, F, G, sparse_p=p)
+    torch.cuda.synchronize()
+    ref = O.streaming_lazy_fit(X64, om, k)
+    bF, bG = pass_bound(X64, om, dtype)
+    assert np.all(np.abs(F.cpu().numpy() - ref["F"]) <= bF)
+    assert np.all(np.abs(G.cpu().numpy() - ref["G"]) <= bG)
+
+
+def test_sparse_sketch_fallback_gives_the_same_bits(gpu_lib, monkeypatch):
+    """A list capacity below the number of nonzeros (forced from the host)
+    switches the workgroups to on-the-fly regeneration: same summation
+    order, so the same F bit for bit."""
+    import torch
+    m, n, k = 1500, 300, 32
+    Xs, _ = _data(m, n, k, "bf16")
+    X = to_device(Xs, "bf16")
+    F1 = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+    gpu_lib.accumulate(X, k, "sparse", 9, F1, sparse_p=4)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("LSPCA_SPARSE_CAP", "64")
+    F2 = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+    gpu_lib.accumulate(X, k, "sparse", 9, F2, sparse_p=4)
+    torch.cuda.synchronize()
+    monkeypatch.delenv("LSPCA_SPARSE_CAP")
+    assert np.array_equal(F1.cpu().numpy(), F2.cpu().numpy())
