@@ -135,7 +135,8 @@ def main():
 
     # dominant kernel: the sketch Y = X Omega (nt product, one launch per step)
     flops_sketch = 2.0 * m * n * k
-    peak = PEAKS["fp64_mfma_TFs"] if cfg["dtype"] == "f64" else PEAKS["fp32_mfma_TFs"]
+    peak = {"f64": PEAKS["fp64_mfma_TFs"], "f32": PEAKS["fp32_mfma_TFs"],
+            "bf16": PEAKS["bf16_mfma_TFs"], "f16": PEAKS["fp16_mfma_TFs"]}[cfg["dtype"]]
     achieved = flops_sketch / (sketch_ms * 1e-3) / 1e12
     out = {
         "metric": "X-stream GB/s (% HBM/MFMA roofline) per Lazy SPCA fit vs SPCA; projection p99 ms",

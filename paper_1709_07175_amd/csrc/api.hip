@@ -199,6 +199,7 @@ static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool wan
             + ws_bytes<char>(p.esz * tn_partial_elems(k, (int)n, p.splits_f))
             + (p.splits_g ? ws_bytes<char>(p.esz * tn_partial_elems(k, k, p.splits_g)) : 0);
   if (p.h16) {
+    p.bytes += 2 * ws_bytes<uint16_t>((size_t)p.stripe * k);                    // Yh, Yl
     p.bytes += ws_bytes<unsigned>(k) + ws_bytes<float>(k) + ws_bytes<double>(k);  // FP16 scales
     p.bytes += ws_bytes<int>(4);                                                 // flags
     if (want_g)
@@ -224,7 +225,10 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
   float *scale = nullptr;
   double *inv = nullptr, *OmT64 = nullptr, *Fs = nullptr;
   int *flags = nullptr;
+  uint16_t *Yh = nullptr, *Yl = nullptr;
   if (pl.h16) {
+    Yh = ws.take<uint16_t>((size_t)pl.stripe * k);
+    Yl = ws.take<uint16_t>((size_t)pl.stripe * k);
     colmax = ws.take<unsigned>(k);
     scale = ws.take<float>(k);
     inv = ws.take<double>(k);
@@ -263,19 +267,25 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
       if (G) LSPCA_TRY(launch_reduce_add(xdt, PG, sg, (int64_t)k * k, G, 1, s));
       tm.mark(PH_REDUCE);
     } else {
+      // sketch, written transposed: BF16 directly split into Yh/Yl;
+      // FP16 as FP32 with column maxima, then scaled and split
+      uint16_t *Ylo = refine ? Yl : nullptr;
       if (fp16) LSPCA_TRY(zero_i32((int *)colmax, k, s));
       if (pl.gather) {
         LSPCA_TRY(zero_i32(flags, 1, s));
-        LSPCA_TRY(launch_sparse_sketch(xdt, Xs, rows, n, ldx, k, seed, o.p, pl.cap, (float *)Y, k,
-                                       fp16 ? colmax : nullptr, flags, s));
+        LSPCA_TRY(launch_sparse_sketch(xdt, Xs, rows, n, ldx, k, seed, o.p, pl.cap,
+                                       fp16 ? (float *)Y : nullptr, rows, fp16 ? colmax : nullptr,
+                                       Yh, Ylo, flags, s));
       } else {
-        LSPCA_TRY(launch_nt16(xdt, Xs, ldx, OmT, nullptr, n, (float *)Y, k, rows, k, (int)n,
-                              fp16 ? colmax : nullptr, s));
+        LSPCA_TRY(launch_nt16(xdt, Xs, ldx, OmT, nullptr, n, fp16 ? (float *)Y : nullptr, rows, rows,
+                              k, (int)n, fp16 ? colmax : nullptr, Yh, Ylo, fp16 ? 1 : 2, s));
       }
-      if (fp16) LSPCA_TRY(launch_col_scales(colmax, k, scale, inv, s));
+      if (fp16) {
+        LSPCA_TRY(launch_col_scales(colmax, k, scale, inv, s));
+        LSPCA_TRY(launch_split16(xdt, (const float *)Y, k, rows, scale, Yh, Ylo, s));
+      }
       tm.mark(PH_SKETCH);
-      LSPCA_TRY(launch_tn16(xdt, (const float *)Y, k, Xs, ldx, (float *)PF, rows, k, (int)n, sf,
-                            refine, fp16 ? scale : nullptr, s));
+      LSPCA_TRY(launch_tn16(xdt, Yh, Ylo, rows, Xs, ldx, (float *)PF, rows, k, (int)n, sf, s));
       tm.mark(PH_FACTOR);
       const int accum = (r0 > 0) ? 1 : acc;
       LSPCA_TRY(launch_reduce_add(LSPCA_F32, PF, sf, (int64_t)k * n, Fdst, accum, s,
@@ -446,7 +456,8 @@ int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t n, int64_
   tm.begin(o.timing != 0, o.stream);
   LSPCA_TRY(launch_convert_vt(V, n, k, xdt, VT, VTlo, o.stream));
   if (h16)
-    LSPCA_TRY(launch_nt16(xdt, X, ldx, VT, VTlo, n, (float *)Z, k, r, k, (int)n, nullptr, o.stream));
+    LSPCA_TRY(launch_nt16(xdt, X, ldx, VT, VTlo, n, (float *)Z, k, r, k, (int)n, nullptr, nullptr,
+                          nullptr, 0, o.stream));
   else
     LSPCA_TRY(launch_nt(xdt, X, ldx, VT, n, Z, k, r, k, (int)n, o.stream));
   tm.mark(PH_TRANSFORM);

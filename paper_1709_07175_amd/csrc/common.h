@@ -43,6 +43,31 @@ __device__ inline float f16_bits_to_f32(uint16_t b) {
   return (float)__builtin_bit_cast(_Float16, b);
 }
 
+// ------------------------------------------------------- XCD-aware grid ----
+// MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
+// with its own L2. For a split-over-rows product launched as a 3-D grid
+// (x: column tiles, y: row-of-output tiles, z: row splits), this remaps the
+// linear workgroup id so that all (x, y) tiles of one split z -- which read
+// the same rows of the shared operand -- run on the same XCD. The map is a
+// bijection of [0, X*Y*Z) whenever X*Y*Z is a multiple of 8 (the launchers
+// round the split count so that it is); otherwise the identity is used.
+__device__ inline void xcd_map(int &bx, int &by, int &bz) {
+  const int X = gridDim.x, Y = gridDim.y, Z = gridDim.z;
+  const int per = X * Y;
+  const int total = per * Z;
+  const int b = blockIdx.x + X * (blockIdx.y + Y * blockIdx.z);
+  int logical = b;
+  if ((total & 7) == 0 && (Z & 7) == 0) {
+    const int xcd = b & 7, slot = b >> 3;        // slot-th workgroup on this XCD
+    const int zl = slot / per, t = slot - zl * per;
+    logical = (zl * 8 + xcd) * per + t;          // split zl*8+xcd, tile t
+  }
+  bz = logical / per;
+  const int t = logical - bz * per;
+  by = t / X;
+  bx = t - by * X;
+}
+
 // ------------------------------------------------------------- errors ------
 void set_error(const char *fmt, ...);
 const char *get_error();
@@ -117,21 +142,29 @@ int launch_tn(lspca_dtype dt, const void *A, int64_t lda, const void *B,
               int64_t ldb, void *P, int64_t M_rows, int Mi, int Nj, int splits,
               hipStream_t s, int64_t ldp = 0, double alpha = 1.0, double beta = 0.0);
 int tn_pick_splits(int64_t rows, int Mi, int Nj);
-// 16-bit products (gemm16.hip): C/P FP32; B_lo may be NULL; colmax may be
-// NULL (else max |C| per column, as float bits, atomically).
+// 16-bit products (gemm16.hip). nt16 output mode: 0 row-major FP32 C;
+// 1 transposed FP32 C[c*ldc + r] with max |C| per column (colmax); 2
+// transposed and split into 16-bit parts Ch, Cl (Cl may be NULL). B_lo
+// (split second operand) only with mode 0.
 int launch_nt16(lspca_dtype dt, const void *A, int64_t lda, const void *Bh,
                 const void *Bl, int64_t ldb, float *C, int64_t ldc, int64_t M,
-                int N, int K, unsigned *colmax, hipStream_t s);
-int launch_tn16(lspca_dtype dt, const float *Y, int64_t ldy, const void *X,
-                int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
-                bool refine, const float *scale, hipStream_t s);
-// Very sparse sketch by gather-adds (sparse.hip).
-bool sparse_sketch_ok(lspca_dtype dt, int64_t n, int k, uint32_t p, int *cap_out);
-int launch_sparse_sketch(lspca_dtype dt, const void *X, int64_t m, int64_t n, int64_t ldx, int k,
-                         uint64_t seed, uint32_t p, int cap, float *Y, int64_t ldy,
-                         unsigned *colmax, int *overflow, hipStream_t s);
+                int N, int K, unsigned *colmax, void *Ch, void *Cl, int mode,
+                hipStream_t s);
+// F partials from the transposed split sketch Yh/Yl[i*ldyt + r] and X.
+int launch_tn16(lspca_dtype dt, const void *Yh, const void *Yl, int64_t ldyt,
+                const void *X, int64_t ldx, float *P, int64_t rows, int Mi, int Nj,
+                int splits, hipStream_t s);
+// Scale row c of Yt (rows_k x ld) by scale[c] and split into 16-bit parts.
+int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld,
+                   const float *scale, void *Yh, void *Yl, hipStream_t s);
 int launch_col_scales(const unsigned *colmax, int k, float *scale, double *inv,
                       hipStream_t s);
+// Very sparse sketch by gather-adds (sparse.hip).
+bool sparse_sketch_ok(lspca_dtype dt, int64_t n, int k, uint32_t p, int *cap_out);
+// Output as launch_nt16 modes 1 (Y FP32 + colmax) or 2 (Yh, Yl split).
+int launch_sparse_sketch(lspca_dtype dt, const void *X, int64_t m, int64_t n, int64_t ldx, int k,
+                         uint64_t seed, uint32_t p, int cap, float *Y, int64_t ldy,
+                         unsigned *colmax, void *Yh, void *Yl, int *overflow, hipStream_t s);
 size_t tn_partial_elems(int Mi, int Nj, int splits);
 
 // Reductions and small FP64 stage (small.hip).

@@ -184,8 +184,10 @@ __global__ __launch_bounds__(256) void k_tn(const T *__restrict__ A, int64_t lda
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
-  const int j0 = blockIdx.x * BN, i0 = blockIdx.y * BM;
-  const int64_t rbeg = (int64_t)blockIdx.z * chunk;
+  int bx, by, bz;
+  xcd_map(bx, by, bz);
+  const int j0 = bx * BN, i0 = by * BM;
+  const int64_t rbeg = (int64_t)bz * chunk;
   const int64_t rend = rbeg + chunk < rows ? rbeg + chunk : rows;
 
   T ra[AV * VW], rb[BV * VW];
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(256) void k_tn(const T *__restrict__ A, int64_t lda
     __syncthreads();
   }
 
-  T *Pz = P + (int64_t)blockIdx.z * Mi * ldp;
+  T *Pz = P + (int64_t)bz * Mi * ldp;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -333,6 +335,7 @@ int tn_pick_splits(int64_t rows, int Mi, int Nj) {
   int64_t want = (2048 + tiles - 1) / tiles;
   int64_t maxs = (rows + 127) / 128;
   int64_t s = want < maxs ? want : maxs;
+  if (s >= 8) s = s / 8 * 8;                 // multiple of 8 for the XCD map
   if (s < 1) s = 1;
   if (s > 4096) s = 4096;
   return (int)s;

@@ -5,14 +5,15 @@
 //
 //  k_nt16: C[M x N] (FP32) = A[M x K] * (B_hi + B_lo)[N x K]^T, 16-bit
 //          operands, both K-contiguous. Sketch Y = X Omega (no B_lo) and the
-//          projection Z = X V with V split in two 16-bit parts.
-//          Optionally records max |C| per column (for FP16 scaling).
+//          projection Z = X V with V split in two 16-bit parts. The sketch
+//          writes Y transposed (Yt, rows contiguous) for k_tn16, and can
+//          record max |C| per column (for FP16 scaling).
 //  k_tn16: P[s][M x N] (FP32) = sum over rows r of chunk s of
 //          (Y_hi + Y_lo)[r][i] * X[r][j]: F = Y^T X with the FP32 sketch Y
 //          split on load into 16-bit parts, Y = Y_hi + Y_lo (refinement) or
 //          Y_hi alone; each column i of Y scaled by an exact power of two
-//          first (FP16 range). Both operands are transposed into LDS so that
-//          every fragment is one 16-byte read.
+//          first (FP16 range). Both LDS tiles are row-index contiguous, so
+//          every MFMA fragment is one 16-byte read.
 #include "common.h"
 
 namespace lspca {
@@ -22,7 +23,8 @@ typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
 
 template <int DT> struct H16;
 template <> struct H16<LSPCA_BF16> {
-  __device__ static inline uint16_t from_f32(float f) { return f32_to_bf16_bits(f); }
+  // (__bf16)f rounds to nearest even (v_cvt_pk_bf16_f32 on gfx950)
+  __device__ static inline uint16_t from_f32(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
   __device__ static inline float to_f32(uint16_t b) { return bf16_bits_to_f32(b); }
   __device__ static inline f32x16 mfma(u16x8 a, u16x8 b, f32x16 c) {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
@@ -43,12 +45,19 @@ __device__ inline int mrow(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >>
 // ------------------------------------------------------------------- NT16 --
 // Tile BM x BN x 32, 4 waves as 2 x 2. VEC: 16-byte global loads (K % 8 == 0,
 // 16-byte aligned rows); otherwise element loads.
-template <int DT, int BM, int BN, bool SPLITB, bool VEC>
+// Output modes: OUT_ROWS: C row-major FP32 (ldc); OUT_T32: C transposed,
+// C[c*ldc + r], FP32, with max |C| per column in colmax; OUT_TSPLIT: the
+// transposed result split into 16-bit parts Ch = rn(C), Cl = rn(C - Ch)
+// (Cl may be NULL), each [c*ldc + r].
+enum { OUT_ROWS = 0, OUT_T32 = 1, OUT_TSPLIT = 2 };
+
+template <int DT, int BM, int BN, bool SPLITB, bool VEC, int OUT>
 __global__ __launch_bounds__(256) void k_nt16(const uint16_t *__restrict__ A, int64_t lda,
                                               const uint16_t *__restrict__ Bh,
                                               const uint16_t *__restrict__ Bl, int64_t ldb,
                                               float *__restrict__ C, int64_t ldc, int64_t M, int N,
-                                              int K, unsigned *__restrict__ colmax) {
+                                              int K, unsigned *__restrict__ colmax,
+                                              uint16_t *__restrict__ Ch, uint16_t *__restrict__ Cl) {
   constexpr int BK = 32, LD = BK + 8;                 // +16 bytes per row of a tile
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
   constexpr int AV = BM * BK / 8 / 256, BV = BN * BK / 8 / 256;
@@ -148,101 +157,164 @@ __global__ __launch_bounds__(256) void k_nt16(const uint16_t *__restrict__ A, in
     const int c = n0 + wn0 + j * 32 + (lane & 31);
     float cmax = 0.f;
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TM; ++i) {
+      if constexpr (OUT != OUT_ROWS) {
+        // elements v = 4q .. 4q+3 of a lane are 4 consecutive rows
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t r = m0 + wm0 + i * 32 + mrow(lane, v);
-        if (r < M && c < N) {
-          C[r * ldc + c] = acc[i][j][v];
-          cmax = fmaxf(cmax, fabsf(acc[i][j][v]));
+        for (int q = 0; q < 4; ++q) {
+          const int64_t r = m0 + wm0 + i * 32 + mrow(lane, 4 * q);
+          const f32x4 w = {acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
+                           acc[i][j][4 * q + 3]};
+          if (c < N) {
+            const bool full = r + 3 < M && (ldc & 3) == 0;
+            if constexpr (OUT == OUT_T32) {
+              if (full) {
+                *(f32x4 *)(C + (int64_t)c * ldc + r) = w;
+              } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                  if (r + e < M) C[(int64_t)c * ldc + r + e] = w[e];
+              }
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (r + e < M) cmax = fmaxf(cmax, fabsf(w[e]));
+            } else {
+              u16x4 hv, lv;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                hv[e] = H16<DT>::from_f32(w[e]);
+                lv[e] = H16<DT>::from_f32(w[e] - H16<DT>::to_f32(hv[e]));
+              }
+              if (full) {
+                *(u16x4 *)(Ch + (int64_t)c * ldc + r) = hv;
+                if (Cl) *(u16x4 *)(Cl + (int64_t)c * ldc + r) = lv;
+              } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                  if (r + e < M) {
+                    Ch[(int64_t)c * ldc + r + e] = hv[e];
+                    if (Cl) Cl[(int64_t)c * ldc + r + e] = lv[e];
+                  }
+              }
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t r = m0 + wm0 + i * 32 + mrow(lane, v);
+          if (r < M && c < N) C[r * ldc + c] = acc[i][j][v];
         }
       }
-    if (colmax && c < N) atomicMax(colmax + c, __float_as_uint(cmax));
+    }
+    if constexpr (OUT == OUT_T32)
+      if (colmax && c < N) atomicMax(colmax + c, __float_as_uint(cmax));
+  }
+}
+
+// FP16 split of the transposed FP32 sketch: column c (row of Yt) is scaled
+// by scale[c] (a power of two) and split, Yh = rn(s y), Yl = rn(s y - Yh).
+template <int DT>
+__global__ void k_split16(const float *__restrict__ Yt, int64_t count, int64_t ld,
+                          const float *__restrict__ scale, uint16_t *__restrict__ Yh,
+                          uint16_t *__restrict__ Yl) {
+  const int64_t e4 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+  if (e4 >= count) return;
+  for (int e = 0; e < 4 && e4 + e < count; ++e) {
+    const int64_t idx = e4 + e;
+    const float y = Yt[idx] * (scale ? scale[idx / ld] : 1.f);
+    const uint16_t h = H16<DT>::from_f32(y);
+    Yh[idx] = h;
+    if (Yl) Yl[idx] = H16<DT>::from_f32(y - H16<DT>::to_f32(h));
   }
 }
 
 // ------------------------------------------------------------------- TN16 --
 // Tile: BM (columns of Y) x 128 (columns of X) x 32 rows; 4 waves as 2 x 2.
-// Y: FP32 rows with leading dimension ldy, column i scaled by scale[i]
-// (powers of two; NULL = 1). X: 16-bit rows, leading dimension ldx.
+// Y arrives transposed and already split into 16-bit parts, Yh[i][r] and
+// Yl[i][r] (leading dimension ldyt, rows contiguous; Yl NULL without
+// refinement), so its tiles go to LDS with 16-byte copies. X (16-bit rows,
+// leading dimension ldx): each thread loads 2 rows x 8 columns and
+// transposes them in registers into eight 2-row pieces of the column-major
+// LDS tile Bs[j][r]. Both LDS tiles are row-index contiguous, so every MFMA
+// fragment is one 16-byte read.
 template <int DT, int BM, bool REFINE>
-__global__ __launch_bounds__(256) void k_tn16(const float *__restrict__ Y, int64_t ldy,
+__global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
+                                              const uint16_t *__restrict__ Yl, int64_t ldyt,
                                               const uint16_t *__restrict__ X, int64_t ldx,
                                               float *__restrict__ P, int64_t rows, int Mi, int Nj,
-                                              int64_t chunk, const float *__restrict__ scale) {
+                                              int64_t chunk) {
   constexpr int BN = 128, BK = 32, LD = BK + 8;
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
   constexpr int NPART = REFINE ? 2 : 1;
-  constexpr int AV = BM * BK / 4 / 256;               // float4 loads of Y per thread
-  constexpr int BV = BN * BK / 8 / 256;               // 8 x 16-bit loads of X per thread
+  constexpr int AV = BM * BK / 8 / 256;               // u16x8 loads per part per thread
+  static_assert(BN * BK / 16 == 256, "one 2x8 piece of X per thread");
   __shared__ uint16_t As[2][NPART * BM * LD];
   __shared__ uint16_t Bs[2][BN * LD];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
-  const int j0 = blockIdx.x * BN, i0 = blockIdx.y * BM;
-  const int64_t rbeg = (int64_t)blockIdx.z * chunk;
+  int bx, by, bz;
+  xcd_map(bx, by, bz);
+  const int j0 = bx * BN, i0 = by * BM;
+  const int64_t rbeg = (int64_t)bz * chunk;
   const int64_t rend = rbeg + chunk < rows ? rbeg + chunk : rows;
+  const bool yvec = (ldyt & 7) == 0 && ((uintptr_t)Yh & 15) == 0 && (!REFINE || ((uintptr_t)Yl & 15) == 0);
+  const bool xvec = (ldx & 7) == 0 && ((uintptr_t)X & 15) == 0;
+  const int xp = tid & 15, xg = tid >> 4;  // X piece: rows 2xp, 2xp+1; columns 8xg..+7
 
-  f32x4 ra[AV];
-  u16x8 rb[BV];
-  float sc[AV][4];
-#pragma unroll
-  for (int v = 0; v < AV; ++v) {
-    const int idx = tid + v * 256, c = (idx % (BM / 4)) * 4;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) sc[v][e] = (scale && i0 + c + e < Mi) ? scale[i0 + c + e] : 1.f;
-  }
+  u16x8 ra[NPART][AV];
+  u16x8 rb[2];
   auto load = [&](int64_t r0) {
 #pragma unroll
-    for (int v = 0; v < AV; ++v) {
-      const int idx = tid + v * 256, kr = idx / (BM / 4), c = (idx % (BM / 4)) * 4;
-      const int64_t gr = r0 + kr;
-      f32x4 x = {};
-      if (gr < rend) {
-        if (i0 + c + 3 < Mi && (ldy & 3) == 0) {
-          x = *(const f32x4 *)(Y + gr * ldy + i0 + c);
-        } else {
+    for (int part = 0; part < NPART; ++part) {
+      const uint16_t *Ysrc = part ? Yl : Yh;
 #pragma unroll
-          for (int e = 0; e < 4; ++e) x[e] = i0 + c + e < Mi ? Y[gr * ldy + i0 + c + e] : 0.f;
+      for (int v = 0; v < AV; ++v) {
+        const int idx = tid + v * 256, i = idx / (BK / 8), kr = (idx % (BK / 8)) * 8;
+        const int64_t gr = r0 + kr;
+        u16x8 x = {};
+        if (i0 + i < Mi) {
+          const uint16_t *src = Ysrc + (int64_t)(i0 + i) * ldyt + gr;
+          if (yvec && gr + 7 < rend) {
+            x = *(const u16x8 *)src;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = gr + e < rend ? src[e] : (uint16_t)0;
+          }
         }
+        ra[part][v] = x;
       }
-      ra[v] = x;
     }
 #pragma unroll
-    for (int v = 0; v < BV; ++v) {
-      const int idx = tid + v * 256, kr = idx / (BN / 8), c = (idx % (BN / 8)) * 8;
-      const int64_t gr = r0 + kr;
+    for (int h = 0; h < 2; ++h) {
+      const int64_t gr = r0 + 2 * xp + h;
+      const int c = j0 + 8 * xg;
       u16x8 x = {};
       if (gr < rend) {
-        if (j0 + c + 7 < Nj && (ldx & 7) == 0) {
-          x = *(const u16x8 *)(X + gr * ldx + j0 + c);
+        const uint16_t *src = X + gr * ldx + c;
+        if (xvec && c + 7 < Nj) {
+          x = *(const u16x8 *)src;
         } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) x[e] = j0 + c + e < Nj ? X[gr * ldx + j0 + c + e] : (uint16_t)0;
+          for (int e = 0; e < 8; ++e) x[e] = c + e < Nj ? src[e] : (uint16_t)0;
         }
       }
-      rb[v] = x;
+      rb[h] = x;
     }
   };
-  // transposed stores: As[part][i][r], Bs[j][r]
   auto store = [&](int buf) {
 #pragma unroll
-    for (int v = 0; v < AV; ++v) {
-      const int idx = tid + v * 256, kr = idx / (BM / 4), c = (idx % (BM / 4)) * 4;
+    for (int part = 0; part < NPART; ++part)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float y = ra[v][e] * sc[v][e];
-        const uint16_t hi = H16<DT>::from_f32(y);
-        As[buf][(c + e) * LD + kr] = hi;
-        if constexpr (REFINE) As[buf][(BM + c + e) * LD + kr] = H16<DT>::from_f32(y - H16<DT>::to_f32(hi));
+      for (int v = 0; v < AV; ++v) {
+        const int idx = tid + v * 256, i = idx / (BK / 8), kr = (idx % (BK / 8)) * 8;
+        *(u16x8 *)&As[buf][(part * BM + i) * LD + kr] = ra[part][v];
       }
-    }
 #pragma unroll
-    for (int v = 0; v < BV; ++v) {
-      const int idx = tid + v * 256, kr = idx / (BN / 8), c = (idx % (BN / 8)) * 8;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) Bs[buf][(c + e) * LD + kr] = rb[v][e];
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t w = (uint32_t)rb[0][e] | ((uint32_t)rb[1][e] << 16);
+      *(uint32_t *)&Bs[buf][(8 * xg + e) * LD + 2 * xp] = w;
     }
   };
 
@@ -283,7 +355,7 @@ __global__ __launch_bounds__(256) void k_tn16(const float *__restrict__ Y, int64
     __syncthreads();
   }
 
-  float *Pz = P + (int64_t)blockIdx.z * Mi * Nj;
+  float *Pz = P + (int64_t)bz * Mi * Nj;
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -297,81 +369,97 @@ __global__ __launch_bounds__(256) void k_tn16(const float *__restrict__ Y, int64
 }
 
 // ------------------------------------------------------------- launchers --
-template <int DT, int BM, int BN, bool SPLITB>
+template <int DT, int BM, int BN, bool SPLITB, int OUT>
 static int nt16_typed(const uint16_t *A, int64_t lda, const uint16_t *Bh, const uint16_t *Bl,
                       int64_t ldb, float *C, int64_t ldc, int64_t M, int N, int K,
-                      unsigned *colmax, hipStream_t s) {
+                      unsigned *colmax, uint16_t *Ch, uint16_t *Cl, hipStream_t s) {
   dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN));
   const bool vec = (lda % 8 == 0) && (ldb % 8 == 0) && (K % 8 == 0) && ((uintptr_t)A % 16 == 0) &&
                    ((uintptr_t)Bh % 16 == 0) && (!SPLITB || (uintptr_t)Bl % 16 == 0);
   if (vec)
-    hipLaunchKernelGGL((k_nt16<DT, BM, BN, SPLITB, true>), grid, dim3(256), 0, s, A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax);
+    hipLaunchKernelGGL((k_nt16<DT, BM, BN, SPLITB, true, OUT>), grid, dim3(256), 0, s, A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl);
   else
-    hipLaunchKernelGGL((k_nt16<DT, BM, BN, SPLITB, false>), grid, dim3(256), 0, s, A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax);
+    hipLaunchKernelGGL((k_nt16<DT, BM, BN, SPLITB, false, OUT>), grid, dim3(256), 0, s, A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
+}
+
+template <int DT, bool SPLITB, int OUT>
+static int nt16_n(const uint16_t *A, int64_t lda, const uint16_t *Bh, const uint16_t *Bl,
+                  int64_t ldb, float *C, int64_t ldc, int64_t M, int N, int K, unsigned *colmax,
+                  uint16_t *Ch, uint16_t *Cl, hipStream_t s) {
+  if (N > 128) return nt16_typed<DT, 128, 256, SPLITB, OUT>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
+  return nt16_typed<DT, 128, 128, SPLITB, OUT>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
 }
 
 template <int DT>
 static int nt16_dt(const uint16_t *A, int64_t lda, const uint16_t *Bh, const uint16_t *Bl,
                    int64_t ldb, float *C, int64_t ldc, int64_t M, int N, int K, unsigned *colmax,
-                   hipStream_t s) {
-  if (Bl) {
-    if (N > 128) return nt16_typed<DT, 128, 256, true>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, s);
-    return nt16_typed<DT, 128, 128, true>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, s);
-  }
-  if (N > 128) return nt16_typed<DT, 128, 256, false>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, s);
-  return nt16_typed<DT, 128, 128, false>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, s);
+                   uint16_t *Ch, uint16_t *Cl, int mode, hipStream_t s) {
+  if (Bl) return nt16_n<DT, true, OUT_ROWS>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
+  if (mode == OUT_T32) return nt16_n<DT, false, OUT_T32>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
+  if (mode == OUT_TSPLIT) return nt16_n<DT, false, OUT_TSPLIT>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
+  return nt16_n<DT, false, OUT_ROWS>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
 }
 
 int launch_nt16(lspca_dtype dt, const void *A, int64_t lda, const void *Bh, const void *Bl,
                 int64_t ldb, float *C, int64_t ldc, int64_t M, int N, int K, unsigned *colmax,
-                hipStream_t s) {
+                void *Ch, void *Cl, int mode, hipStream_t s) {
   if (M <= 0 || N <= 0) return LSPCA_OK;
   if ((M + 127) / 128 > 0x7fffffff) {
     set_error("nt16 product: too many row tiles");
     return LSPCA_EINVAL;
   }
   if (dt == LSPCA_BF16)
-    return nt16_dt<LSPCA_BF16>((const uint16_t *)A, lda, (const uint16_t *)Bh, (const uint16_t *)Bl, ldb, C, ldc, M, N, K, colmax, s);
+    return nt16_dt<LSPCA_BF16>((const uint16_t *)A, lda, (const uint16_t *)Bh, (const uint16_t *)Bl, ldb, C, ldc, M, N, K, colmax, (uint16_t *)Ch, (uint16_t *)Cl, mode, s);
   if (dt == LSPCA_F16)
-    return nt16_dt<LSPCA_F16>((const uint16_t *)A, lda, (const uint16_t *)Bh, (const uint16_t *)Bl, ldb, C, ldc, M, N, K, colmax, s);
+    return nt16_dt<LSPCA_F16>((const uint16_t *)A, lda, (const uint16_t *)Bh, (const uint16_t *)Bl, ldb, C, ldc, M, N, K, colmax, (uint16_t *)Ch, (uint16_t *)Cl, mode, s);
   set_error("nt16 product: dtype %d", (int)dt);
   return LSPCA_ENOTSUP;
 }
 
+int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld, const float *scale,
+                   void *Yh, void *Yl, hipStream_t s) {
+  const int64_t count = rows_k * ld;
+  const unsigned grid = (unsigned)((count / 4 + 256) / 256);
+  if (dt == LSPCA_BF16)
+    hipLaunchKernelGGL(k_split16<LSPCA_BF16>, grid, 256, 0, s, Yt, count, ld, scale, (uint16_t *)Yh, (uint16_t *)Yl);
+  else
+    hipLaunchKernelGGL(k_split16<LSPCA_F16>, grid, 256, 0, s, Yt, count, ld, scale, (uint16_t *)Yh, (uint16_t *)Yl);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
 template <int DT, int BM, bool REFINE>
-static int tn16_typed(const float *Y, int64_t ldy, const uint16_t *X, int64_t ldx, float *P,
-                      int64_t rows, int Mi, int Nj, int splits, const float *scale,
+static int tn16_typed(const uint16_t *Yh, const uint16_t *Yl, int64_t ldyt, const uint16_t *X,
+                      int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
                       hipStream_t s) {
   int64_t chunk = (rows + splits - 1) / splits;
   chunk = (chunk + 31) / 32 * 32;
   dim3 grid((unsigned)((Nj + 127) / 128), (unsigned)((Mi + BM - 1) / BM), (unsigned)splits);
-  hipLaunchKernelGGL((k_tn16<DT, BM, REFINE>), grid, dim3(256), 0, s, Y, ldy, X, ldx, P, rows, Mi, Nj, chunk, scale);
+  hipLaunchKernelGGL((k_tn16<DT, BM, REFINE>), grid, dim3(256), 0, s, Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, chunk);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }
 
 template <int DT>
-static int tn16_dt(const float *Y, int64_t ldy, const uint16_t *X, int64_t ldx, float *P,
-                   int64_t rows, int Mi, int Nj, int splits, bool refine, const float *scale,
-                   hipStream_t s) {
+static int tn16_dt(const uint16_t *Yh, const uint16_t *Yl, int64_t ldyt, const uint16_t *X,
+                   int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits, hipStream_t s) {
   if (Mi > 128) {
-    if (refine) return tn16_typed<DT, 256, true>(Y, ldy, X, ldx, P, rows, Mi, Nj, splits, scale, s);
-    return tn16_typed<DT, 256, false>(Y, ldy, X, ldx, P, rows, Mi, Nj, splits, scale, s);
+    if (Yl) return tn16_typed<DT, 256, true>(Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, splits, s);
+    return tn16_typed<DT, 256, false>(Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, splits, s);
   }
-  if (refine) return tn16_typed<DT, 128, true>(Y, ldy, X, ldx, P, rows, Mi, Nj, splits, scale, s);
-  return tn16_typed<DT, 128, false>(Y, ldy, X, ldx, P, rows, Mi, Nj, splits, scale, s);
+  if (Yl) return tn16_typed<DT, 128, true>(Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, splits, s);
+  return tn16_typed<DT, 128, false>(Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, splits, s);
 }
 
-int launch_tn16(lspca_dtype dt, const float *Y, int64_t ldy, const void *X, int64_t ldx, float *P,
-                int64_t rows, int Mi, int Nj, int splits, bool refine, const float *scale,
-                hipStream_t s) {
+int launch_tn16(lspca_dtype dt, const void *Yh, const void *Yl, int64_t ldyt, const void *X,
+                int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits, hipStream_t s) {
   if (Mi <= 0 || Nj <= 0 || splits <= 0) return LSPCA_OK;
   if (dt == LSPCA_BF16)
-    return tn16_dt<LSPCA_BF16>(Y, ldy, (const uint16_t *)X, ldx, P, rows, Mi, Nj, splits, refine, scale, s);
+    return tn16_dt<LSPCA_BF16>((const uint16_t *)Yh, (const uint16_t *)Yl, ldyt, (const uint16_t *)X, ldx, P, rows, Mi, Nj, splits, s);
   if (dt == LSPCA_F16)
-    return tn16_dt<LSPCA_F16>(Y, ldy, (const uint16_t *)X, ldx, P, rows, Mi, Nj, splits, refine, scale, s);
+    return tn16_dt<LSPCA_F16>((const uint16_t *)Yh, (const uint16_t *)Yl, ldyt, (const uint16_t *)X, ldx, P, rows, Mi, Nj, splits, s);
   set_error("tn16 product: dtype %d", (int)dt);
   return LSPCA_ENOTSUP;
 }

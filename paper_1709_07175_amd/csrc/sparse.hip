@@ -26,6 +26,9 @@ constexpr int kSpThreads = 256;
 template <int DT> __device__ inline float h2f(uint16_t b);
 template <> __device__ inline float h2f<LSPCA_BF16>(uint16_t b) { return bf16_bits_to_f32(b); }
 template <> __device__ inline float h2f<LSPCA_F16>(uint16_t b) { return f16_bits_to_f32(b); }
+template <int DT> __device__ inline uint16_t f2h(float f);
+template <> __device__ inline uint16_t f2h<LSPCA_BF16>(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+template <> __device__ inline uint16_t f2h<LSPCA_F16>(float f) { return f32_to_f16_bits(f); }
 
 // Dynamic LDS: [ X tile: n * 4 x 16-bit | start: k+1 ints | fill: k ints |
 //                entries: cap x 16-bit ]
@@ -33,7 +36,8 @@ template <int DT>
 __global__ __launch_bounds__(kSpThreads) void k_sparse_sketch(
     const uint16_t *__restrict__ X, int64_t m, int n, int64_t ldx, int k, uint32_t key0,
     uint32_t key1, uint32_t t_plus, uint64_t t_minus, int cap, float *__restrict__ Y, int64_t ldy,
-    unsigned *__restrict__ colmax, int *__restrict__ overflow) {
+    unsigned *__restrict__ colmax, uint16_t *__restrict__ Yh, uint16_t *__restrict__ Yl,
+    int *__restrict__ overflow) {
   extern __shared__ __align__(16) unsigned char lds[];
   uint16_t *xt = (uint16_t *)lds;                                   // n * 4
   int *start = (int *)(lds + (((size_t)n * kSpRows * 2 + 15) & ~(size_t)15));
@@ -164,17 +168,45 @@ __global__ __launch_bounds__(kSpThreads) void k_sparse_sketch(
             }
           }
         }
-        const float a[4] = {a0, a1, a2, a3};
+        // Y is written transposed (ldy = rows of the stripe): as FP32 Yt[c][r]
+        // (Y != NULL), or split into 16-bit parts Yh[c][r], Yl[c][r]
+        const f32x4 a = {a0, a1, a2, a3};
+        const bool full = r0 + 3 < m && (ldy & 3) == 0;
+        if (Y) {
+          float *dst = Y + (int64_t)c * ldy + r0;
+          if (full) {
+            *(f32x4 *)dst = a;
+          } else {
 #pragma unroll
-        for (int r = 0; r < kSpRows; ++r) {
-          if (r0 + r < m) {
-            Y[(r0 + r) * ldy + c] = a[r];
-            if (cb == 0) cmax[0] = fmaxf(cmax[0], fabsf(a[r]));
-            else if (cb == 256) cmax[1] = fmaxf(cmax[1], fabsf(a[r]));
-            else if (cb == 512) cmax[2] = fmaxf(cmax[2], fabsf(a[r]));
-            else cmax[3] = fmaxf(cmax[3], fabsf(a[r]));
+            for (int r = 0; r < kSpRows; ++r)
+              if (r0 + r < m) dst[r] = a[r];
+          }
+        } else {
+          u16x4 hv, lv;
+#pragma unroll
+          for (int r = 0; r < kSpRows; ++r) {
+            hv[r] = f2h<DT>(a[r]);
+            lv[r] = f2h<DT>(a[r] - h2f<DT>(hv[r]));
+          }
+          uint16_t *dh = Yh + (int64_t)c * ldy + r0;
+          uint16_t *dl = Yl ? Yl + (int64_t)c * ldy + r0 : nullptr;
+          if (full) {
+            *(u16x4 *)dh = hv;
+            if (dl) *(u16x4 *)dl = lv;
+          } else {
+#pragma unroll
+            for (int r = 0; r < kSpRows; ++r)
+              if (r0 + r < m) {
+                dh[r] = hv[r];
+                if (dl) dl[r] = lv[r];
+              }
           }
         }
+        float amax = 0.f;
+#pragma unroll
+        for (int r = 0; r < kSpRows; ++r)
+          if (r0 + r < m) amax = fmaxf(amax, fabsf(a[r]));
+        cmax[cb >> 8] = fmaxf(cmax[cb >> 8], amax);
       }
     }
     __syncthreads();
@@ -212,7 +244,7 @@ bool sparse_sketch_ok(lspca_dtype dt, int64_t n, int k, uint32_t p, int *cap_out
 
 int launch_sparse_sketch(lspca_dtype dt, const void *X, int64_t m, int64_t n, int64_t ldx, int k,
                          uint64_t seed, uint32_t p, int cap, float *Y, int64_t ldy,
-                         unsigned *colmax, int *overflow, hipStream_t s) {
+                         unsigned *colmax, void *Yh, void *Yl, int *overflow, hipStream_t s) {
   const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
   const uint32_t t_plus = (uint32_t)((1ull << 32) / (2ull * p));
   const uint64_t t_minus = (1ull << 32) / (uint64_t)p;
@@ -227,12 +259,12 @@ int launch_sparse_sketch(lspca_dtype dt, const void *X, int64_t m, int64_t n, in
     LSPCA_HIP(hipFuncSetAttribute((const void *)k_sparse_sketch<LSPCA_BF16>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_sparse_sketch<LSPCA_BF16>, grid, kSpThreads, lds, s, (const uint16_t *)X, m,
-                       (int)n, ldx, k, key0, key1, t_plus, t_minus, cap, Y, ldy, colmax, overflow);
+                       (int)n, ldx, k, key0, key1, t_plus, t_minus, cap, Y, ldy, colmax, (uint16_t *)Yh, (uint16_t *)Yl, overflow);
   } else {
     LSPCA_HIP(hipFuncSetAttribute((const void *)k_sparse_sketch<LSPCA_F16>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(k_sparse_sketch<LSPCA_F16>, grid, kSpThreads, lds, s, (const uint16_t *)X, m,
-                       (int)n, ldx, k, key0, key1, t_plus, t_minus, cap, Y, ldy, colmax, overflow);
+                       (int)n, ldx, k, key0, key1, t_plus, t_minus, cap, Y, ldy, colmax, (uint16_t *)Yh, (uint16_t *)Yl, overflow);
   }
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
