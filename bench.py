@@ -71,6 +71,8 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--m", type=int, default=0, help="override rows (smaller runs)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-spca", action="store_true")
+    ap.add_argument("--spca-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -166,6 +168,27 @@ def main():
                      "frac": round(achieved / peak, 4), "traffic": None,
                      "algorithmic": f"2 m n k = {flops_sketch:.4g} flop per launch"},
     }
+    if not args.no_spca:
+        # the non-lazy baseline on the same X: Algorithm 1 with the GPU
+        # tall-skinny Householder QR (two passes over X)
+        try:
+            lib.spca_fit(X, k, cfg["kind"], cfg["omega_seed"], sparse_p=cfg.get("p", 64))
+            torch.cuda.synchronize()
+            sp = []
+            for _ in range(args.spca_steps):
+                lib.spca_fit(X, k, cfg["kind"], cfg["omega_seed"], timing=True, sparse_p=cfg.get("p", 64))
+                sp.append(lib.last_timings())
+            sp_ms = sum(t["total_ms"] for t in sp) / len(sp)
+            out["spca"] = {
+                "fit_ms": round(sp_ms, 4),
+                "fit_x_stream_GBs": round(xbytes / (sp_ms * 1e-3) / 1e9, 3),
+                "phases_ms": {key: round(sum(t[key + "_ms"] for t in sp) / len(sp), 4)
+                              for key in ("omega", "sketch", "qr", "pass2", "reduce", "small")},
+                "lazy_fit_speedup": round(sp_ms / fit_ms, 3),
+            }
+            log(f"spca_fit {sp_ms:.3f} ms vs lazy fit {fit_ms:.3f} ms")
+        except lib.LspcaError as e:
+            out["spca"] = {"error": str(e)}
     if not args.no_cpu:
         log("cpu baseline (oracle on a row sample)")
         out["cpu_baseline"] = cpu_baseline(cfg, X)

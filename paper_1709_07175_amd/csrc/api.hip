@@ -468,10 +468,69 @@ int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t n, int64_
 int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, int32_t k,
              lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts, double *V,
              double *sigma) {
-  (void)X; (void)xdt; (void)m; (void)n; (void)ldx; (void)k; (void)kind; (void)seed; (void)opts;
-  (void)V; (void)sigma;
-  set_error("spca_fit: not built in this version");
-  return LSPCA_ENOTSUP;
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  LSPCA_TRY(check_pass_args(X, xdt, m, n, ldx, k, kind, o));
+  if (!V || !sigma) { set_error("V and sigma must not be NULL"); return LSPCA_EINVAL; }
+  if (k > m) { set_error("k must satisfy k <= min(m, n) (k=%d m=%lld)", k, (long long)m); return LSPCA_EINVAL; }
+  const lspca_dtype ydt = xdt == LSPCA_F64 ? LSPCA_F64 : LSPCA_F32;
+  if (k > (ydt == LSPCA_F64 ? 128 : 256)) {
+    set_error("spca_fit: k = %d above the QR block height (%d)", k, ydt == LSPCA_F64 ? 128 : 256);
+    return LSPCA_ENOTSUP;
+  }
+  const bool h16 = is16(xdt);
+  const bool refine = o.refine != 0;
+  const size_t xs = dtype_size(xdt), ys = dtype_size(ydt);
+  const int sf = tn_pick_splits(m, k, (int)n);
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  const size_t need = ws_bytes<char>(xs * (size_t)n * k) + ws_bytes<char>(ys * (size_t)m * k) +
+                      (h16 ? 2 * ws_bytes<uint16_t>((size_t)m * k) : ws_bytes<char>(ys * (size_t)m * k)) +
+                      tsqr_workspace_bytes(m, k, ydt) + ws_bytes<char>(ys * tn_partial_elems(k, (int)n, sf)) +
+                      ws_bytes<double>((size_t)k * n) + factor_bytes(n, k);
+  LSPCA_TRY(L.st->ws.ensure(need));
+  Workspace &ws = L.st->ws;
+  hipStream_t s = o.stream;
+  void *OmT = ws.take<char>(xs * (size_t)n * k);
+  void *Y = ws.take<char>(ys * (size_t)m * k);
+  void *Q = nullptr;
+  uint16_t *Qh = nullptr, *Ql = nullptr;
+  if (h16) {
+    Qh = ws.take<uint16_t>((size_t)m * k);
+    Ql = ws.take<uint16_t>((size_t)m * k);
+  } else {
+    Q = ws.take<char>(ys * (size_t)m * k);
+  }
+  void *PF = ws.take<char>(ys * tn_partial_elems(k, (int)n, sf));
+  double *F = ws.take<double>((size_t)k * n);
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, s);
+  // Algorithm 1 step 1: U = X Omega, stored m x k (row-major)
+  LSPCA_TRY(launch_omega(n, k, kind, seed, o.p, xdt, OmT, 1, n, s));
+  tm.mark(PH_OMEGA);
+  if (h16)
+    LSPCA_TRY(launch_nt16(xdt, X, ldx, OmT, nullptr, n, (float *)Y, k, m, k, (int)n, nullptr, nullptr,
+                          nullptr, 0, s));
+  else
+    LSPCA_TRY(launch_nt(xdt, X, ldx, OmT, n, Y, k, m, k, (int)n, s));
+  tm.mark(PH_SKETCH);
+  // step 2: Q, R = qr(U)
+  LSPCA_TRY(tsqr(Y, ydt, m, k, ws, h16 ? 1 : 0, xdt, Q, Qh, Ql, h16 ? m : k, s));
+  tm.mark(PH_QR);
+  // step 3: F = Q^T X (second pass over X)
+  if (h16)
+    LSPCA_TRY(launch_tn16(xdt, Qh, refine ? Ql : nullptr, m, X, ldx, (float *)PF, m, k, (int)n, sf, s));
+  else
+    LSPCA_TRY(launch_tn(xdt, Q, k, X, ldx, PF, m, k, (int)n, sf, s));
+  tm.mark(PH_PASS2);
+  LSPCA_TRY(launch_reduce_add(ydt, PF, sf, (int64_t)k * n, F, 0, s));
+  tm.mark(PH_REDUCE);
+  // step 4: truncated SVD of F gives V^s, Sigma^s
+  int rank_flag = 0;
+  LSPCA_TRY(small_factor(F, nullptr, k, n, V, sigma, nullptr, ws, s, &rank_flag));
+  tm.mark(PH_SMALL);
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
 }
 
 }  // extern "C"
