@@ -484,7 +484,8 @@ int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, 
   const int sf = tn_pick_splits(m, k, (int)n);
   Locked L;
   LSPCA_TRY(lock_device(L));
-  const size_t need = ws_bytes<char>(xs * (size_t)n * k) + ws_bytes<char>(ys * (size_t)m * k) +
+  const int64_t ldt = tsqr_ld(m, ydt);
+  const size_t need = ws_bytes<char>(xs * (size_t)n * k) + ws_bytes<char>(ys * (size_t)ldt * k) +
                       (h16 ? 2 * ws_bytes<uint16_t>((size_t)m * k) : ws_bytes<char>(ys * (size_t)m * k)) +
                       tsqr_workspace_bytes(m, k, ydt) + ws_bytes<char>(ys * tn_partial_elems(k, (int)n, sf)) +
                       ws_bytes<double>((size_t)k * n) + factor_bytes(n, k);
@@ -492,7 +493,7 @@ int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, 
   Workspace &ws = L.st->ws;
   hipStream_t s = o.stream;
   void *OmT = ws.take<char>(xs * (size_t)n * k);
-  void *Y = ws.take<char>(ys * (size_t)m * k);
+  void *Y = ws.take<char>(ys * (size_t)ldt * k);   // U^T: column j at Y + j * ldt
   void *Q = nullptr;
   uint16_t *Qh = nullptr, *Ql = nullptr;
   if (h16) {
@@ -505,17 +506,23 @@ int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, 
   double *F = ws.take<double>((size_t)k * n);
   PhaseTimer tm;
   tm.begin(o.timing != 0, s);
-  // Algorithm 1 step 1: U = X Omega, stored m x k (row-major)
+  // Algorithm 1 step 1: U = X Omega, stored transposed (U^T = Omega^T X^T)
   LSPCA_TRY(launch_omega(n, k, kind, seed, o.p, xdt, OmT, 1, n, s));
   tm.mark(PH_OMEGA);
-  if (h16)
-    LSPCA_TRY(launch_nt16(xdt, X, ldx, OmT, nullptr, n, (float *)Y, k, m, k, (int)n, nullptr, nullptr,
-                          nullptr, 0, s));
-  else
-    LSPCA_TRY(launch_nt(xdt, X, ldx, OmT, n, Y, k, m, k, (int)n, s));
+  if (h16) {
+    LSPCA_TRY(launch_nt16(xdt, X, ldx, OmT, nullptr, n, (float *)Y, ldt, m, k, (int)n, nullptr, nullptr,
+                          nullptr, 1, s));
+  } else {
+    const int64_t stripe = 4 << 20;               // rows per launch (grid limit on the row tiles)
+    for (int64_t r0 = 0; r0 < m; r0 += stripe) {
+      const int64_t rows = m - r0 < stripe ? m - r0 : stripe;
+      LSPCA_TRY(launch_nt(xdt, OmT, n, (const char *)X + xs * (size_t)r0 * ldx, ldx,
+                          (char *)Y + ys * (size_t)r0, ldt, k, (int)rows, (int)n, s));
+    }
+  }
   tm.mark(PH_SKETCH);
   // step 2: Q, R = qr(U)
-  LSPCA_TRY(tsqr(Y, ydt, m, k, ws, h16 ? 1 : 0, xdt, Q, Qh, Ql, h16 ? m : k, s));
+  LSPCA_TRY(tsqr(Y, ydt, m, ldt, k, ws, h16 ? 1 : 0, xdt, Q, Qh, Ql, h16 ? m : k, s));
   tm.mark(PH_QR);
   // step 3: F = Q^T X (second pass over X)
   if (h16)

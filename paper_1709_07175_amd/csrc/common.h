@@ -181,9 +181,11 @@ int launch_transpose_f64(const double *src, int64_t rows, int cols,
 int launch_convert_vt(const double *V, int64_t n, int k, lspca_dtype dt,
                       void *hi, void *lo, hipStream_t s);
 
-// Tall-skinny Householder QR (tsqr.hip).
+// Tall-skinny Householder QR (tsqr.hip). U enters transposed, column c at
+// Ut + c * ldu with ldu >= tsqr_ld(m, ydt).
+int64_t tsqr_ld(int64_t m, lspca_dtype ydt);
 size_t tsqr_workspace_bytes(int64_t m, int k, lspca_dtype ydt);
-int tsqr(void *U, lspca_dtype ydt, int64_t m, int k, Workspace &ws, int out_mode,
+int tsqr(void *Ut, lspca_dtype ydt, int64_t m, int64_t ldu, int k, Workspace &ws, int out_mode,
          lspca_dtype dt16, void *Q, void *Qh, void *Ql, int64_t ldq, hipStream_t s);
 
 size_t dtype_size(lspca_dtype dt);

@@ -2,20 +2,28 @@
 // explicit thin Q: the "Q, R = qr(U)" of Algorithm 1 (SPCA, the non-lazy
 // baseline).
 //
-// Leaves: workgroup b factors rows [b*BR, (b+1)*BR) of U (BR = 256 for FP32,
-// 128 for FP64) by k Householder reflectors H_j = I - tau_j v_j v_j^T
-// (LAPACK's convention: v_j[j] = 1, H_j x = beta e_j). Four adjacent lanes
-// (a quad) own one column, each holding a quarter of its BR entries in
-// registers; reflector j is built by the quad that owns column j, broadcast
-// through LDS (double buffered: one barrier per reflector) and applied by
-// every quad c > j.
-// The block is stored back in compact form (R above, v below the
-// diagonal); its k x k R goes to level 0 of a binary tree.
+// U arrives transposed: column c of U is contiguous at U + c * ldu, with ldu
+// a multiple of the block height BR (256 rows for FP32, 128 for FP64).
+// Leaves: workgroup b factors rows [b*BR, (b+1)*BR) by k Householder
+// reflectors H_j = I - tau_j v_j v_j^T (LAPACK's convention: v_j[j] = 1,
+// H_j x = beta e_j); its k x k R goes to level 0 of a binary tree.
 // Tree nodes: [R_a; R_b] -> R by reflectors whose top part is e_j and whose
-// bottom part v_b has rows 0..j only (R_b upper triangular).
+// bottom part has rows 0..j only (R_b upper triangular).
 // Q: top down. The root starts from C = I_k; a node maps its C to
 // (C_a, C_b) = top and bottom halves of H_0 ... H_{k-1} [C; 0]; a leaf forms
 // its BR x k rows of Q = H_0 ... H_{k-1} [C; 0].
+//
+// Register layout (1024-thread workgroups, 16 wavefronts): lane l of wave w
+// holds column c = w + 16 (l / 16) + 64 q for q < NQ and rows
+// r = (l % 16) + 16 i for i < NI, so the 16 lanes of one DPP row hold one
+// whole column and a column sum takes four DPP steps. Columns are dealt to
+// the waves cyclically, so every wave keeps work until the last reflectors.
+// Reflectors, R and C are stored in the matching "slice" order: column c,
+// then lane row l % 16, then i (one lane's NI entries are contiguous); a
+// column occupies BR entries whatever k is.
+// Reflector j touches rows >= j (leaf) or <= j (node) and columns > j only;
+// with 16 reflectors per block both bounds are static, so finished rows and
+// columns cost nothing.
 #include "common.h"
 
 #include <vector>
@@ -23,10 +31,7 @@
 namespace lspca {
 
 typedef int i32x2 __attribute__((ext_vector_type(2)));
-typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-// Sum of a value over the four lanes of a quad (lanes 4c .. 4c+3): DPP
-// quad_perm xor 1, then xor 2.
 template <int CTRL> __device__ inline float dpp_f(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
@@ -36,15 +41,53 @@ template <int CTRL> __device__ inline double dpp_f(double v) {
   p.y = __builtin_amdgcn_update_dpp(0, p.y, CTRL, 0xF, 0xF, false);
   return __builtin_bit_cast(double, p);
 }
-template <typename T> __device__ inline T quad_sum(T v) {
+// Sum over a DPP row of 16 lanes, received by all 16 (bitwise equal, since
+// each step adds the same two values in either order): quad_perm xor 1 and
+// xor 2, then row_half_mirror and row_mirror.
+template <typename T> __device__ inline T sum16(T v) {
   v += dpp_f<0xB1>(v);
   v += dpp_f<0x4E>(v);
+  v += dpp_f<0x141>(v);
+  v += dpp_f<0x140>(v);
   return v;
 }
 
 template <typename T> struct TsqrCfg;
-template <> struct TsqrCfg<float> { static constexpr int BR = 256; };
-template <> struct TsqrCfg<double> { static constexpr int BR = 128; };
+template <> struct TsqrCfg<float> {
+  static constexpr int BR = 256, NI = 16, NQ = 4;
+  typedef float vec __attribute__((ext_vector_type(4)));
+};
+template <> struct TsqrCfg<double> {
+  static constexpr int BR = 128, NI = 8, NQ = 2;
+  typedef double vec __attribute__((ext_vector_type(2)));
+};
+// LDS stride of one lane slice: NI entries plus 16 bytes, so that the 16
+// slices of a DPP row start on distinct bank groups for 16-byte reads.
+template <typename T> constexpr int lds_stride() { return TsqrCfg<T>::NI + 16 / (int)sizeof(T); }
+// Slice position of row r within a column.
+template <typename T> __device__ inline int spos(int r) { return (r & 15) * TsqrCfg<T>::NI + (r >> 4); }
+
+template <typename T> __device__ inline void put_slice(T *dst, const T (&v)[TsqrCfg<T>::NI]) {
+  using V = typename TsqrCfg<T>::vec;
+  constexpr int W = 16 / sizeof(T);
+#pragma unroll
+  for (int i = 0; i < TsqrCfg<T>::NI; i += W) {
+    V x;
+#pragma unroll
+    for (int e = 0; e < W; ++e) x[e] = v[i + e];
+    *reinterpret_cast<V *>(dst + i) = x;
+  }
+}
+template <typename T> __device__ inline void get_slice(const T *src, T (&v)[TsqrCfg<T>::NI]) {
+  using V = typename TsqrCfg<T>::vec;
+  constexpr int W = 16 / sizeof(T);
+#pragma unroll
+  for (int i = 0; i < TsqrCfg<T>::NI; i += W) {
+    const V x = *reinterpret_cast<const V *>(src + i);
+#pragma unroll
+    for (int e = 0; e < W; ++e) v[i + e] = x[e];
+  }
+}
 
 // Householder reflector for x = (x0, rest) with ||rest||^2 = s (LAPACK
 // dlarfg): beta = -sign(x0) ||x||, tau = (beta - x0) / beta, the rest of v
@@ -64,405 +107,517 @@ __device__ inline void householder(T x0, T s, T &beta, T &tau, T &scale) {
 }
 
 // ------------------------------------------------------------------ leaf --
-// Factor one block of U in place (compact form); write tau (k) and the
-// block's R (k x k, zeros below the diagonal).
+// Factor block b of U. Reflector j is built by the 16 lanes that hold column
+// j and written three ways: v_j (slice order) over column j of the block in
+// U, into the LDS buffer for the other columns (double buffered: one barrier
+// per reflector), and R's column j (slice order, zeros below the diagonal)
+// to R_out[b].
 template <typename T>
-__global__ __launch_bounds__(1024) void k_tsqr_leaf(T *__restrict__ U, int64_t m, int k, int64_t ldu,
-                                                   T *__restrict__ tau_out, T *__restrict__ R_out) {
-  constexpr int BR = TsqrCfg<T>::BR, H = BR / 4;
-  __shared__ T vl[2][BR];
+__global__ __launch_bounds__(1024) void k_tsqr_leaf(T *__restrict__ U, int64_t ldu, int64_t m, int k,
+                                                    T *__restrict__ tau_out, T *__restrict__ R_out) {
+  constexpr int BR = TsqrCfg<T>::BR, NI = TsqrCfg<T>::NI, NQ = TsqrCfg<T>::NQ, SP = lds_stride<T>();
+  __shared__ __align__(16) T vl[2][16 * SP];
   __shared__ T tl[2];
-  const int tid = threadIdx.x, c = tid >> 2, h = tid & 3;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, rg = lane & 15, cg = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * BR;
-  const bool active = c < k;
-  T a[H];
-  {
-    // rows row0 + h*H + i of column c; a full block loads without guards
-    const T *p = U + (row0 + h * H) * ldu + c;
-    const int64_t left = m - (row0 + h * H);
-    if (active && left >= H) {
+  const int rows_here = (int)(m - row0 < BR ? m - row0 : BR);
+  T a[NQ][NI];
 #pragma unroll
-      for (int i = 0; i < H; ++i, p += ldu) a[i] = *p;
-    } else {
+  for (int q = 0; q < NQ; ++q) {
+    const int c = w + 16 * cg + 64 * q;
+    const T *src = U + (int64_t)(c < k ? c : 0) * ldu + row0 + rg;
 #pragma unroll
-      for (int i = 0; i < H; ++i, p += ldu) a[i] = (active && i < left) ? *p : (T)0;
-    }
+    for (int i = 0; i < NI; ++i) a[q][i] = (c < k && rg + 16 * i < rows_here) ? src[16 * i] : (T)0;
   }
-  T mytau = 0;
-  for (int j = 0; j < k; ++j) {
-    const int buf = j & 1;
-    if (c == j) {
-      T s = 0, x0 = 0;
 #pragma unroll
-      for (int i = 0; i < H; ++i) {
-        const int row = h * H + i;
-        s += row > j ? a[i] * a[i] : (T)0;
-        x0 += row == j ? a[i] : (T)0;
-      }
-      s = quad_sum(s);
-      x0 = quad_sum(x0);
-      T beta, tau, scale;
-      householder(x0, s, beta, tau, scale);
-      mytau = tau;
+  for (int bi = 0; bi < 4 * NQ; ++bi) {           // reflectors 16 bi .. 16 bi + 15
+    const int q = bi / 4, jb = bi % 4;
+    if (16 * bi >= k) break;
+    for (int j16 = 0; j16 < 16; ++j16) {
+      const int j = 16 * bi + j16, buf = j & 1;
+      if (j >= k) break;
+      if (w == j16 && cg == jb) {                 // this DPP row holds column j
+        T s = 0, x0 = 0;
 #pragma unroll
-      for (int i = 0; i < H; ++i) {
-        const int row = h * H + i;
-        if (row > j) a[i] *= scale;
-        else if (row == j) a[i] = beta;
-        vl[buf][row] = row > j ? a[i] : (row == j ? (T)1 : (T)0);
+        for (int i = bi; i < NI; ++i) {
+          const int r = rg + 16 * i;
+          const T x = a[q][i];
+          s += r > j ? x * x : (T)0;
+          x0 += r == j ? x : (T)0;
+        }
+        s = sum16(s);
+        x0 = sum16(x0);
+        T beta, tau, scale;
+        householder(x0, s, beta, tau, scale);
+        T v[NI], rc[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          const int r = rg + 16 * i;
+          const T x = a[q][i];
+          v[i] = i < bi ? (T)0 : (r > j ? x * scale : (r == j ? (T)1 : (T)0));
+          rc[i] = r < j ? x : (r == j ? beta : (T)0);
+        }
+        put_slice<T>(vl[buf] + rg * SP, v);
+        put_slice<T>(U + (int64_t)j * ldu + row0 + rg * NI, v);
+        put_slice<T>(R_out + ((int64_t)blockIdx.x * k + j) * BR + rg * NI, rc);
+        if (rg == 0) {
+          tl[buf] = tau;
+          tau_out[(int64_t)blockIdx.x * k + j] = tau;
+        }
       }
-      if (h == 0) tl[buf] = tau;
-    }
-    __syncthreads();
-    if (active && c > j) {
+      __syncthreads();
       const T tau = tl[buf];
-      T d = 0;
+      T v[NI];
+      get_slice<T>(vl[buf] + rg * SP, v);
 #pragma unroll
-      for (int i = 0; i < H; ++i) d += vl[buf][h * H + i] * a[i];
-      d = quad_sum(d) * tau;
-      asm volatile("" ::: "memory");   // re-read v from LDS: keep it out of registers
+      for (int qq = q; qq < NQ; ++qq) {
+        const int c = w + 16 * cg + 64 * qq;
+        if (w + 64 * qq + 48 > j) {               // wave-uniform: a column right of j
+          T d0 = 0, d1 = 0;
 #pragma unroll
-      for (int i = 0; i < H; ++i) a[i] -= d * vl[buf][h * H + i];
+          for (int i = bi; i < NI; ++i) {
+            if ((i - bi) & 1) d1 += v[i] * a[qq][i];
+            else d0 += v[i] * a[qq][i];
+          }
+          T d = sum16(d0 + d1);
+          d = (c > j && c < k) ? d * tau : (T)0;
+#pragma unroll
+          for (int i = bi; i < NI; ++i) a[qq][i] -= d * v[i];
+        }
+      }
     }
   }
-  if (!active) return;
-  {
-    T *p = U + (row0 + h * H) * ldu + c;
-    const int64_t left = m - (row0 + h * H);
-    if (left >= H) {
-#pragma unroll
-      for (int i = 0; i < H; ++i, p += ldu) *p = a[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < H; ++i, p += ldu)
-        if (i < left) *p = a[i];
-    }
-    T *rp = R_out + (int64_t)blockIdx.x * k * k + (int64_t)(h * H) * k + c;
-#pragma unroll
-    for (int i = 0; i < H; ++i, rp += k) {
-      const int row = h * H + i;
-      if (row < k) *rp = row <= c ? a[i] : (T)0;
-    }
-  }
-  if (h == 0) tau_out[(int64_t)blockIdx.x * k + c] = mytau;
 }
 
 // ----------------------------------------------------------------- nodes --
-// Node p of a level combines R_in[2p] (top) and R_in[2p+1] (bottom) into
-// R_out[p]; writes the bottom parts of its reflectors to Vb[p] (column j:
-// rows 0..j) and tau[p]. A node without a second child copies R_in[2p].
+// Node p of a level combines R_in[2p] (top, R_a) and R_in[2p+1] (bottom,
+// R_b) into R_out[p]; writes the bottom parts of its reflectors to Vb[p]
+// (slice order, rows 0..j, zeros elsewhere) and tau[p]. Reflector j changes
+// only row j of R_a, so each lane reads its columns' entries of R_a's row j
+// one step ahead and writes the final row j of R_out. A node without a
+// second child copies R_in[2p].
 template <typename T>
 __global__ __launch_bounds__(1024) void k_tsqr_node(const T *__restrict__ R_in, int nin, int k,
-                                                   T *__restrict__ R_out, T *__restrict__ Vb,
-                                                   T *__restrict__ tau_out) {
-  constexpr int BR = TsqrCfg<T>::BR, H = BR / 4;
-  __shared__ T vl[2][BR];
+                                                    T *__restrict__ R_out, T *__restrict__ Vb,
+                                                    T *__restrict__ tau_out) {
+  constexpr int BR = TsqrCfg<T>::BR, NI = TsqrCfg<T>::NI, NQ = TsqrCfg<T>::NQ, SP = lds_stride<T>();
+  __shared__ __align__(16) T vl[2][16 * SP];
   __shared__ T tl[2];
-  const int tid = threadIdx.x, c = tid >> 2, h = tid & 3;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, rg = lane & 15, cg = lane >> 4;
   const int p = blockIdx.x;
-  const int64_t kk = (int64_t)k * k;
-  const T *Ra = R_in + (2 * (int64_t)p) * kk;
-  T *Rn = R_out + (int64_t)p * kk;
-  const bool active = c < k;
+  const int64_t kb = (int64_t)k * BR;
+  const T *Ra = R_in + 2 * (int64_t)p * kb;
+  T *Rn = R_out + (int64_t)p * kb;
   if (2 * p + 1 >= nin) {                         // single child: pass R through
-    for (int64_t e = tid; e < kk; e += blockDim.x) Rn[e] = Ra[e];
-    for (int e = tid; e < k; e += blockDim.x) tau_out[(int64_t)p * k + e] = 0;
+    for (int64_t e = threadIdx.x; e < kb; e += blockDim.x) Rn[e] = Ra[e];
+    for (int e = threadIdx.x; e < k; e += blockDim.x) tau_out[(int64_t)p * k + e] = 0;
     return;
   }
-  const T *Rb = Ra + kk;
-  for (int64_t e = tid; e < kk; e += blockDim.x) Rn[e] = Ra[e];
-  T b[H];
-  {
-    const T *p = Rb + (int64_t)(h * H) * k + c;
+  const T *Rb = Ra + kb;
+  T *V = Vb + (int64_t)p * kb;
+  T b[NQ][NI], ra_next[NQ];
 #pragma unroll
-    for (int i = 0; i < H; ++i, p += k) b[i] = (active && h * H + i < k) ? *p : (T)0;
+  for (int q = 0; q < NQ; ++q) {
+    const int c = w + 16 * cg + 64 * q;
+    T t[NI];
+    get_slice<T>(Rb + (int64_t)(c < k ? c : 0) * BR + rg * NI, t);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) b[q][i] = (c < k && rg + 16 * i < k) ? t[i] : (T)0;
+    ra_next[q] = c < k ? Ra[(int64_t)c * BR] : (T)0;   // row 0 sits first in every slice order
   }
-  __syncthreads();                                // Rn complete
-  for (int j = 0; j < k; ++j) {
-    const int buf = j & 1;
-    if (c == j) {
-      T s = 0;
 #pragma unroll
-      for (int i = 0; i < H; ++i) {
-        const int row = h * H + i;
-        s += row <= j ? b[i] * b[i] : (T)0;
-      }
-      s = quad_sum(s);
-      const T x0 = Rn[(int64_t)j * k + j];
-      T beta, tau, scale;
-      householder(x0, s, beta, tau, scale);
+  for (int bi = 0; bi < 4 * NQ; ++bi) {
+    const int q = bi / 4, jb = bi % 4;
+    if (16 * bi >= k) break;
+    for (int j16 = 0; j16 < 16; ++j16) {
+      const int j = 16 * bi + j16, buf = j & 1;
+      if (j >= k) break;
+      T ra[NQ];
 #pragma unroll
-      for (int i = 0; i < H; ++i) {
-        const int row = h * H + i;
-        const T v = row <= j ? b[i] * scale : (T)0;
-        vl[buf][row] = v;
-        b[i] = 0;
+      for (int qq = 0; qq < NQ; ++qq) {
+        ra[qq] = 0;
+        if (qq < q) continue;
+        const int c = w + 16 * cg + 64 * qq;
+        ra[qq] = ra_next[qq];
+        if (c < k && j + 1 < k) ra_next[qq] = Ra[(int64_t)c * BR + spos<T>(j + 1)];
       }
-      {
-        T *vp = Vb + (int64_t)p * kk + (int64_t)(h * H) * k + j;
+      if (w == j16 && cg == jb) {
+        T s = 0;
 #pragma unroll
-        for (int i = 0; i < H; ++i, vp += k)
-          if (h * H + i < k) *vp = vl[buf][h * H + i];
+        for (int i = 0; i <= bi; ++i) {
+          const T x = b[q][i];
+          s += rg + 16 * i <= j ? x * x : (T)0;
+        }
+        s = sum16(s);
+        T beta, tau, scale;
+        householder(ra[q], s, beta, tau, scale);
+        T v[NI];
+#pragma unroll
+        for (int i = 0; i < NI; ++i) v[i] = (i <= bi && rg + 16 * i <= j) ? b[q][i] * scale : (T)0;
+        put_slice<T>(vl[buf] + rg * SP, v);
+        put_slice<T>(V + (int64_t)j * BR + rg * NI, v);
+        if (rg == 0) {
+          tl[buf] = tau;
+          tau_out[(int64_t)p * k + j] = tau;
+          Rn[(int64_t)j * BR + spos<T>(j)] = beta;
+        }
       }
-      if (h == 0) {
-        tl[buf] = tau;
-        tau_out[(int64_t)p * k + j] = tau;
-        Rn[(int64_t)j * k + j] = beta;
-      }
-    }
-    __syncthreads();
-    if (active && c > j) {
+      __syncthreads();
       const T tau = tl[buf];
-      T d = 0;
+      T v[NI];
+      get_slice<T>(vl[buf] + rg * SP, v);
 #pragma unroll
-      for (int i = 0; i < H; ++i) d += vl[buf][h * H + i] * b[i];
-      d = quad_sum(d);
-      const T w = (Rn[(int64_t)j * k + c] + d) * tau;
-      asm volatile("" ::: "memory");
+      for (int qq = 0; qq < NQ; ++qq) {
+        const int c = w + 16 * cg + 64 * qq;
+        if (qq < q) {                             // columns left of j: zero below the diagonal
+          if (rg == 0 && c < k) Rn[(int64_t)c * BR + spos<T>(j)] = (T)0;
+          continue;
+        }
+        T wv = 0;
+        if (w + 64 * qq + 48 > j) {
+          T d0 = 0, d1 = 0;
 #pragma unroll
-      for (int i = 0; i < H; ++i) b[i] -= w * vl[buf][h * H + i];
-      if (h == 0) Rn[(int64_t)j * k + c] -= w;
+          for (int i = 0; i <= bi; ++i) {
+            if (i & 1) d1 += v[i] * b[qq][i];
+            else d0 += v[i] * b[qq][i];
+          }
+          const T d = sum16(d0 + d1);
+          wv = (c > j && c < k) ? (ra[qq] + d) * tau : (T)0;
+#pragma unroll
+          for (int i = 0; i <= bi; ++i) b[qq][i] -= wv * v[i];
+        }
+        if (rg == 0 && c < k && c != j) Rn[(int64_t)c * BR + spos<T>(j)] = c > j ? ra[qq] - wv : (T)0;
+      }
     }
   }
 }
+
+// Staging of 16 stored reflectors (16 x BR entries, slice order) into LDS:
+// thread t moves one 16-byte vector.
+template <typename T> struct Stage16 {
+  using V = typename TsqrCfg<T>::vec;
+  static constexpr int W = 16 / sizeof(T), BR = TsqrCfg<T>::BR, NI = TsqrCfg<T>::NI, SP = lds_stride<T>();
+  int jj, src, dst;
+  __device__ Stage16() {
+    const int e = threadIdx.x * W;
+    jj = e / BR;
+    src = e % BR;
+    dst = jj * 16 * SP + (src / NI) * SP + src % NI;
+  }
+  // reflector 16 blk + jj, stored at base + j * ld
+  __device__ V fetch(const T *base, int64_t ld, int blk, int k) const {
+    const int j = 16 * blk + jj;
+    V x = {};
+    if (j < k) x = *reinterpret_cast<const V *>(base + (int64_t)j * ld + src);
+    return x;
+  }
+};
 
 // Q formation at a node: C_in[p] (k x k) -> C_out[2p] = top, C_out[2p+1] =
-// bottom halves of H_0 ... H_{k-1} [C; 0]. Single child: C passes through.
+// bottom halves of H_0 ... H_{k-1} [C; 0]. Reflector j changes only row j
+// of the top half, so each lane reads its columns' entries of row j of C_in
+// when the descending sweep reaches it (one step ahead) and writes the final
+// row j of C_out[2p]. Single child: C passes through. Reflectors come from
+// Vb[p] through LDS, 16 at a time, the next 16 loaded during the current.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_tsqr_node_q(const T *__restrict__ C_in, int nchild, int k,
-                                                     const T *__restrict__ Vb,
-                                                     const T *__restrict__ tau_in,
-                                                     T *__restrict__ C_out) {
-  constexpr int BR = TsqrCfg<T>::BR, H = BR / 4;
-  constexpr int CH = 16;                          // reflectors per LDS chunk
-  __shared__ T vl[CH][BR];
-  __shared__ T tl[CH];
-  const int tid = threadIdx.x, c = tid >> 2, h = tid & 3;
+                                                      const T *__restrict__ Vb,
+                                                      const T *__restrict__ tau_in,
+                                                      T *__restrict__ C_out) {
+  constexpr int BR = TsqrCfg<T>::BR, NI = TsqrCfg<T>::NI, NQ = TsqrCfg<T>::NQ, SP = lds_stride<T>();
+  using Vec = typename TsqrCfg<T>::vec;
+  __shared__ __align__(16) T vs[2][16 * 16 * SP];
+  __shared__ T ts[2][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, rg = lane & 15, cg = lane >> 4;
   const int p = blockIdx.x;
-  const int64_t kk = (int64_t)k * k;
-  const T *Cn = C_in + (int64_t)p * kk;
-  T *Ca = C_out + (2 * (int64_t)p) * kk;
-  for (int64_t e = tid; e < kk; e += blockDim.x) Ca[e] = Cn[e];
-  if (2 * p + 1 >= nchild) return;
-  T *Cb = Ca + kk;
-  const bool active = c < k;
-  T b[H];
+  const int64_t kb = (int64_t)k * BR;
+  const T *Cn = C_in + (int64_t)p * kb;
+  T *Ca = C_out + 2 * (int64_t)p * kb;
+  if (2 * p + 1 >= nchild) {
+    for (int64_t e = threadIdx.x; e < kb; e += blockDim.x) Ca[e] = Cn[e];
+    return;
+  }
+  T *Cb = Ca + kb;
+  const T *V = Vb + (int64_t)p * kb;
+  const T *tau = tau_in + (int64_t)p * k;
+  const Stage16<T> st;
+  const int nblk = (k + 15) / 16;
+  Vec pre = st.fetch(V, BR, nblk - 1, k);
+  T tpre = (threadIdx.x < 16 && 16 * (nblk - 1) + (int)threadIdx.x < k) ? tau[16 * (nblk - 1) + threadIdx.x] : (T)0;
+  T cb[NQ][NI], cn_next[NQ];
 #pragma unroll
-  for (int i = 0; i < H; ++i) b[i] = 0;
-  __syncthreads();                                // Ca complete
-  for (int j1 = k; j1 > 0; j1 -= CH) {
-    const int j0 = j1 - CH > 0 ? j1 - CH : 0;
+  for (int q = 0; q < NQ; ++q) {
+    const int c = w + 16 * cg + 64 * q;
+#pragma unroll
+    for (int i = 0; i < NI; ++i) cb[q][i] = 0;
+    cn_next[q] = c < k ? Cn[(int64_t)c * BR + spos<T>(k - 1)] : (T)0;
+  }
+#pragma unroll
+  for (int bi = 4 * NQ - 1; bi >= 0; --bi) {
+    if (bi >= nblk) continue;
+    const int buf = bi & 1;
+    *reinterpret_cast<Vec *>(&vs[buf][st.dst]) = pre;
+    if (threadIdx.x < 16) ts[buf][threadIdx.x] = tpre;
     __syncthreads();
-    for (int e = tid; e < (j1 - j0) * BR; e += blockDim.x) {
-      const int jj = e / BR, row = e % BR, j = j0 + jj;
-      vl[jj][row] = (row <= j && row < k) ? Vb[(int64_t)p * kk + (int64_t)row * k + j] : (T)0;
+    if (bi > 0) {
+      pre = st.fetch(V, BR, bi - 1, k);
+      tpre = threadIdx.x < 16 ? tau[16 * (bi - 1) + threadIdx.x] : (T)0;
     }
-    for (int e = tid; e < j1 - j0; e += blockDim.x) tl[e] = tau_in[(int64_t)p * k + j0 + e];
-    __syncthreads();
-    for (int j = j1 - 1; j >= j0; --j) {
-      const int jj = j - j0;
-      if (active) {
-        T d = 0;
+    for (int j16 = 15; j16 >= 0; --j16) {
+      const int j = 16 * bi + j16;
+      if (j >= k) continue;
+      T cn[NQ];
 #pragma unroll
-        for (int i = 0; i < H; ++i) d += vl[jj][h * H + i] * b[i];
-        d = quad_sum(d);
-        const T w = (Ca[(int64_t)j * k + c] + d) * tl[jj];
-        asm volatile("" ::: "memory");
-#pragma unroll
-        for (int i = 0; i < H; ++i) b[i] -= w * vl[jj][h * H + i];
-        if (h == 0) Ca[(int64_t)j * k + c] -= w;
+      for (int qq = 0; qq < NQ; ++qq) {
+        const int c = w + 16 * cg + 64 * qq;
+        cn[qq] = cn_next[qq];
+        if (c < k && j > 0) cn_next[qq] = Cn[(int64_t)c * BR + spos<T>(j - 1)];
       }
-      // row j of Ca is read and written by quad c only; no barrier needed
+      const T t = ts[buf][j16];
+      T v[NI];
+      get_slice<T>(&vs[buf][j16 * 16 * SP + rg * SP], v);
+#pragma unroll
+      for (int qq = 0; qq < NQ; ++qq) {
+        const int c = w + 16 * cg + 64 * qq;
+        if (w + 64 * qq < k) {                    // wave-uniform
+          T d0 = 0, d1 = 0;
+#pragma unroll
+          for (int i = 0; i <= bi; ++i) {
+            if (i & 1) d1 += v[i] * cb[qq][i];
+            else d0 += v[i] * cb[qq][i];
+          }
+          const T d = sum16(d0 + d1);
+          const T wv = (cn[qq] + d) * t;
+#pragma unroll
+          for (int i = 0; i <= bi; ++i) cb[qq][i] -= wv * v[i];
+          if (rg == 0 && c < k) Ca[(int64_t)c * BR + spos<T>(j)] = cn[qq] - wv;
+        }
+      }
     }
   }
-  if (!active) return;
 #pragma unroll
-  for (int i = 0; i < H; ++i) {
-    const int row = h * H + i;
-    if (row < k) Cb[(int64_t)row * k + c] = b[i];
+  for (int q = 0; q < NQ; ++q) {
+    const int c = w + 16 * cg + 64 * q;
+    if (c < k) put_slice<T>(Cb + (int64_t)c * BR + rg * NI, cb[q]);
   }
 }
 
-// Q formation at a leaf: rows of Q = H_0 ... H_{k-1} [C; 0] for block b.
-// OUT 0: Q row-major in T (ldq); OUT 1: Q transposed and split into 16-bit
-// parts, Qh[c*ldq + r], Ql[c*ldq + r] (DT the 16-bit type).
+// Q formation at a leaf: rows of Q = H_0 ... H_{k-1} [C; 0] for block b,
+// reflectors read back from U (slice order) 16 at a time through LDS.
+// OUT 0: Q row-major in T (ldq), written row-contiguously through an LDS
+// tile; OUT 1: Q transposed and split into 16-bit parts, Qh[c*ldq + r],
+// Ql[c*ldq + r] (DT the 16-bit type).
 template <typename T, int OUT, int DT>
-__global__ __launch_bounds__(1024) void k_tsqr_leaf_q(const T *__restrict__ U, int64_t m, int k,
-                                                     int64_t ldu, const T *__restrict__ tau_in,
-                                                     const T *__restrict__ C_in,
-                                                     T *__restrict__ Q, int64_t ldq,
-                                                     uint16_t *__restrict__ Qh,
-                                                     uint16_t *__restrict__ Ql) {
-  constexpr int BR = TsqrCfg<T>::BR, H = BR / 4;
-  constexpr int CH = 16;
-  __shared__ T vl[CH][BR];
-  __shared__ T tl[CH];
-  const int tid = threadIdx.x, c = tid >> 2, h = tid & 3;
+__global__ __launch_bounds__(1024) void k_tsqr_leaf_q(const T *__restrict__ U, int64_t ldu, int64_t m, int k,
+                                                      const T *__restrict__ tau_in,
+                                                      const T *__restrict__ C_in,
+                                                      T *__restrict__ Q, int64_t ldq,
+                                                      uint16_t *__restrict__ Qh,
+                                                      uint16_t *__restrict__ Ql) {
+  constexpr int BR = TsqrCfg<T>::BR, NI = TsqrCfg<T>::NI, NQ = TsqrCfg<T>::NQ, SP = lds_stride<T>();
+  using Vec = typename TsqrCfg<T>::vec;
+  __shared__ __align__(16) T vs[2][16 * 16 * SP];
+  __shared__ T ts[2][16];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, rg = lane & 15, cg = lane >> 4;
   const int64_t row0 = (int64_t)blockIdx.x * BR;
-  const int64_t kk = (int64_t)k * k;
-  const T *C = C_in + (int64_t)blockIdx.x * kk;
-  const bool active = c < k;
-  T q[H];
+  const int rows_here = (int)(m - row0 < BR ? m - row0 : BR);
+  const int64_t kb = (int64_t)k * BR;
+  const T *C = C_in + (int64_t)blockIdx.x * kb;
+  const T *Ub = U + row0;
+  const T *tau = tau_in + (int64_t)blockIdx.x * k;
+  const Stage16<T> st;
+  const int nblk = (k + 15) / 16;
+  Vec pre = st.fetch(Ub, ldu, nblk - 1, k);
+  T tpre = (threadIdx.x < 16 && 16 * (nblk - 1) + (int)threadIdx.x < k) ? tau[16 * (nblk - 1) + threadIdx.x] : (T)0;
+  T qv[NQ][NI];
 #pragma unroll
-  for (int i = 0; i < H; ++i) {
-    const int row = h * H + i;
-    q[i] = (active && row < k) ? C[(int64_t)row * k + c] : (T)0;
+  for (int q = 0; q < NQ; ++q) {
+    const int c = w + 16 * cg + 64 * q;
+    T t[NI];
+    get_slice<T>(C + (int64_t)(c < k ? c : 0) * BR + rg * NI, t);
+#pragma unroll
+    for (int i = 0; i < NI; ++i) qv[q][i] = (c < k && rg + 16 * i < k) ? t[i] : (T)0;
   }
-  for (int j1 = k; j1 > 0; j1 -= CH) {
-    const int j0 = j1 - CH > 0 ? j1 - CH : 0;
+#pragma unroll
+  for (int bi = 4 * NQ - 1; bi >= 0; --bi) {
+    if (bi >= nblk) continue;
+    const int buf = bi & 1;
+    *reinterpret_cast<Vec *>(&vs[buf][st.dst]) = pre;
+    if (threadIdx.x < 16) ts[buf][threadIdx.x] = tpre;
     __syncthreads();
-    // chunk of reflectors j0..j1-1: v_j[row] = 0 (row < j), 1 (row == j),
-    // the stored entry below the diagonal
-    for (int e = tid; e < (j1 - j0) * BR; e += blockDim.x) {
-      const int jj = e / BR, row = e % BR, j = j0 + jj;
-      const int64_t r = row0 + row;
-      T v = 0;
-      if (row == j) v = 1;
-      else if (row > j && r < m) v = U[r * ldu + j];
-      vl[jj][row] = v;
+    if (bi > 0) {
+      pre = st.fetch(Ub, ldu, bi - 1, k);
+      tpre = threadIdx.x < 16 ? tau[16 * (bi - 1) + threadIdx.x] : (T)0;
     }
-    for (int e = tid; e < j1 - j0; e += blockDim.x) tl[e] = tau_in[(int64_t)blockIdx.x * k + j0 + e];
-    __syncthreads();
-    for (int j = j1 - 1; j >= j0; --j) {
-      const int jj = j - j0;
-      if (active) {
-        T d = 0;
+    for (int j16 = 15; j16 >= 0; --j16) {
+      const int j = 16 * bi + j16;
+      if (j >= k) continue;
+      const T t = ts[buf][j16];
+      T v[NI];
+      get_slice<T>(&vs[buf][j16 * 16 * SP + rg * SP], v);
 #pragma unroll
-        for (int i = 0; i < H; ++i) d += vl[jj][h * H + i] * q[i];
-        d = quad_sum(d) * tl[jj];
-        asm volatile("" ::: "memory");
+      for (int qq = 0; qq < NQ; ++qq) {
+        if (w + 64 * qq < k) {
+          T d0 = 0, d1 = 0;
 #pragma unroll
-        for (int i = 0; i < H; ++i) q[i] -= d * vl[jj][h * H + i];
+          for (int i = bi; i < NI; ++i) {
+            if ((i - bi) & 1) d1 += v[i] * qv[qq][i];
+            else d0 += v[i] * qv[qq][i];
+          }
+          const T d = sum16(d0 + d1) * t;
+#pragma unroll
+          for (int i = bi; i < NI; ++i) qv[qq][i] -= d * v[i];
+        }
       }
     }
   }
-  if (!active) return;
   if constexpr (OUT == 0) {
+    // 16 rows at a time through an LDS tile (stride k + 1) into row-major Q
+    T *tile = &vs[0][0];
+    const int ts_ = k + 1;
 #pragma unroll
-    for (int i = 0; i < H; ++i) {
-      const int64_t r = row0 + h * H + i;
-      if (r < m) Q[r * ldq + c] = q[i];
+    for (int i = 0; i < NI; ++i) {
+      __syncthreads();
+#pragma unroll
+      for (int qq = 0; qq < NQ; ++qq) {
+        const int c = w + 16 * cg + 64 * qq;
+        if (c < k) tile[rg * ts_ + c] = qv[qq][i];
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < 16 * k; e += blockDim.x) {
+        const int rr = e / k, c = e - rr * k, r = 16 * i + rr;
+        if (r < rows_here) Q[(row0 + r) * ldq + c] = tile[rr * ts_ + c];
+      }
     }
   } else {
 #pragma unroll
-    for (int i = 0; i < H; ++i) {
-      const int64_t r = row0 + h * H + i;
-      if (r < m) {
-        const float f = (float)q[i];
-        uint16_t hi, lo;
-        if constexpr (DT == LSPCA_BF16) {
-          hi = __builtin_bit_cast(uint16_t, (__bf16)f);
-          lo = __builtin_bit_cast(uint16_t, (__bf16)(f - bf16_bits_to_f32(hi)));
-        } else {
-          hi = f32_to_f16_bits(f);
-          lo = f32_to_f16_bits(f - f16_bits_to_f32(hi));
+    for (int qq = 0; qq < NQ; ++qq) {
+      const int c = w + 16 * cg + 64 * qq;
+      if (c >= k) continue;
+#pragma unroll
+      for (int i = 0; i < NI; ++i) {
+        const int r = rg + 16 * i;
+        if (r < rows_here) {
+          const float f = (float)qv[qq][i];
+          uint16_t hi, lo;
+          if constexpr (DT == LSPCA_BF16) {
+            hi = __builtin_bit_cast(uint16_t, (__bf16)f);
+            lo = __builtin_bit_cast(uint16_t, (__bf16)(f - bf16_bits_to_f32(hi)));
+          } else {
+            hi = f32_to_f16_bits(f);
+            lo = f32_to_f16_bits(f - f16_bits_to_f32(hi));
+          }
+          Qh[(int64_t)c * ldq + row0 + r] = hi;
+          Ql[(int64_t)c * ldq + row0 + r] = lo;
         }
-        Qh[(int64_t)c * ldq + r] = hi;
-        Ql[(int64_t)c * ldq + r] = lo;
       }
     }
   }
 }
 
-__global__ void k_eye(double *C, int k) {
+// C = I_k in slice order (column c: BR entries).
+template <typename T> __global__ void k_eye_slices(T *C, int k) {
+  constexpr int BR = TsqrCfg<T>::BR, NI = TsqrCfg<T>::NI;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < (int64_t)k * k) C[e] = (e / k == e % k) ? 1.0 : 0.0;
-}
-__global__ void k_eye_f(float *C, int k) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < (int64_t)k * k) C[e] = (e / k == e % k) ? 1.f : 0.f;
+  if (e >= (int64_t)k * BR) return;
+  const int c = (int)(e / BR), pp = (int)(e % BR);
+  const int r = pp / NI + 16 * (pp % NI);
+  C[e] = r == c ? (T)1 : (T)0;
 }
 
 // ---------------------------------------------------------------- driver --
-static int tsqr_threads(int k) {
-  int t = ((4 * k + 63) / 64) * 64;
-  return t < 64 ? 64 : t;
+static int tsqr_br(lspca_dtype ydt) { return ydt == LSPCA_F64 ? TsqrCfg<double>::BR : TsqrCfg<float>::BR; }
+
+int64_t tsqr_ld(int64_t m, lspca_dtype ydt) {
+  const int BR = tsqr_br(ydt);
+  return (m + BR - 1) / BR * BR;
 }
 
 size_t tsqr_workspace_bytes(int64_t m, int k, lspca_dtype ydt) {
   const size_t es = ydt == LSPCA_F64 ? 8 : 4;
-  const int BR = ydt == LSPCA_F64 ? 128 : 256;
-  int64_t nb = (m + BR - 1) / BR;
+  const int BR = tsqr_br(ydt);
+  int64_t level = (m + BR - 1) / BR;
   size_t total = 0;
-  int64_t level = nb;
-  // R per level, Vb and tau per node level, C per level (top-down)
+  bool leaf = true;
+  // per level: R, C, tau; Vb above the leaves
   while (true) {
-    total += 3 * ws_bytes<char>(es * (size_t)level * k * k) + ws_bytes<char>(es * (size_t)level * k);
+    const size_t blk = es * (size_t)level * k * BR;
+    total += 2 * ws_bytes<char>(blk) + ws_bytes<char>(es * (size_t)level * k);
+    if (!leaf) total += ws_bytes<char>(blk);
     if (level == 1) break;
     level = (level + 1) / 2;
+    leaf = false;
   }
-  total += ws_bytes<char>(es * (size_t)nb * k);   // leaf tau
   return total + 4096;
 }
 
 template <typename T>
-static int tsqr_typed(T *U, int64_t m, int k, Workspace &ws, int out_mode, lspca_dtype dt16,
+static int tsqr_typed(T *U, int64_t m, int64_t ldu, int k, Workspace &ws, int out_mode, lspca_dtype dt16,
                       T *Q, uint16_t *Qh, uint16_t *Ql, int64_t ldq, hipStream_t s) {
   constexpr int BR = TsqrCfg<T>::BR;
   if (k > BR) {
     set_error("spca_fit: k = %d exceeds the QR block height %d for this type", k, BR);
     return LSPCA_ENOTSUP;
   }
-  const int threads = tsqr_threads(k);
-  const int64_t kk = (int64_t)k * k;
-  std::vector<int64_t> counts;
-  int64_t nb = (m + BR - 1) / BR;
+  const int64_t nb = (m + BR - 1) / BR;
   if (nb > 0x7fffffff) {
     set_error("spca_fit: too many QR blocks");
     return LSPCA_EINVAL;
   }
-  counts.push_back(nb);
+  if (ldu < nb * BR) {
+    set_error("tsqr: leading dimension %lld below %lld", (long long)ldu, (long long)(nb * BR));
+    return LSPCA_EINVAL;
+  }
+  const int64_t kb = (int64_t)k * BR;
+  std::vector<int64_t> counts{nb};
   while (counts.back() > 1) counts.push_back((counts.back() + 1) / 2);
   const size_t L = counts.size();
-  std::vector<T *> R(L), Vb(L), tau(L), C(L);
+  std::vector<T *> R(L), C(L), tau(L), Vb(L, nullptr);
   for (size_t l = 0; l < L; ++l) {
-    R[l] = ws.take<T>((size_t)counts[l] * kk);
-    Vb[l] = ws.take<T>((size_t)counts[l] * kk);
+    R[l] = ws.take<T>((size_t)counts[l] * kb);
+    C[l] = ws.take<T>((size_t)counts[l] * kb);
     tau[l] = ws.take<T>((size_t)counts[l] * k);
-    C[l] = ws.take<T>((size_t)counts[l] * kk);
+    if (l) Vb[l] = ws.take<T>((size_t)counts[l] * kb);
   }
-  T *tau_leaf = tau[0];
-  hipLaunchKernelGGL(k_tsqr_leaf<T>, (unsigned)nb, threads, 0, s, U, m, k, (int64_t)k, tau_leaf, R[0]);
+  hipLaunchKernelGGL((k_tsqr_leaf<T>), (unsigned)nb, 1024, 0, s, U, ldu, m, k, tau[0], R[0]);
   LSPCA_HIP(hipGetLastError());
   for (size_t l = 1; l < L; ++l) {
-    hipLaunchKernelGGL(k_tsqr_node<T>, (unsigned)counts[l], threads, 0, s, R[l - 1], (int)counts[l - 1], k,
-                       R[l], Vb[l], tau[l]);
+    hipLaunchKernelGGL((k_tsqr_node<T>), (unsigned)counts[l], 1024, 0, s, R[l - 1], (int)counts[l - 1], k, R[l],
+                       Vb[l], tau[l]);
     LSPCA_HIP(hipGetLastError());
   }
   // top-down: C at the root is the identity
-  if constexpr (sizeof(T) == 8)
-    hipLaunchKernelGGL(k_eye, (unsigned)((kk + 255) / 256), 256, 0, s, (double *)C[L - 1], k);
-  else
-    hipLaunchKernelGGL(k_eye_f, (unsigned)((kk + 255) / 256), 256, 0, s, (float *)C[L - 1], k);
+  hipLaunchKernelGGL((k_eye_slices<T>), (unsigned)((kb + 255) / 256), 256, 0, s, C[L - 1], k);
   LSPCA_HIP(hipGetLastError());
   for (size_t l = L - 1; l >= 1; --l) {
-    hipLaunchKernelGGL(k_tsqr_node_q<T>, (unsigned)counts[l], threads, 0, s, C[l], (int)counts[l - 1], k,
-                       Vb[l], tau[l], C[l - 1]);
+    hipLaunchKernelGGL((k_tsqr_node_q<T>), (unsigned)counts[l], 1024, 0, s, C[l], (int)counts[l - 1], k, Vb[l],
+                       tau[l], C[l - 1]);
     LSPCA_HIP(hipGetLastError());
   }
-  if (out_mode == 0) {
-    hipLaunchKernelGGL((k_tsqr_leaf_q<T, 0, LSPCA_BF16>), (unsigned)nb, threads, 0, s, U, m, k, (int64_t)k,
-                       tau_leaf, C[0], Q, ldq, nullptr, nullptr);
-  } else if (dt16 == LSPCA_BF16) {
-    hipLaunchKernelGGL((k_tsqr_leaf_q<T, 1, LSPCA_BF16>), (unsigned)nb, threads, 0, s, U, m, k, (int64_t)k,
-                       tau_leaf, C[0], Q, ldq, Qh, Ql);
-  } else {
-    hipLaunchKernelGGL((k_tsqr_leaf_q<T, 1, LSPCA_F16>), (unsigned)nb, threads, 0, s, U, m, k, (int64_t)k,
-                       tau_leaf, C[0], Q, ldq, Qh, Ql);
-  }
+  if (out_mode == 0)
+    hipLaunchKernelGGL((k_tsqr_leaf_q<T, 0, LSPCA_BF16>), (unsigned)nb, 1024, 0, s, U, ldu, m, k, tau[0], C[0], Q,
+                       ldq, nullptr, nullptr);
+  else if (dt16 == LSPCA_BF16)
+    hipLaunchKernelGGL((k_tsqr_leaf_q<T, 1, LSPCA_BF16>), (unsigned)nb, 1024, 0, s, U, ldu, m, k, tau[0], C[0], Q,
+                       ldq, Qh, Ql);
+  else
+    hipLaunchKernelGGL((k_tsqr_leaf_q<T, 1, LSPCA_F16>), (unsigned)nb, 1024, 0, s, U, ldu, m, k, tau[0], C[0], Q,
+                       ldq, Qh, Ql);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }
 
-// U (m x k, row-major, FP32 or FP64 as ydt) is overwritten by its compact
-// factors. out_mode 0: Q (m x k, row-major, ydt) in Q; out_mode 1: Q^T split
-// into 16-bit parts of type dt16 in Qh, Ql (k x m, leading dimension ldq).
-int tsqr(void *U, lspca_dtype ydt, int64_t m, int k, Workspace &ws, int out_mode,
+// Ut: U transposed (column c of U at Ut + c * ldu, ldu >= tsqr_ld(m)),
+// FP32 or FP64 as ydt; overwritten by the leaves' reflectors. out_mode 0:
+// Q (m x k, row-major, ydt, leading dimension ldq) in Q; out_mode 1: Q^T
+// split into 16-bit parts of type dt16 in Qh, Ql (k x m, leading dimension
+// ldq).
+int tsqr(void *Ut, lspca_dtype ydt, int64_t m, int64_t ldu, int k, Workspace &ws, int out_mode,
          lspca_dtype dt16, void *Q, void *Qh, void *Ql, int64_t ldq, hipStream_t s) {
   if (ydt == LSPCA_F64)
-    return tsqr_typed<double>((double *)U, m, k, ws, out_mode, dt16, (double *)Q, (uint16_t *)Qh,
+    return tsqr_typed<double>((double *)Ut, m, ldu, k, ws, out_mode, dt16, (double *)Q, (uint16_t *)Qh,
                               (uint16_t *)Ql, ldq, s);
-  return tsqr_typed<float>((float *)U, m, k, ws, out_mode, dt16, (float *)Q, (uint16_t *)Qh,
+  return tsqr_typed<float>((float *)Ut, m, ldu, k, ws, out_mode, dt16, (float *)Q, (uint16_t *)Qh,
                            (uint16_t *)Ql, ldq, s);
 }
 
