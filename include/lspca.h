@@ -29,6 +29,8 @@
  *    process exit). Calls that overlap on one device from several host
  *    threads are serialised by a lock.
  *  - X is never centred (Sec. I-B: the SPCA subspace does not need it).
+ *  - The projection server (lspca_server_*) is the one exception to
+ *    "device pointers only": its requests may also live in host memory.
  */
 #ifndef LSPCA_H
 #define LSPCA_H
@@ -203,6 +205,90 @@ LSPCA_API int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n,
 LSPCA_API int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t n,
                     int64_t ldx, const double *V, int32_t k, void *Z,
                     const lspca_opts *opts);
+
+/*
+ * Projection server: continuous batching of requests Z = X V, the map
+ * pi(x) = V^T x of eq. (dim_reduction_maps), with V resident on the device.
+ *
+ * A request is r rows of X (r x n, rows contiguous, in the server's dtype)
+ * and its output Z (r x k, rows contiguous; FP32, FP64 for an F64 server).
+ * Requests enter a FIFO queue. The server's scheduler thread admits them in
+ * order while fewer than max_inflight requests are admitted and unfinished
+ * and, for host requests, while the staging arena has room for X and Z.
+ * Admitted requests are packed, up to 64 at a time, into one launch of a
+ * persistent kernel that walks the launch's row tiles across requests. Each
+ * launch replays a HIP graph captured at creation (request-table upload and
+ * kernel) and launches rotate over several streams, so requests that arrive
+ * while others are on the device are launched at once and overlap them.
+ * Each row is computed by the tile code lspca_transform uses, so a result
+ * is bitwise the same alone, in any mix of requests, and as lspca_transform.
+ * X and Z are both device pointers, or both host pointers (hipHostMalloc
+ * memory gives asynchronous copies): host requests are copied into the
+ * arena, projected there and copied back before they complete.
+ * Latency is measured by the server from lspca_server_submit to the moment
+ * its scheduler sees the request's launch (and copies) complete.
+ * All functions are thread-safe for one server.
+ */
+typedef struct lspca_server lspca_server;
+
+typedef struct {
+  uint32_t struct_size;             /* sizeof(lspca_server_stats) */
+  uint32_t max_requests_per_launch; /* largest batch packed into one launch */
+  uint32_t max_concurrent_launches; /* most launches in flight at once */
+  uint32_t reserved;
+  uint64_t submitted, completed, launches, rows_completed;
+  uint64_t arena_peak_bytes;        /* most staging bytes held at once */
+} lspca_server_stats;
+
+/*
+ * lspca_server_create -- V: n x k FP64 (device, caller-owned; copied and
+ *  converted at creation, so it may be freed afterwards). xdt: dtype of X
+ *  (BF16/FP16 use V split in two 16-bit parts, as lspca_transform).
+ *  arena_bytes: device staging memory for host requests (0 = device
+ *  requests only). max_inflight: admitted, unfinished requests (>= 1).
+ *  *out receives the server (library-owned, freed by lspca_server_destroy).
+ *  Errors: EINVAL (n < 1, k < 1, bad dtype, NULL), ENOMEM, EHIP.
+ */
+LSPCA_API int lspca_server_create(const double *V, int64_t n, int32_t k, lspca_dtype xdt,
+                        size_t arena_bytes, int32_t max_inflight, lspca_server **out);
+
+/*
+ * lspca_server_submit -- queue Z = X V for r rows; *ticket identifies the
+ *  request for lspca_server_wait. X and Z must stay valid and untouched
+ *  until the request completes, and any device work producing X (or still
+ *  using Z) must be complete when submitting: the server's streams do not
+ *  wait on the caller's. r = 0 completes at once.
+ *  Errors: EINVAL (NULL, r < 0, X and Z of different memory kinds, device X
+ *  not 16-byte aligned), E2BIG (host request larger than the arena),
+ *  EAGAIN (queue full: 16 * max_inflight requests waiting for admission).
+ */
+LSPCA_API int lspca_server_submit(lspca_server *srv, const void *X, int64_t r, void *Z,
+                        uint64_t *ticket);
+
+/*
+ * lspca_server_wait -- wait up to timeout_us (< 0: no limit; 0: poll) for
+ *  the request to complete. On completion returns its status, writes its
+ *  latency in ms (if latency_ms is not NULL) and forgets the ticket.
+ *  Errors: ENOTFOUND (unknown or already waited ticket), ETIMEDOUT (still
+ *  running; the ticket stays valid), EHIP (its launch failed).
+ */
+LSPCA_API int lspca_server_wait(lspca_server *srv, uint64_t ticket, int64_t timeout_us,
+                      double *latency_ms);
+
+/*
+ * lspca_server_pause -- paused != 0: start no new launches (launches in
+ *  flight finish; submissions still queue and are admitted); 0: resume.
+ */
+LSPCA_API int lspca_server_pause(lspca_server *srv, int paused);
+
+/* lspca_server_get_stats -- counters since creation (out->struct_size set by the caller). */
+LSPCA_API int lspca_server_get_stats(lspca_server *srv, lspca_server_stats *out);
+
+/*
+ * lspca_server_destroy -- finish every submitted request, then free the
+ *  server. Tickets not yet waited are dropped. NULL is allowed.
+ */
+LSPCA_API int lspca_server_destroy(lspca_server *srv);
 
 #ifdef __cplusplus
 }

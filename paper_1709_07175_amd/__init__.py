@@ -14,7 +14,7 @@ import os
 __all__ = [
     "load", "LspcaError", "F64", "F32", "BF16", "F16", "GAUSSIAN", "VERY_SPARSE",
     "version", "omega", "accumulate", "factor", "fit", "spca_fit", "transform",
-    "last_timings", "exported_symbols", "LIB_PATH",
+    "last_timings", "exported_symbols", "LIB_PATH", "Server",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,7 +31,8 @@ STATUS = {0: "LSPCA_OK", -1: "LSPCA_EINVAL", -2: "LSPCA_ENOMEM", -3: "LSPCA_EHIP
 # Every symbol include/lspca.h declares.
 EXPORTS = ["lspca_version", "lspca_strerror", "lspca_last_error", "lspca_last_timings",
            "lspca_omega", "lspca_accumulate", "lspca_factor", "lspca_fit", "spca_fit",
-           "lspca_transform"]
+           "lspca_transform", "lspca_server_create", "lspca_server_submit", "lspca_server_wait",
+           "lspca_server_pause", "lspca_server_get_stats", "lspca_server_destroy"]
 
 
 class LspcaError(RuntimeError):
@@ -53,6 +54,14 @@ class lspca_timings(ctypes.Structure):
                  "pass2_ms", "transform_ms", "total_ms")]
 
 
+class lspca_server_stats(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_requests_per_launch", ctypes.c_uint32),
+                ("max_concurrent_launches", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("rows_completed", ctypes.c_uint64),
+                ("arena_peak_bytes", ctypes.c_uint64)]
+
+
 _lib = None
 _P, _I64, _I32, _U64, _U32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                               ctypes.c_uint64, ctypes.c_uint32)
@@ -71,6 +80,13 @@ _SIGS = {
                   ctypes.POINTER(lspca_opts), _P, _P], ctypes.c_int),
     "lspca_transform": ([_P, ctypes.c_int, _I64, _I64, _I64, _P, _I32, _P,
                          ctypes.POINTER(lspca_opts)], ctypes.c_int),
+    "lspca_server_create": ([_P, _I64, _I32, ctypes.c_int, ctypes.c_size_t, _I32,
+                             ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "lspca_server_submit": ([_P, _P, _I64, _P, ctypes.POINTER(_U64)], ctypes.c_int),
+    "lspca_server_wait": ([_P, _U64, _I64, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "lspca_server_pause": ([_P, ctypes.c_int], ctypes.c_int),
+    "lspca_server_get_stats": ([_P, ctypes.POINTER(lspca_server_stats)], ctypes.c_int),
+    "lspca_server_destroy": ([_P], ctypes.c_int),
 }
 
 
@@ -237,3 +253,75 @@ def last_timings():
     t = lspca_timings()
     _check(load().lspca_last_timings(ctypes.byref(t)))
     return {n: getattr(t, n) for n, _ in lspca_timings._fields_}
+
+
+class Server:
+    """Projection server (lspca_server_*): continuous batching of Z = X V.
+
+    V (n x k FP64, device) is copied at creation. submit() takes X (r x n,
+    rows contiguous, the server's dtype) and Z (r x k, FP32; FP64 for an F64
+    server), both device tensors or both host tensors (pinned for
+    asynchronous copies), and returns a ticket; wait() returns the latency
+    in ms measured by the server. The tensors must stay alive and untouched
+    until the request completes.
+    """
+
+    def __init__(self, V, dtype, arena_bytes=0, max_inflight=32):
+        torch = _torch()
+        if V.dtype != torch.float64 or not V.is_cuda or not V.is_contiguous():
+            raise ValueError("V must be a contiguous FP64 device tensor")
+        self.n, self.k = V.shape
+        self.dtype = dtype
+        h = ctypes.c_void_p()
+        _check(load().lspca_server_create(V.data_ptr(), self.n, self.k, dtype, arena_bytes,
+                                          max_inflight, ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, X, Z):
+        if X.dim() != 2 or X.shape[1] != self.n or not X.is_contiguous():
+            raise ValueError("X must be a contiguous r x n tensor")
+        if _dtype_code(X) != self.dtype:
+            raise TypeError("X dtype differs from the server's")
+        if Z.shape != (X.shape[0], self.k) or not Z.is_contiguous():
+            raise ValueError("Z must be a contiguous r x k tensor")
+        t = _U64()
+        _check(load().lspca_server_submit(self._h, X.data_ptr(), X.shape[0], Z.data_ptr(),
+                                          ctypes.byref(t)))
+        return t.value
+
+    def submit_ptr(self, x_ptr, rows, z_ptr):
+        """Submit by raw addresses (rows contiguous, as submit)."""
+        t = _U64()
+        _check(load().lspca_server_submit(self._h, x_ptr, rows, z_ptr, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket, timeout_us=-1):
+        lat = ctypes.c_double()
+        _check(load().lspca_server_wait(self._h, ticket, timeout_us, ctypes.byref(lat)))
+        return lat.value
+
+    def pause(self, paused=True):
+        _check(load().lspca_server_pause(self._h, 1 if paused else 0))
+
+    def stats(self):
+        st = lspca_server_stats()
+        st.struct_size = ctypes.sizeof(lspca_server_stats)
+        _check(load().lspca_server_get_stats(self._h, ctypes.byref(st)))
+        return {n: getattr(st, n) for n, _ in lspca_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().lspca_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -178,6 +178,32 @@ int small_factor(const double *F, const double *G, int k, int64_t n,
                  hipStream_t s, int *rank_flag);
 int launch_transpose_f64(const double *src, int64_t rows, int cols,
                          double *dst, hipStream_t s);
+// Request table of one batched projection launch (the projection server):
+// request i owns tiles [req[i].tile0, req[i+1].tile0), numbered row tile
+// major, ntn column tiles per row tile. X rows are n-contiguous (ldx), Z
+// rows k-contiguous (ldz).
+constexpr int kProjMaxReq = 64;
+struct ProjReq {
+  const void *X;
+  void *Z;
+  int64_t ldx, ldz, rows;
+  int32_t tile0, pad;
+};
+struct ProjTable {
+  int32_t nreq, ntiles, ntn, pad;
+  ProjReq req[kProjMaxReq];
+};
+// Tile shape of the projection Z = X V for dtype dt and k columns: the one
+// lspca_transform uses, so a batched result is bitwise that of a single call.
+void proj_tile_shape(lspca_dtype dt, int k, int *BM, int *BN);
+// Workgroups that keep every CU busy for the persistent batch kernel.
+int proj_batch_grid(lspca_dtype dt, int k, bool vec, int *grid);
+// Z = X V for every request of the table in device memory; VT = V^T in the
+// compute type (16-bit: VTh + VTl), ldv = n. vec: every X row and V^T row is
+// 16-byte aligned (n a multiple of the vector width).
+int launch_proj_batch(lspca_dtype dt, const ProjTable *tab, const void *VTh, const void *VTl,
+                      int64_t ldv, int k, int n, bool vec, int grid, hipStream_t s);
+
 int launch_convert_vt(const double *V, int64_t n, int k, lspca_dtype dt,
                       void *hi, void *lo, hipStream_t s);
 

@@ -48,11 +48,14 @@ template <> struct Vec16<float> { typedef f32x4 type; static constexpr int W = 4
 template <> struct Vec16<double> { typedef f64x2 type; static constexpr int W = 2; };
 
 // --------------------------------------------------------------------- NT --
+// One BM x BN tile of C at (m0, n0); the LDS it stages through is free
+// again on return, so a workgroup may call it for several tiles in turn.
 template <typename T, int BM, int BN, int BK, int WGM, int WGN, bool VEC>
-__global__ __launch_bounds__(256) void k_nt(const T *__restrict__ A, int64_t lda,
-                                            const T *__restrict__ B, int64_t ldb,
-                                            T *__restrict__ C, int64_t ldc,
-                                            int64_t M, int N, int K, T alpha, T beta) {
+__device__ __forceinline__ void nt_tile(const T *__restrict__ A, int64_t lda,
+                                        const T *__restrict__ B, int64_t ldb,
+                                        T *__restrict__ C, int64_t ldc,
+                                        int64_t M, int N, int K, T alpha, T beta,
+                                        const int64_t m0, const int n0) {
   typedef Mfma<T> MF;
   constexpr int MB = MF::MB, KB = MF::KB;
   constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -68,8 +71,6 @@ __global__ __launch_bounds__(256) void k_nt(const T *__restrict__ A, int64_t lda
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
 
   T ra[AV * VW], rb[BV * VW];
   auto load = [&](int k0) {
@@ -162,6 +163,15 @@ __global__ __launch_bounds__(256) void k_nt(const T *__restrict__ A, int64_t lda
           C[r * ldc + c] = val;
         }
       }
+}
+
+template <typename T, int BM, int BN, int BK, int WGM, int WGN, bool VEC>
+__global__ __launch_bounds__(256) void k_nt(const T *__restrict__ A, int64_t lda,
+                                            const T *__restrict__ B, int64_t ldb,
+                                            T *__restrict__ C, int64_t ldc,
+                                            int64_t M, int N, int K, T alpha, T beta) {
+  nt_tile<T, BM, BN, BK, WGM, WGN, VEC>(A, lda, B, ldb, C, ldc, M, N, K, alpha, beta,
+                                        (int64_t)blockIdx.x * BM, (int)blockIdx.y * BN);
 }
 
 // --------------------------------------------------------------------- TN --
@@ -381,6 +391,63 @@ int launch_tn(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t
       set_error("tn product: dtype %d not handled here", (int)dt);
       return LSPCA_ENOTSUP;
   }
+}
+
+// ------------------------------------------------------ batched projection --
+// Persistent: workgroup b takes tiles b, b + grid, ... of the table; the
+// request of a tile is found by binary search over the tiles' first numbers.
+template <typename T, int BM, int BN, bool VEC>
+__global__ __launch_bounds__(256) void k_proj_batch(const ProjTable *__restrict__ tab,
+                                                    const T *__restrict__ VT, int64_t ldv, int N, int K) {
+  const int ntiles = tab->ntiles, nreq = tab->nreq, ntn = tab->ntn;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tab->req[mid].tile0 <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const ProjReq &rq = tab->req[lo];
+    const int local = t - rq.tile0, mt = local / ntn;
+    nt_tile<T, BM, BN, 16, 2, 2, VEC>((const T *)rq.X, rq.ldx, VT, ldv, (T *)rq.Z, rq.ldz, rq.rows, N, K,
+                                      (T)1, (T)0, (int64_t)mt * BM, (local - mt * ntn) * BN);
+  }
+}
+
+static const void *projf_kernel(lspca_dtype dt, bool vec) {
+  if (dt == LSPCA_F64)
+    return vec ? (const void *)&k_proj_batch<double, 64, 64, true> : (const void *)&k_proj_batch<double, 64, 64, false>;
+  return vec ? (const void *)&k_proj_batch<float, 128, 128, true> : (const void *)&k_proj_batch<float, 128, 128, false>;
+}
+
+int proj16_grid(lspca_dtype dt, int k, bool vec, int *grid);
+int launch_proj_batch16(lspca_dtype dt, const ProjTable *tab, const void *VTh, const void *VTl, int64_t ldv,
+                        int k, int n, bool vec, int grid, hipStream_t s);
+
+void proj_tile_shape(lspca_dtype dt, int k, int *BM, int *BN) {
+  switch (dt) {
+    case LSPCA_F64: *BM = 64; *BN = 64; break;
+    case LSPCA_F32: *BM = 128; *BN = 128; break;
+    default: *BM = 128; *BN = k > 128 ? 256 : 128; break;
+  }
+}
+
+int proj_batch_grid(lspca_dtype dt, int k, bool vec, int *grid) {
+  if (dt == LSPCA_BF16 || dt == LSPCA_F16) return proj16_grid(dt, k, vec, grid);
+  int dev = 0, cus = 0, per = 0;
+  LSPCA_HIP(hipGetDevice(&dev));
+  LSPCA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  LSPCA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, projf_kernel(dt, vec), 256, 0));
+  *grid = cus * (per > 0 ? per : 1);
+  return LSPCA_OK;
+}
+
+int launch_proj_batch(lspca_dtype dt, const ProjTable *tab, const void *VTh, const void *VTl, int64_t ldv,
+                      int k, int n, bool vec, int grid, hipStream_t s) {
+  if (dt == LSPCA_BF16 || dt == LSPCA_F16) return launch_proj_batch16(dt, tab, VTh, VTl, ldv, k, n, vec, grid, s);
+  void *args[] = {(void *)&tab, (void *)&VTh, (void *)&ldv, (void *)&k, (void *)&n};
+  LSPCA_HIP(hipLaunchKernel(projf_kernel(dt, vec), dim3(grid), dim3(256), args, 0, s));
+  return LSPCA_OK;
 }
 
 }  // namespace lspca

@@ -51,13 +51,16 @@ __device__ inline int mrow(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >>
 // (Cl may be NULL), each [c*ldc + r].
 enum { OUT_ROWS = 0, OUT_T32 = 1, OUT_TSPLIT = 2 };
 
+// One BM x BN tile of C at (m0, n0); the LDS it stages through is free
+// again on return, so a workgroup may call it for several tiles in turn.
 template <int DT, int BM, int BN, bool SPLITB, bool VEC, int OUT>
-__global__ __launch_bounds__(256) void k_nt16(const uint16_t *__restrict__ A, int64_t lda,
-                                              const uint16_t *__restrict__ Bh,
-                                              const uint16_t *__restrict__ Bl, int64_t ldb,
-                                              float *__restrict__ C, int64_t ldc, int64_t M, int N,
-                                              int K, unsigned *__restrict__ colmax,
-                                              uint16_t *__restrict__ Ch, uint16_t *__restrict__ Cl) {
+__device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_t lda,
+                                          const uint16_t *__restrict__ Bh,
+                                          const uint16_t *__restrict__ Bl, int64_t ldb,
+                                          float *__restrict__ C, int64_t ldc, int64_t M, int N,
+                                          int K, unsigned *__restrict__ colmax,
+                                          uint16_t *__restrict__ Ch, uint16_t *__restrict__ Cl,
+                                          const int64_t m0, const int n0) {
   constexpr int BK = 32, LD = BK + 8;                 // +16 bytes per row of a tile
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
   constexpr int AV = BM * BK / 8 / 256, BV = BN * BK / 8 / 256;
@@ -67,8 +70,6 @@ __global__ __launch_bounds__(256) void k_nt16(const uint16_t *__restrict__ A, in
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
-  const int64_t m0 = (int64_t)blockIdx.x * BM;
-  const int n0 = blockIdx.y * BN;
 
   u16x8 ra[AV], rbh[BV], rbl[SPLITB ? BV : 1];
   auto ld8 = [&](const uint16_t *p, bool ok, int kleft) -> u16x8 {
@@ -210,6 +211,17 @@ __global__ __launch_bounds__(256) void k_nt16(const uint16_t *__restrict__ A, in
     if constexpr (OUT == OUT_T32)
       if (colmax && c < N) atomicMax(colmax + c, __float_as_uint(cmax));
   }
+}
+
+template <int DT, int BM, int BN, bool SPLITB, bool VEC, int OUT>
+__global__ __launch_bounds__(256) void k_nt16(const uint16_t *__restrict__ A, int64_t lda,
+                                              const uint16_t *__restrict__ Bh,
+                                              const uint16_t *__restrict__ Bl, int64_t ldb,
+                                              float *__restrict__ C, int64_t ldc, int64_t M, int N,
+                                              int K, unsigned *__restrict__ colmax,
+                                              uint16_t *__restrict__ Ch, uint16_t *__restrict__ Cl) {
+  nt16_tile<DT, BM, BN, SPLITB, VEC, OUT>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl,
+                                          (int64_t)blockIdx.x * BM, (int)blockIdx.y * BN);
 }
 
 // FP16 split of the transposed FP32 sketch: column c (row of Yt) is scaled
@@ -416,6 +428,59 @@ int launch_nt16(lspca_dtype dt, const void *A, int64_t lda, const void *Bh, cons
     return nt16_dt<LSPCA_F16>((const uint16_t *)A, lda, (const uint16_t *)Bh, (const uint16_t *)Bl, ldb, C, ldc, M, N, K, colmax, (uint16_t *)Ch, (uint16_t *)Cl, mode, s);
   set_error("nt16 product: dtype %d", (int)dt);
   return LSPCA_ENOTSUP;
+}
+
+// ------------------------------------------------------ batched projection --
+// Persistent: workgroup b takes tiles b, b + grid, ... of the table; the
+// request of a tile is found by binary search over the tiles' first numbers.
+template <int DT, int BM, int BN, bool VEC>
+__global__ __launch_bounds__(256) void k_proj_batch16(const ProjTable *__restrict__ tab,
+                                                      const uint16_t *__restrict__ Vh,
+                                                      const uint16_t *__restrict__ Vl, int64_t ldv,
+                                                      int N, int K) {
+  const int ntiles = tab->ntiles, nreq = tab->nreq, ntn = tab->ntn;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tab->req[mid].tile0 <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const ProjReq &rq = tab->req[lo];
+    const int local = t - rq.tile0, mt = local / ntn;
+    nt16_tile<DT, BM, BN, true, VEC, OUT_ROWS>((const uint16_t *)rq.X, rq.ldx, Vh, Vl, ldv, (float *)rq.Z,
+                                              rq.ldz, rq.rows, N, K, nullptr, nullptr, nullptr,
+                                              (int64_t)mt * BM, (local - mt * ntn) * BN);
+  }
+}
+
+template <int DT, int BN, bool VEC> static const void *proj16_fn() {
+  return (const void *)&k_proj_batch16<DT, 128, BN, VEC>;
+}
+static const void *proj16_kernel(lspca_dtype dt, int k, bool vec) {
+  const bool wide = k > 128;
+  if (dt == LSPCA_BF16) {
+    if (wide) return vec ? proj16_fn<LSPCA_BF16, 256, true>() : proj16_fn<LSPCA_BF16, 256, false>();
+    return vec ? proj16_fn<LSPCA_BF16, 128, true>() : proj16_fn<LSPCA_BF16, 128, false>();
+  }
+  if (wide) return vec ? proj16_fn<LSPCA_F16, 256, true>() : proj16_fn<LSPCA_F16, 256, false>();
+  return vec ? proj16_fn<LSPCA_F16, 128, true>() : proj16_fn<LSPCA_F16, 128, false>();
+}
+
+int proj16_grid(lspca_dtype dt, int k, bool vec, int *grid) {
+  int dev = 0, cus = 0, per = 0;
+  LSPCA_HIP(hipGetDevice(&dev));
+  LSPCA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  LSPCA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, proj16_kernel(dt, k, vec), 256, 0));
+  *grid = cus * (per > 0 ? per : 1);
+  return LSPCA_OK;
+}
+
+int launch_proj_batch16(lspca_dtype dt, const ProjTable *tab, const void *VTh, const void *VTl, int64_t ldv,
+                        int k, int n, bool vec, int grid, hipStream_t s) {
+  void *args[] = {(void *)&tab, (void *)&VTh, (void *)&VTl, (void *)&ldv, (void *)&k, (void *)&n};
+  LSPCA_HIP(hipLaunchKernel(proj16_kernel(dt, k, vec), dim3(grid), dim3(256), args, 0, s));
+  return LSPCA_OK;
 }
 
 int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld, const float *scale,

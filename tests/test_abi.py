@@ -105,3 +105,20 @@ def test_small_opts_struct_is_accepted(lib):
     st = lib.lspca_fit(1 << 20, L.F32, 100, 50, 50, 5, L.VERY_SPARSE, 1, po,
                        1 << 21, 1 << 22, None)
     assert st == -1 and "power of two" in lib.lspca_last_error().decode()
+
+
+def test_server_argument_checks(lib):
+    h = ctypes.c_void_p()
+    assert lib.lspca_server_create(None, 64, 8, L.BF16, 0, 4, ctypes.byref(h)) == -1   # V NULL
+    assert lib.lspca_server_create(1 << 20, 0, 8, L.BF16, 0, 4, ctypes.byref(h)) == -1  # n < 1
+    assert lib.lspca_server_create(1 << 20, 64, 8, 7, 0, 4, ctypes.byref(h)) == -1      # dtype
+    assert lib.lspca_server_create(1 << 20, 64, 8, L.BF16, 0, 0, ctypes.byref(h)) == -1  # max_inflight
+    assert "max_inflight" in lib.lspca_last_error().decode()
+    t = ctypes.c_uint64()
+    assert lib.lspca_server_submit(None, 1 << 20, 4, 1 << 21, ctypes.byref(t)) == -1
+    assert lib.lspca_server_wait(None, 1, 0, None) == -1
+    assert lib.lspca_server_pause(None, 1) == -1
+    st = L.lspca_server_stats()
+    st.struct_size = ctypes.sizeof(st)
+    assert lib.lspca_server_get_stats(None, ctypes.byref(st)) == -1
+    assert lib.lspca_server_destroy(None) == 0
