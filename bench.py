@@ -63,6 +63,106 @@ def cpu_baseline(cfg, X_dev, budget_s=15.0):
                       f"fit (Algorithm 2, numpy/BLAS) plus Z = X V, {dt:.2f} s"}
 
 
+def serving(lib, V, Xsrc, levels, counts, modes, seed=7175 + 5, log_every=500):
+    """Projection serving at Poisson arrivals (one level after another).
+
+    Requests: r rows, log-uniform on [1, 65,536], of BF16 rows drawn from the
+    fitted workload (a pool of the first rows of X, cast to BF16); V resident
+    in the server. Mode "device": payloads pre-staged in HBM; mode "host":
+    payloads and results in pinned host memory (H2D and D2H included).
+    Latency is the server's own (submit to completion seen). Returns a dict
+    per mode and level."""
+    import threading
+    import numpy as np
+    import torch
+    from synth import request_sizes
+
+    sys.setswitchinterval(1e-4)
+    n, k = V.shape
+    max_rows = 65_536
+    pool_rows = min(Xsrc.shape[0], max_rows + 16_384)
+    pool = Xsrc[:pool_rows].to(torch.bfloat16).contiguous()
+    out = {}
+    for mode in modes:
+        host = mode == "host"
+        Q = 16 if host else 64
+        if host:
+            Xp = pool.cpu().pin_memory()
+            Zring = torch.empty((Q, max_rows, k), dtype=torch.float32).pin_memory()
+            arena = 6 * (max_rows * n * 2 + max_rows * k * 4)
+        else:
+            Xp = pool
+            Zring = torch.empty((Q, max_rows, k), dtype=torch.float32, device=pool.device)
+            arena = 0
+        torch.cuda.synchronize()
+        res = {}
+        with lib.Server(V, lib.BF16, arena_bytes=arena, max_inflight=64) as srv:
+            # warm-up: a few requests of each size class
+            for r in (1, 300, 5000, max_rows):
+                srv.wait(srv.submit_ptr(Xp.data_ptr(), r, Zring[0].data_ptr()))
+            xrow = n * Xp.element_size()
+            zslot = max_rows * k * 4
+            for li, qps in enumerate(levels):
+                N = counts[li]
+                rng = np.random.default_rng(seed + 1000 * li + (7 if host else 0))
+                sizes = request_sizes(N, seed + li)
+                offs = rng.integers(0, pool_rows - sizes + 1)
+                gaps = rng.exponential(1.0 / qps, size=N)
+                lat = [None] * N
+                done = [threading.Event() for _ in range(N)]
+                tickets = [None] * N
+                have = [threading.Event() for _ in range(N)]
+
+                def waiter():
+                    for i in range(N):
+                        have[i].wait()
+                        lat[i] = srv.wait(tickets[i])
+                        done[i].set()
+
+                th = threading.Thread(target=waiter)
+                th.start()
+                t0 = time.perf_counter()
+                target = t0
+                for i in range(N):
+                    target += gaps[i]
+                    if i >= Q:
+                        done[i - Q].wait()        # its result slot is free again
+                    while True:
+                        dt = target - time.perf_counter()
+                        if dt <= 0:
+                            break
+                        if dt > 3e-4:
+                            time.sleep(dt - 2e-4)
+                    tickets[i] = srv.submit_ptr(Xp.data_ptr() + int(offs[i]) * xrow, int(sizes[i]),
+                                                Zring.data_ptr() + (i % Q) * zslot)
+                    have[i].set()
+                    if log_every and (i + 1) % log_every == 0:
+                        log(f"serving {mode} {qps} QPS: {i + 1}/{N} submitted")
+                th.join()
+                wall = time.perf_counter() - t0
+                a = np.array(lat)
+                rows = int(sizes.sum())
+                res[str(qps)] = {"requests": N, "p50_ms": round(float(np.percentile(a, 50)), 4),
+                                 "p99_ms": round(float(np.percentile(a, 99)), 4),
+                                 "mean_ms": round(float(a.mean()), 4), "max_ms": round(float(a.max()), 4),
+                                 "offered_qps": qps, "achieved_qps": round(N / wall, 2),
+                                 "rows_per_s": round(rows / wall, 1),
+                                 "payload_GBs": round(rows * (xrow + 4 * k) / wall / 1e9, 3)}
+                log(f"serving {mode} {qps} QPS: p50 {res[str(qps)]['p50_ms']} ms, "
+                    f"p99 {res[str(qps)]['p99_ms']} ms")
+            st = srv.stats()
+        res["server"] = {key: st[key] for key in ("launches", "max_requests_per_launch",
+                                                  "max_concurrent_launches", "arena_peak_bytes")}
+        c = max(1, st["completed"])
+        res["server"]["mean_us"] = {"queue": round(st["queue_ns"] / c / 1e3, 2),
+                                    "enqueue": round(st["enqueue_ns"] / c / 1e3, 2),
+                                    "device": round(st["device_ns"] / c / 1e3, 2)}
+        out[mode] = res
+        del Zring, Xp
+        torch.cuda.synchronize()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +173,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-spca", action="store_true")
     ap.add_argument("--spca-steps", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-counts", type=str, default="200,600,2000",
+                    help="requests at 50,200,800 QPS")
+    ap.add_argument("--serve-modes", type=str, default="device,host")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -189,6 +293,15 @@ def main():
             log(f"spca_fit {sp_ms:.3f} ms vs lazy fit {fit_ms:.3f} ms")
         except lib.LspcaError as e:
             out["spca"] = {"error": str(e)}
+    if not args.no_serve and n == 4096 and k == 256:
+        # projection serving with the fitted V (the 4,096 x 256 map of this workload)
+        levels = (50, 200, 800)
+        counts = [int(c) for c in args.serve_counts.split(",")]
+        V, _ = lib.fit(X, k, cfg["kind"], cfg["omega_seed"], sparse_p=cfg.get("p", 64))
+        sv = serving(lib, V, X, levels, counts, args.serve_modes.split(","))
+        out["serving"] = sv
+        if "device" in sv:
+            out["projection_p99_ms"] = {q: sv["device"][q]["p99_ms"] for q in map(str, levels)}
     if not args.no_cpu:
         log("cpu baseline (oracle on a row sample)")
         out["cpu_baseline"] = cpu_baseline(cfg, X)

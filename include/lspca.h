@@ -238,6 +238,10 @@ typedef struct {
   uint32_t reserved;
   uint64_t submitted, completed, launches, rows_completed;
   uint64_t arena_peak_bytes;        /* most staging bytes held at once */
+  /* Latency breakdown, summed over requests (divide by completed): */
+  uint64_t queue_ns;                /* submit -> its launch enqueued */
+  uint64_t enqueue_ns;              /* host time of the enqueue calls of its launch */
+  uint64_t device_ns;               /* launch enqueued -> completion seen */
 } lspca_server_stats;
 
 /*

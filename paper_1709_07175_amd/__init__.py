@@ -59,7 +59,8 @@ class lspca_server_stats(ctypes.Structure):
                 ("max_concurrent_launches", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
                 ("launches", ctypes.c_uint64), ("rows_completed", ctypes.c_uint64),
-                ("arena_peak_bytes", ctypes.c_uint64)]
+                ("arena_peak_bytes", ctypes.c_uint64), ("queue_ns", ctypes.c_uint64),
+                ("enqueue_ns", ctypes.c_uint64), ("device_ns", ctypes.c_uint64)]
 
 
 _lib = None

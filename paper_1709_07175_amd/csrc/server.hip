@@ -40,7 +40,8 @@ struct Request {
   bool host = false;
   size_t off = 0, bx = 0, bz = 0;      // arena block of a host request: X then Z
   int64_t tiles = 0;
-  Clock::time_point t_submit, t_done;
+  Clock::time_point t_submit, t_launch, t_done;
+  int64_t enqueue_ns = 0;
   int status = 1;                      // 1 while pending; then LSPCA_OK or an error
 };
 
@@ -95,6 +96,7 @@ struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
+  Clock::time_point t_enqueued;
   std::vector<Request *> reqs;
 };
 
@@ -145,6 +147,10 @@ void finish(lspca_server *S, Request *r, int status, Clock::time_point now) {
   --S->inflight;
   ++S->st.completed;
   S->st.rows_completed += (uint64_t)r->rows;
+  using ns = std::chrono::nanoseconds;
+  S->st.queue_ns += (uint64_t)std::chrono::duration_cast<ns>(r->t_launch - r->t_submit).count();
+  S->st.enqueue_ns += (uint64_t)r->enqueue_ns;
+  S->st.device_ns += (uint64_t)std::chrono::duration_cast<ns>(now - r->t_launch).count();
 }
 
 // Enqueue one launch on a free slot with the requests at the front of
@@ -179,6 +185,7 @@ bool launch_one(lspca_server *S) {
   t->ntiles = (int32_t)tiles;
   t->ntn = S->ntn;
   t->pad = 0;
+  const auto t_start = Clock::now();
   hipError_t e = hipSuccess;
   for (Request *r : sl->reqs)
     if (r->host && e == hipSuccess)
@@ -190,6 +197,11 @@ bool launch_one(lspca_server *S) {
       e = hipMemcpyAsync(r->Z, S->arena + r->off + r->bx, (size_t)r->rows * S->k * S->zsz,
                          hipMemcpyDeviceToHost, sl->stream);
   if (e == hipSuccess) e = hipEventRecord(sl->done, sl->stream);
+  const auto t_end = Clock::now();
+  for (Request *r : sl->reqs) {
+    r->t_launch = t_end;
+    r->enqueue_ns = std::chrono::duration_cast<std::chrono::nanoseconds>(t_end - t_start).count();
+  }
   if (e != hipSuccess) {
     const auto now = Clock::now();
     for (Request *r : sl->reqs) finish(S, r, LSPCA_EHIP, now);
