@@ -177,6 +177,9 @@ def main():
     ap.add_argument("--serve-counts", type=str, default="200,600,2000",
                     help="requests at 50,200,800 QPS")
     ap.add_argument("--serve-modes", type=str, default="device,host")
+    ap.add_argument("--calib-gib", type=float, default=0.0,
+                    help="run y = 2 x over this many GiB (FP32) before timing: a reference of "
+                         "known traffic for HBM byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
@@ -202,6 +205,14 @@ def main():
     log(f"generated in {time.time() - t0:.1f}s")
     xbytes = X.numel() * X.element_size()
     stream = torch.cuda.current_stream()
+    if args.calib_gib > 0:
+        cnt = int(args.calib_gib * 2 ** 30) // 4
+        a = torch.ones(cnt, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 2.0, out=b)           # reads and writes calib_gib GiB once
+        torch.cuda.synchronize()
+        del a, b
 
     def step(timing):
         V, s = lib.fit(X, k, cfg["kind"], cfg["omega_seed"], timing=timing, sparse_p=cfg.get("p", 64))

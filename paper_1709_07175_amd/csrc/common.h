@@ -64,8 +64,22 @@ __device__ inline void xcd_map(int &bx, int &by, int &bz) {
   }
   bz = logical / per;
   const int t = logical - bz * per;
-  by = t / X;
-  bx = t - by * X;
+  bx = t / Y;                                      // tiles sharing a column slice of B
+  by = t - bx * Y;                                 // (same bx) run back to back
+}
+
+// 1-D launch of T = tiles_slow * tiles_fast output tiles: XCD x (workgroups
+// b = x, x + 8, ...; the dispatcher deals workgroups to the 8 XCDs in turn)
+// takes the contiguous range [x q + min(x, r), ...) of tile numbers, q = T / 8,
+// r = T % 8, in order, fast index fastest. The tiles_fast tiles that share
+// one block of the long operand then run back to back on one XCD and share
+// its L2. A bijection of [0, T) for every T.
+__device__ inline void xcd_linear(int64_t T, int tiles_fast, int64_t &slow, int &fast) {
+  const int64_t b = blockIdx.x;
+  const int64_t q = T / 8, r = T % 8, x = b & 7, slot = b >> 3;
+  const int64_t logical = x * q + (x < r ? x : r) + slot;
+  slow = logical / tiles_fast;
+  fast = (int)(logical - slow * tiles_fast);
 }
 
 // ------------------------------------------------------------- errors ------

@@ -170,8 +170,19 @@ __global__ __launch_bounds__(256) void k_nt(const T *__restrict__ A, int64_t lda
                                             const T *__restrict__ B, int64_t ldb,
                                             T *__restrict__ C, int64_t ldc,
                                             int64_t M, int N, int K, T alpha, T beta) {
-  nt_tile<T, BM, BN, BK, WGM, WGN, VEC>(A, lda, B, ldb, C, ldc, M, N, K, alpha, beta,
-                                        (int64_t)blockIdx.x * BM, (int)blockIdx.y * BN);
+  // the side with fewer tiles is the short operand, kept in L2: its tiles
+  // go fastest so that each block of the long operand is read once
+  const int64_t tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+  int64_t tm, tn;
+  int f;
+  if (tiles_n <= tiles_m) {
+    xcd_linear(tiles_m * tiles_n, (int)tiles_n, tm, f);
+    tn = f;
+  } else {
+    xcd_linear(tiles_m * tiles_n, (int)tiles_m, tn, f);
+    tm = f;
+  }
+  nt_tile<T, BM, BN, BK, WGM, WGN, VEC>(A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, tm * BM, (int)tn * BN);
 }
 
 // --------------------------------------------------------------------- TN --
@@ -305,9 +316,10 @@ template <typename T> static bool vec_ok(const void *p, int64_t ld, int64_t exte
 template <typename T, int BM, int BN, int BK, int WGM, int WGN>
 static int nt_typed(const T *A, int64_t lda, const T *B, int64_t ldb, T *C, int64_t ldc,
                     int64_t M, int N, int K, T alpha, T beta, hipStream_t s) {
-  dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN));
-  if (grid.x == 0 || grid.y == 0) return LSPCA_OK;
-  if ((M + BM - 1) / BM > 0x7fffffff) {
+  const int64_t tiles = (M + BM - 1) / BM * ((N + BN - 1) / BN);
+  dim3 grid((unsigned)tiles);
+  if (tiles == 0) return LSPCA_OK;
+  if (tiles > 0x7fffffff) {
     set_error("nt product: too many row tiles");
     return LSPCA_EINVAL;
   }
