@@ -201,6 +201,7 @@ static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool wan
   if (p.h16) {
     p.bytes += 2 * ws_bytes<uint16_t>((size_t)p.stripe * k);                    // Yh, Yl
     p.bytes += ws_bytes<unsigned>(k) + ws_bytes<float>(k) + ws_bytes<double>(k);  // FP16 scales
+    p.bytes += ws_bytes<unsigned>((size_t)nt16_row_tiles(p.stripe) * k);           // tile maxima
     p.bytes += ws_bytes<int>(4);                                                 // flags
     if (want_g)
       p.bytes += ws_bytes<double>((size_t)n * k)      // Omega^T in FP64 (the values used)
@@ -221,7 +222,7 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
   void *Y = ws.take<char>(pl.esz * (size_t)pl.stripe * k);
   void *PF = ws.take<char>(pl.esz * tn_partial_elems(k, (int)n, pl.splits_f));
   void *PG = pl.splits_g ? ws.take<char>(pl.esz * tn_partial_elems(k, k, pl.splits_g)) : nullptr;
-  unsigned *colmax = nullptr;
+  unsigned *colmax = nullptr, *colpart = nullptr;
   float *scale = nullptr;
   double *inv = nullptr, *OmT64 = nullptr, *Fs = nullptr;
   int *flags = nullptr;
@@ -230,6 +231,7 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
     Yh = ws.take<uint16_t>((size_t)pl.stripe * k);
     Yl = ws.take<uint16_t>((size_t)pl.stripe * k);
     colmax = ws.take<unsigned>(k);
+    colpart = ws.take<unsigned>((size_t)nt16_row_tiles(pl.stripe) * k);
     scale = ws.take<float>(k);
     inv = ws.take<double>(k);
     flags = ws.take<int>(4);
@@ -278,7 +280,8 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
                                        Yh, Ylo, flags, s));
       } else {
         LSPCA_TRY(launch_nt16(xdt, Xs, ldx, OmT, nullptr, n, fp16 ? (float *)Y : nullptr, rows, rows,
-                              k, (int)n, fp16 ? colmax : nullptr, Yh, Ylo, fp16 ? 1 : 2, s));
+                              k, (int)n, fp16 ? colpart : nullptr, Yh, Ylo, fp16 ? 1 : 2, s));
+        if (fp16) LSPCA_TRY(launch_colmax_reduce(colpart, nt16_row_tiles(rows), k, colmax, s));
       }
       if (fp16) {
         LSPCA_TRY(launch_col_scales(colmax, k, scale, inv, s));

@@ -157,7 +157,8 @@ int launch_tn(lspca_dtype dt, const void *A, int64_t lda, const void *B,
               hipStream_t s, int64_t ldp = 0, double alpha = 1.0, double beta = 0.0);
 int tn_pick_splits(int64_t rows, int Mi, int Nj);
 // 16-bit products (gemm16.hip). nt16 output mode: 0 row-major FP32 C;
-// 1 transposed FP32 C[c*ldc + r] with max |C| per column (colmax); 2
+// 1 transposed FP32 C[c*ldc + r] with max |C| per column of each 128-row
+// tile (colmax[tile][c], see nt16_row_tiles); 2
 // transposed and split into 16-bit parts Ch, Cl (Cl may be NULL). B_lo
 // (split second operand) only with mode 0.
 int launch_nt16(lspca_dtype dt, const void *A, int64_t lda, const void *Bh,
@@ -171,6 +172,10 @@ int launch_tn16(lspca_dtype dt, const void *Yh, const void *Yl, int64_t ldyt,
 // Scale row c of Yt (rows_k x ld) by scale[c] and split into 16-bit parts.
 int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld,
                    const float *scale, void *Yh, void *Yl, hipStream_t s);
+// Row tiles of launch_nt16 (mode 1 writes one column-max row per tile) and
+// the reduction of those rows into colmax (zeroed by the caller).
+int nt16_row_tiles(int64_t M);
+int launch_colmax_reduce(const unsigned *part, int64_t tiles, int N, unsigned *colmax, hipStream_t s);
 int launch_col_scales(const unsigned *colmax, int k, float *scale, double *inv,
                       hipStream_t s);
 // Very sparse sketch by gather-adds (sparse.hip).

@@ -46,10 +46,20 @@ __device__ inline int mrow(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >>
 // Tile BM x BN x 32, 4 waves as 2 x 2. VEC: 16-byte global loads (K % 8 == 0,
 // 16-byte aligned rows); otherwise element loads.
 // Output modes: OUT_ROWS: C row-major FP32 (ldc); OUT_T32: C transposed,
-// C[c*ldc + r], FP32, with max |C| per column in colmax; OUT_TSPLIT: the
+// C[c*ldc + r], FP32, with max |C| per column of each BM-row tile in
+// colmax[tile][c] (bit patterns; NULL skips it); OUT_TSPLIT: the
 // transposed result split into 16-bit parts Ch = rn(C), Cl = rn(C - Ch)
 // (Cl may be NULL), each [c*ldc + r].
 enum { OUT_ROWS = 0, OUT_T32 = 1, OUT_TSPLIT = 2 };
+
+// Register stages of the K-tile prefetch in the 16-bit NT product, and the
+// K depth of its tiles.
+#ifndef LSPCA_NT16_STAGES
+#define LSPCA_NT16_STAGES 3
+#endif
+#ifndef LSPCA_NT16_BK
+#define LSPCA_NT16_BK 64
+#endif
 
 // One BM x BN tile of C at (m0, n0); the LDS it stages through is free
 // again on return, so a workgroup may call it for several tiles in turn.
@@ -61,7 +71,10 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
                                           int K, unsigned *__restrict__ colmax,
                                           uint16_t *__restrict__ Ch, uint16_t *__restrict__ Cl,
                                           const int64_t m0, const int n0) {
-  constexpr int BK = 32, LD = BK + 8;                 // +16 bytes per row of a tile
+  // K depth of a tile: LSPCA_NT16_BK where two LDS buffers fit, else 32
+  constexpr int BKW = LSPCA_NT16_BK;
+  constexpr int BK = (BM + (SPLITB ? 2 : 1) * BN) * (BKW + 8) * 2 * 2 <= 160 * 1024 ? BKW : 32;
+  constexpr int LD = BK + 8;                          // +16 bytes per row of a tile
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
   constexpr int AV = BM * BK / 8 / 256, BV = BN * BK / 8 / 256;
   static_assert(AV >= 1 && BV >= 1, "tile too small");
@@ -71,46 +84,66 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave >> 1) * WM, wn0 = (wave & 1) * WN;
 
-  u16x8 ra[AV], rbh[BV], rbl[SPLITB ? BV : 1];
+  // R register stages: the loads of K tile t + R are issued while tile t is
+  // multiplied, so each load has R tile steps to arrive
+  constexpr int R = LSPCA_NT16_STAGES;
+  u16x8 ra[R][AV], rbh[R][BV], rbl[R][SPLITB ? BV : 1];
+  // VEC: loads are issued unconditionally from clamped addresses (a row
+  // past M or N only feeds outputs that are never written), so nothing
+  // consumes a load before its stage is stored to LDS and the loads of
+  // later stages stay in flight; pieces past K are zeroed at the store.
+  const int64_t mlast = M - 1;
+  const int nlast = N - 1;
   auto ld8 = [&](const uint16_t *p, bool ok, int kleft) -> u16x8 {
     u16x8 x = {};
     if (ok) {
-      if constexpr (VEC) {
-        x = *(const u16x8 *)p;
-      } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) x[e] = e < kleft ? p[e] : (uint16_t)0;
-      }
+      for (int e = 0; e < 8; ++e) x[e] = e < kleft ? p[e] : (uint16_t)0;
     }
     return x;
   };
-  auto load = [&](int k0) {
+  auto load = [&](int sl, int k0) {
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
       const int idx = tid + v * 256, r = idx / (BK / 8), kc = (idx % (BK / 8)) * 8;
       const int64_t gr = m0 + r;
-      ra[v] = ld8(A + gr * lda + k0 + kc, gr < M && k0 + kc < K, K - k0 - kc);
+      if constexpr (VEC) {
+        const int kk = k0 + kc < K ? k0 + kc : K - 8;
+        ra[sl][v] = *(const u16x8 *)(A + (gr < M ? gr : mlast) * lda + kk);
+      } else {
+        ra[sl][v] = ld8(A + gr * lda + k0 + kc, gr < M && k0 + kc < K, K - k0 - kc);
+      }
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
       const int idx = tid + v * 256, r = idx / (BK / 8), kc = (idx % (BK / 8)) * 8;
       const int gn = n0 + r;
-      const bool ok = gn < N && k0 + kc < K;
-      rbh[v] = ld8(Bh + (int64_t)gn * ldb + k0 + kc, ok, K - k0 - kc);
-      if constexpr (SPLITB) rbl[v] = ld8(Bl + (int64_t)gn * ldb + k0 + kc, ok, K - k0 - kc);
+      if constexpr (VEC) {
+        const int kk = k0 + kc < K ? k0 + kc : K - 8;
+        const int64_t off = (int64_t)(gn < N ? gn : nlast) * ldb + kk;
+        rbh[sl][v] = *(const u16x8 *)(Bh + off);
+        if constexpr (SPLITB) rbl[sl][v] = *(const u16x8 *)(Bl + off);
+      } else {
+        const bool ok = gn < N && k0 + kc < K;
+        rbh[sl][v] = ld8(Bh + (int64_t)gn * ldb + k0 + kc, ok, K - k0 - kc);
+        if constexpr (SPLITB) rbl[sl][v] = ld8(Bl + (int64_t)gn * ldb + k0 + kc, ok, K - k0 - kc);
+      }
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int sl, int buf, int k0) {
+    const u16x8 z = {};
+    const bool tail = VEC && k0 + BK > K;          // uniform: the last, partial K tile
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
       const int idx = tid + v * 256, r = idx / (BK / 8), kc = (idx % (BK / 8)) * 8;
-      *(u16x8 *)&As[buf][r * LD + kc] = ra[v];
+      *(u16x8 *)&As[buf][r * LD + kc] = (tail && k0 + kc >= K) ? z : ra[sl][v];
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
       const int idx = tid + v * 256, r = idx / (BK / 8), kc = (idx % (BK / 8)) * 8;
-      *(u16x8 *)&Bs[buf][r * LD + kc] = rbh[v];
-      if constexpr (SPLITB) *(u16x8 *)&Bs[buf][(BN + r) * LD + kc] = rbl[v];
+      const bool zero = tail && k0 + kc >= K;
+      *(u16x8 *)&Bs[buf][r * LD + kc] = zero ? z : rbh[sl][v];
+      if constexpr (SPLITB) *(u16x8 *)&Bs[buf][(BN + r) * LD + kc] = zero ? z : rbl[sl][v];
     }
   };
 
@@ -120,13 +153,7 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = {};
 
-  const int nk = (K + BK - 1) / BK;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) load((kt + 1) * BK);
+  auto mma = [&](int cur) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       const int ko = kk + 8 * (lane >> 5);
@@ -149,10 +176,40 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
           for (int j = 0; j < TN; ++j) acc[i][j] = H16<DT>::mfma(a[i], b[j], acc[i][j]);
       }
     }
-    if (kt + 1 < nk) store(cur ^ 1);
+  };
+
+  // Tile t lives in stage t % R. Steady state (groups of R steps) is
+  // branch-free: the refill index is clamped to the last tile and the store
+  // of the next tile always happens (a store past the end is never read),
+  // so the compiler can count outstanding loads exactly.
+  const int nk = (K + BK - 1) / BK;
+#pragma unroll
+  for (int sl = 0; sl < R; ++sl) load(sl, (sl < nk ? sl : nk - 1) * BK);
+  store(0, 0, 0);
+  __syncthreads();
+  int kt0 = 0;
+  for (; kt0 + R <= nk; kt0 += R) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const int kt = kt0 + u, cur = kt & 1;
+      const int refill = kt + R < nk ? kt + R : nk - 1;
+      load(u, refill * BK);                       // stage u's tile kt is already in LDS
+      mma(cur);
+      store((u + 1) % R, cur ^ 1, (kt + 1) * BK);
+      __syncthreads();
+    }
+  }
+  // the last nk % R tiles are already loaded
+#pragma unroll
+  for (int u = 0; u < R - 1; ++u) {
+    const int kt = kt0 + u;
+    if (kt >= nk) break;
+    mma(kt & 1);
+    if (kt + 1 < nk) store((u + 1) % R, (kt & 1) ^ 1, (kt + 1) * BK);
     __syncthreads();
   }
 
+  float cm[TN];
 #pragma unroll
   for (int j = 0; j < TN; ++j) {
     const int c = n0 + wn0 + j * 32 + (lane & 31);
@@ -208,8 +265,25 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
         }
       }
     }
-    if constexpr (OUT == OUT_T32)
-      if (colmax && c < N) atomicMax(colmax + c, __float_as_uint(cmax));
+    if constexpr (OUT == OUT_T32) cm[j] = cmax;
+  }
+  if constexpr (OUT == OUT_T32) {
+    // this tile's column maxima: lanes l and l + 32 hold one column, the two
+    // waves of a column half meet in LDS; one plain store per column into
+    // the partial row of this row tile (no atomics)
+    if (colmax) {
+      float *red = reinterpret_cast<float *>(&As[0][0]);   // 2 x BN floats
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const float mj = fmaxf(cm[j], __shfl_xor(cm[j], 32));
+        if (lane < 32) red[(wave >> 1) * BN + wn0 + j * 32 + lane] = mj;
+      }
+      __syncthreads();
+      for (int t = tid; t < BN; t += 256)
+        if (n0 + t < N)
+          colmax[(m0 / BM) * (int64_t)N + n0 + t] = __float_as_uint(fmaxf(red[t], red[BN + t]));
+    }
   }
 }
 
@@ -545,6 +619,27 @@ __global__ void k_col_scales(const unsigned *colmax, int k, float *scale, double
   }
   scale[c] = ldexpf(1.f, e);
   inv[c] = ldexp(1.0, -e);
+}
+
+// colmax[c] = max over row tiles t of part[t][c] (bit patterns of
+// non-negative floats compare as unsigned integers); colmax zeroed first.
+__global__ void k_colmax_reduce(const unsigned *__restrict__ part, int64_t tiles, int N,
+                                unsigned *__restrict__ colmax) {
+  for (int c = threadIdx.x; c < N; c += blockDim.x) {
+    unsigned m = 0;
+    for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) m = max(m, part[t * N + c]);
+    atomicMax(colmax + c, m);
+  }
+}
+
+int nt16_row_tiles(int64_t M) { return (int)((M + 127) / 128); }
+
+int launch_colmax_reduce(const unsigned *part, int64_t tiles, int N, unsigned *colmax, hipStream_t s) {
+  const unsigned grid = (unsigned)(tiles < 512 ? tiles : 512);
+  if (grid == 0) return LSPCA_OK;
+  hipLaunchKernelGGL(k_colmax_reduce, grid, 256, 0, s, part, tiles, N, colmax);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
 }
 
 int launch_col_scales(const unsigned *colmax, int k, float *scale, double *inv, hipStream_t s) {
