@@ -316,25 +316,40 @@ __global__ void k_split16(const float *__restrict__ Yt, int64_t count, int64_t l
 }
 
 // ------------------------------------------------------------------- TN16 --
-// Tile: BM (columns of Y) x 128 (columns of X) x 32 rows; 4 waves as 2 x 2.
+// Tile: BM (columns of Y) x 128 (columns of X) x BK rows; 4 waves as 2 x 2.
 // Y arrives transposed and already split into 16-bit parts, Yh[i][r] and
 // Yl[i][r] (leading dimension ldyt, rows contiguous; Yl NULL without
 // refinement), so its tiles go to LDS with 16-byte copies. X (16-bit rows,
-// leading dimension ldx): each thread loads 2 rows x 8 columns and
-// transposes them in registers into eight 2-row pieces of the column-major
-// LDS tile Bs[j][r]. Both LDS tiles are row-index contiguous, so every MFMA
-// fragment is one 16-byte read.
-template <int DT, int BM, bool REFINE>
+// leading dimension ldx): each thread loads pieces of 2 rows x 8 columns
+// and transposes them in registers into eight 2-row pieces of the
+// column-major LDS tile Bs[j][r]. Both LDS tiles are row-index contiguous,
+// so every MFMA fragment is one 16-byte read.
+// VEC (16-byte aligned rows, ldyt, ldx and Nj multiples of 8): loads are
+// issued unconditionally from clamped addresses and rows past the chunk are
+// zeroed at the LDS store, so the steady-state loop is branch-free and
+// LSPCA_TN16_STAGES register stages of K tiles stay in flight.
+#ifndef LSPCA_TN16_STAGES
+#define LSPCA_TN16_STAGES 3
+#endif
+#ifndef LSPCA_TN16_BK
+#define LSPCA_TN16_BK 64
+#endif
+
+template <int DT, int BM, bool REFINE, bool VEC>
 __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
                                               const uint16_t *__restrict__ Yl, int64_t ldyt,
                                               const uint16_t *__restrict__ X, int64_t ldx,
                                               float *__restrict__ P, int64_t rows, int Mi, int Nj,
                                               int64_t chunk) {
-  constexpr int BN = 128, BK = 32, LD = BK + 8;
-  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
   constexpr int NPART = REFINE ? 2 : 1;
+  constexpr int BN = 128, BKW = LSPCA_TN16_BK;
+  constexpr int BK = (NPART * BM + BN) * (BKW + 8) * 2 * 2 <= 160 * 1024 ? BKW : 32;
+  constexpr int LD = BK + 8;
+  constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
   constexpr int AV = BM * BK / 8 / 256;               // u16x8 loads per part per thread
-  static_assert(BN * BK / 16 == 256, "one 2x8 piece of X per thread");
+  constexpr int XP = BN * BK / 16 / 256;              // 2 x 8 pieces of X per thread
+  constexpr int R = LSPCA_TN16_STAGES;
+  static_assert(XP >= 1 && AV >= 1, "tile too small");
   __shared__ uint16_t As[2][NPART * BM * LD];
   __shared__ uint16_t Bs[2][BN * LD];
 
@@ -345,13 +360,10 @@ __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
   const int j0 = bx * BN, i0 = by * BM;
   const int64_t rbeg = (int64_t)bz * chunk;
   const int64_t rend = rbeg + chunk < rows ? rbeg + chunk : rows;
-  const bool yvec = (ldyt & 7) == 0 && ((uintptr_t)Yh & 15) == 0 && (!REFINE || ((uintptr_t)Yl & 15) == 0);
-  const bool xvec = (ldx & 7) == 0 && ((uintptr_t)X & 15) == 0;
-  const int xp = tid & 15, xg = tid >> 4;  // X piece: rows 2xp, 2xp+1; columns 8xg..+7
 
-  u16x8 ra[NPART][AV];
-  u16x8 rb[2];
-  auto load = [&](int64_t r0) {
+  u16x8 ra[R][NPART][AV];
+  u16x8 rb[R][XP][2];
+  auto load = [&](int sl, int64_t r0) {
 #pragma unroll
     for (int part = 0; part < NPART; ++part) {
       const uint16_t *Ysrc = part ? Yl : Yh;
@@ -359,48 +371,74 @@ __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
       for (int v = 0; v < AV; ++v) {
         const int idx = tid + v * 256, i = idx / (BK / 8), kr = (idx % (BK / 8)) * 8;
         const int64_t gr = r0 + kr;
-        u16x8 x = {};
-        if (i0 + i < Mi) {
-          const uint16_t *src = Ysrc + (int64_t)(i0 + i) * ldyt + gr;
-          if (yvec && gr + 7 < rend) {
-            x = *(const u16x8 *)src;
-          } else {
+        if constexpr (VEC) {
+          const int ii = i0 + i < Mi ? i0 + i : Mi - 1;
+          const int64_t rr = gr + 8 <= ldyt ? gr : ldyt - 8;
+          ra[sl][part][v] = *(const u16x8 *)(Ysrc + (int64_t)ii * ldyt + rr);
+        } else {
+          u16x8 x = {};
+          if (i0 + i < Mi) {
+            const uint16_t *src = Ysrc + (int64_t)(i0 + i) * ldyt + gr;
 #pragma unroll
             for (int e = 0; e < 8; ++e) x[e] = gr + e < rend ? src[e] : (uint16_t)0;
           }
+          ra[sl][part][v] = x;
         }
-        ra[part][v] = x;
       }
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t gr = r0 + 2 * xp + h;
+    for (int p = 0; p < XP; ++p) {
+      const int pidx = tid + p * 256, xp = pidx % (BK / 2), xg = pidx / (BK / 2);
       const int c = j0 + 8 * xg;
-      u16x8 x = {};
-      if (gr < rend) {
-        const uint16_t *src = X + gr * ldx + c;
-        if (xvec && c + 7 < Nj) {
-          x = *(const u16x8 *)src;
-        } else {
 #pragma unroll
-          for (int e = 0; e < 8; ++e) x[e] = c + e < Nj ? src[e] : (uint16_t)0;
+      for (int h = 0; h < 2; ++h) {
+        const int64_t gr = r0 + 2 * xp + h;
+        if constexpr (VEC) {
+          const int64_t rr = gr < rows ? gr : rows - 1;
+          const int cc = c < Nj ? c : Nj - 8;
+          rb[sl][p][h] = *(const u16x8 *)(X + rr * ldx + cc);
+        } else {
+          u16x8 x = {};
+          if (gr < rend) {
+            const uint16_t *src = X + gr * ldx + c;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = c + e < Nj ? src[e] : (uint16_t)0;
+          }
+          rb[sl][p][h] = x;
         }
       }
-      rb[h] = x;
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](int sl, int buf, int64_t r0) {
+    const bool tail = VEC && r0 + BK > rend;            // uniform: the chunk's last K tile
 #pragma unroll
     for (int part = 0; part < NPART; ++part)
 #pragma unroll
       for (int v = 0; v < AV; ++v) {
         const int idx = tid + v * 256, i = idx / (BK / 8), kr = (idx % (BK / 8)) * 8;
-        *(u16x8 *)&As[buf][(part * BM + i) * LD + kr] = ra[part][v];
+        u16x8 x = ra[sl][part][v];
+        if (tail) {
+          const int64_t gr = r0 + kr;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) x[e] = gr + e < rend ? x[e] : (uint16_t)0;
+        }
+        *(u16x8 *)&As[buf][(part * BM + i) * LD + kr] = x;
       }
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const uint32_t w = (uint32_t)rb[0][e] | ((uint32_t)rb[1][e] << 16);
-      *(uint32_t *)&Bs[buf][(8 * xg + e) * LD + 2 * xp] = w;
+    for (int p = 0; p < XP; ++p) {
+      const int pidx = tid + p * 256, xp = pidx % (BK / 2), xg = pidx / (BK / 2);
+      u16x8 lo = rb[sl][p][0], hi = rb[sl][p][1];
+      if (tail) {
+        const int64_t gr = r0 + 2 * xp;
+        const u16x8 z = {};
+        lo = gr < rend ? lo : z;
+        hi = gr + 1 < rend ? hi : z;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const uint32_t w = (uint32_t)lo[e] | ((uint32_t)hi[e] << 16);
+        *(uint32_t *)&Bs[buf][(8 * xg + e) * LD + 2 * xp] = w;
+      }
     }
   };
 
@@ -410,15 +448,7 @@ __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = {};
 
-  const int64_t nt = rend > rbeg ? (rend - rbeg + BK - 1) / BK : 0;
-  if (nt > 0) {
-    load(rbeg);
-    store(0);
-  }
-  __syncthreads();
-  for (int64_t t = 0; t < nt; ++t) {
-    const int cur = (int)(t & 1);
-    if (t + 1 < nt) load(rbeg + (t + 1) * BK);
+  auto mma = [&](int cur) {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 16) {
       const int ko = kk + 8 * (lane >> 5);
@@ -437,8 +467,37 @@ __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
           for (int j = 0; j < TN; ++j) acc[i][j] = H16<DT>::mfma(a[i], b[j], acc[i][j]);
       }
     }
-    if (t + 1 < nt) store(cur ^ 1);
+  };
+
+  const int64_t nt = rend > rbeg ? (rend - rbeg + BK - 1) / BK : 0;
+  if (nt > 0) {
+    // tile t lives in stage t % R; steady state branch-free (refill index
+    // clamped to the last tile, the next tile's store always made)
+#pragma unroll
+    for (int sl = 0; sl < R; ++sl) load(sl, rbeg + (sl < nt ? sl : nt - 1) * BK);
+    store(0, 0, rbeg);
     __syncthreads();
+    int64_t t0 = 0;
+    for (; t0 + R <= nt; t0 += R) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int64_t t = t0 + u;
+        const int cur = (int)(t & 1);
+        const int64_t refill = t + R < nt ? t + R : nt - 1;
+        load(u, rbeg + refill * BK);
+        mma(cur);
+        store((u + 1) % R, cur ^ 1, rbeg + (t + 1) * BK);
+        __syncthreads();
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R - 1; ++u) {
+      const int64_t t = t0 + u;
+      if (t >= nt) break;
+      mma((int)(t & 1));
+      if (t + 1 < nt) store((u + 1) % R, (int)(t & 1) ^ 1, rbeg + (t + 1) * BK);
+      __syncthreads();
+    }
   }
 
   float *Pz = P + (int64_t)bz * Mi * Nj;
@@ -574,9 +633,14 @@ static int tn16_typed(const uint16_t *Yh, const uint16_t *Yl, int64_t ldyt, cons
                       int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
                       hipStream_t s) {
   int64_t chunk = (rows + splits - 1) / splits;
-  chunk = (chunk + 31) / 32 * 32;
+  chunk = (chunk + 63) / 64 * 64;                 // a multiple of every K-tile depth
   dim3 grid((unsigned)((Nj + 127) / 128), (unsigned)((Mi + BM - 1) / BM), (unsigned)splits);
-  hipLaunchKernelGGL((k_tn16<DT, BM, REFINE>), grid, dim3(256), 0, s, Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, chunk);
+  const bool vec = (ldyt % 8 == 0) && ((uintptr_t)Yh % 16 == 0) && (!REFINE || (uintptr_t)Yl % 16 == 0) &&
+                   (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0) && (Nj % 8 == 0) && Nj >= 8 && ldyt >= 8;
+  if (vec)
+    hipLaunchKernelGGL((k_tn16<DT, BM, REFINE, true>), grid, dim3(256), 0, s, Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, chunk);
+  else
+    hipLaunchKernelGGL((k_tn16<DT, BM, REFINE, false>), grid, dim3(256), 0, s, Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, chunk);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }

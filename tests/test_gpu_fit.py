@@ -24,6 +24,10 @@ PASS_CASES = [
     (3001, 520, 136, "bf16"),
     (1037, 203, 17, "f16"),
     (2999, 512, 64, "f16"),
+    # m and n multiples of 8: the 16-bit vector-load paths, split-row chunk tails
+    (4000, 512, 64, "bf16"),
+    (3008, 520, 136, "f16"),
+    (6000, 256, 256, "bf16"),
 ]
 
 
