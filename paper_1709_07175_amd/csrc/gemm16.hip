@@ -335,20 +335,22 @@ __global__ void k_split16(const float *__restrict__ Yt, int64_t count, int64_t l
 #define LSPCA_TN16_BK 64
 #endif
 
-template <int DT, int BM, bool REFINE, bool VEC>
+template <int DT, int BM, int BN, bool REFINE, bool VEC>
 __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
                                               const uint16_t *__restrict__ Yl, int64_t ldyt,
                                               const uint16_t *__restrict__ X, int64_t ldx,
                                               float *__restrict__ P, int64_t rows, int Mi, int Nj,
                                               int64_t chunk) {
   constexpr int NPART = REFINE ? 2 : 1;
-  constexpr int BN = 128, BKW = LSPCA_TN16_BK;
+  constexpr int BKW = LSPCA_TN16_BK;
   constexpr int BK = (NPART * BM + BN) * (BKW + 8) * 2 * 2 <= 160 * 1024 ? BKW : 32;
   constexpr int LD = BK + 8;
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
   constexpr int AV = BM * BK / 8 / 256;               // u16x8 loads per part per thread
   constexpr int XP = BN * BK / 16 / 256;              // 2 x 8 pieces of X per thread
-  constexpr int R = LSPCA_TN16_STAGES;
+  // register stages: one fewer for the wide refined tile (its ring would not
+  // fit the register file next to the accumulators)
+  constexpr int R = (BN > 128 && REFINE && LSPCA_TN16_STAGES > 2) ? 2 : LSPCA_TN16_STAGES;
   static_assert(XP >= 1 && AV >= 1, "tile too small");
   __shared__ uint16_t As[2][NPART * BM * LD];
   __shared__ uint16_t Bs[2][BN * LD];
@@ -628,19 +630,29 @@ int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld, 
   return LSPCA_OK;
 }
 
+// X-column tile: 256 when the Y side is one 128-column tile (halves the
+// re-reads of Y per X column), else 128.
+#ifndef LSPCA_TN16_WIDE_BN
+#define LSPCA_TN16_WIDE_BN 256
+#endif
+#ifndef LSPCA_TN16_WIDE_ALL
+#define LSPCA_TN16_WIDE_ALL 0
+#endif
+
 template <int DT, int BM, bool REFINE>
 static int tn16_typed(const uint16_t *Yh, const uint16_t *Yl, int64_t ldyt, const uint16_t *X,
                       int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
                       hipStream_t s) {
+  constexpr int BN = (BM <= 128 || LSPCA_TN16_WIDE_ALL) ? LSPCA_TN16_WIDE_BN : 128;
   int64_t chunk = (rows + splits - 1) / splits;
   chunk = (chunk + 63) / 64 * 64;                 // a multiple of every K-tile depth
-  dim3 grid((unsigned)((Nj + 127) / 128), (unsigned)((Mi + BM - 1) / BM), (unsigned)splits);
+  dim3 grid((unsigned)((Nj + BN - 1) / BN), (unsigned)((Mi + BM - 1) / BM), (unsigned)splits);
   const bool vec = (ldyt % 8 == 0) && ((uintptr_t)Yh % 16 == 0) && (!REFINE || (uintptr_t)Yl % 16 == 0) &&
                    (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0) && (Nj % 8 == 0) && Nj >= 8 && ldyt >= 8;
   if (vec)
-    hipLaunchKernelGGL((k_tn16<DT, BM, REFINE, true>), grid, dim3(256), 0, s, Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, chunk);
+    hipLaunchKernelGGL((k_tn16<DT, BM, BN, REFINE, true>), grid, dim3(256), 0, s, Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, chunk);
   else
-    hipLaunchKernelGGL((k_tn16<DT, BM, REFINE, false>), grid, dim3(256), 0, s, Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, chunk);
+    hipLaunchKernelGGL((k_tn16<DT, BM, BN, REFINE, false>), grid, dim3(256), 0, s, Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, chunk);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }
