@@ -210,16 +210,42 @@ __global__ void k_to_cols(const double *__restrict__ A, int k, double *__restric
 constexpr int kLdsDoubles = 16384;   // problem size limit: k*k or 2b*k doubles
 constexpr int kLdsAlloc = 16640;     // allocation incl. padding (130 KB)
 
-// Orthogonalise columns ap and aq (length len <= 16 * ROWS, in LDS) with
-// the 16 lanes of one DPP row (gl = lane within the row). The rotation is
-// skipped when |a_p.a_q| <= tol |a_p| |a_q|; otherwise Rutishauser's
-// formulas give c, s with (c a_p - s a_q).(s a_p + c a_q) = 0.
-template <int ROWS>
+// Sum over G lanes (16: one DPP row; 32, 64: rows combined by lane
+// exchanges). Every lane receives the same bits (each step adds the same
+// two values in either order).
+template <int G> __device__ inline double sum_lanes(double v) {
+  v = sum16(v);
+  if constexpr (G >= 32) v += __shfl_xor(v, 16);
+  if constexpr (G >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Rotation of a column pair from its Gram entries al = |a_p|^2,
+// be = |a_q|^2, ga = a_p.a_q. False (no rotation) when
+// |ga| <= tol |a_p| |a_q|; otherwise Rutishauser's formulas give c, s with
+// (c a_p - s a_q).(s a_p + c a_q) = 0.
+__device__ inline bool jacobi_cs(double al, double be, double ga, double tol, double &c, double &sn) {
+  // |ga| > tol sqrt(al be), squared (al, be >= 0)
+  if (!(ga != 0.0 && ga * ga > (tol * tol) * (al * be))) return false;
+  // t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)) with zeta = (be - al) / (2 ga),
+  // multiplied through by 2|ga|:
+  // t = 2 ga sgn(be - al) / (|be - al| + sqrt((be - al)^2 + 4 ga^2)).
+  const double d = be - al;
+  const double t = (d >= 0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
+  c = 1.0 / sqrt(1.0 + t * t);
+  sn = c * t;
+  return true;
+}
+
+// Orthogonalise columns ap and aq (length len <= G * ROWS, in LDS) with
+// G lanes (gl = lane within the group; rows gl + G i), the pair's entries
+// held in registers.
+template <int ROWS, int G = 16>
 __device__ inline bool rotate_pair(double *ap, double *aq, int len, int gl, double tol) {
   double x[ROWS], y[ROWS];
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
-    const int r = gl + 16 * i;
+    const int r = gl + G * i;
     x[i] = r < len ? ap[r] : 0.0;
     y[i] = r < len ? aq[r] : 0.0;
   }
@@ -230,20 +256,11 @@ __device__ inline bool rotate_pair(double *ap, double *aq, int len, int gl, doub
     be += y[i] * y[i];
     ga += x[i] * y[i];
   }
-  al = sum16(al);
-  be = sum16(be);
-  ga = sum16(ga);
-  // |ga| > tol sqrt(al be), squared (al, be >= 0)
-  if (!(ga != 0.0 && ga * ga > (tol * tol) * (al * be))) return false;
-  // Rutishauser's t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)) with
-  // zeta = (be - al) / (2 ga), multiplied through by 2|ga|:
-  // t = 2 ga sgn(be - al) / (|be - al| + sqrt((be - al)^2 + 4 ga^2)).
-  const double d = be - al;
-  const double t = (d >= 0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
-  const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+  double c, sn;
+  if (!jacobi_cs(sum_lanes<G>(al), sum_lanes<G>(be), sum_lanes<G>(ga), tol, c, sn)) return false;
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
-    const int r = gl + 16 * i;
+    const int r = gl + G * i;
     if (r < len) {
       ap[r] = c * x[i] - sn * y[i];
       aq[r] = sn * x[i] + c * y[i];
@@ -252,11 +269,40 @@ __device__ inline bool rotate_pair(double *ap, double *aq, int len, int gl, doub
   return true;
 }
 
+// Any length: two passes over LDS (Gram entries, then the rotation).
+template <int G>
+__device__ inline bool rotate_long(double *ap, double *aq, int len, int gl, double tol) {
+  double al = 0, be = 0, ga = 0;
+  for (int r = gl; r < len; r += G) {
+    const double x = ap[r], y = aq[r];
+    al += x * x;
+    be += y * y;
+    ga += x * y;
+  }
+  double c, sn;
+  if (!jacobi_cs(sum_lanes<G>(al), sum_lanes<G>(be), sum_lanes<G>(ga), tol, c, sn)) return false;
+  for (int r = gl; r < len; r += G) {
+    const double x = ap[r], y = aq[r];
+    ap[r] = c * x - sn * y;
+    aq[r] = sn * x + c * y;
+  }
+  return true;
+}
+
 __device__ inline bool rotate_any(double *ap, double *aq, int len, int gl, double tol) {
   if (len <= 32) return rotate_pair<2>(ap, aq, len, gl, tol);
   if (len <= 64) return rotate_pair<4>(ap, aq, len, gl, tol);
   if (len <= 128) return rotate_pair<8>(ap, aq, len, gl, tol);
-  return rotate_pair<16>(ap, aq, len, gl, tol);
+  if (len <= 256) return rotate_pair<16>(ap, aq, len, gl, tol);
+  return rotate_long<16>(ap, aq, len, gl, tol);
+}
+
+// The same with a whole wave (64 lanes) per pair.
+__device__ inline bool rotate_any64(double *ap, double *aq, int len, int gl, double tol) {
+  if (len <= 128) return rotate_pair<2, 64>(ap, aq, len, gl, tol);
+  if (len <= 256) return rotate_pair<4, 64>(ap, aq, len, gl, tol);
+  if (len <= 512) return rotate_pair<8, 64>(ap, aq, len, gl, tol);
+  return rotate_long<64>(ap, aq, len, gl, tol);
 }
 
 // Round-robin pair (i-th of round s) over nc' = even(nc) columns:
@@ -339,7 +385,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double *Wc, int k, int b,
   }
   if (threadIdx.x == 0) counter = 0;
   __syncthreads();
-  const int g = threadIdx.x >> 4, gl = threadIdx.x & 15, ng = blockDim.x >> 4;
+  // one wave per column pair
+  const int g = threadIdx.x >> 6, gl = threadIdx.x & 63, ng = blockDim.x >> 6;
   if (round == 0) {
     // pairs inside I and inside J: two interleaved round-robins
     const int bp = (max(ni, nj) + 1) & ~1, Lb = bp - 1, half = bp / 2;
@@ -350,7 +397,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double *Wc, int k, int b,
         int p, q;
         rr_pair(s, i, Lb, p, q);
         if (p < nside && q < nside) {
-          if (rotate_any(cols + (base + min(p, q)) * ld, cols + (base + max(p, q)) * ld, k, gl, tol) &&
+          if (rotate_any64(cols + (base + min(p, q)) * ld, cols + (base + max(p, q)) * ld, k, gl, tol) &&
               gl == 0)
             atomicAdd(&counter, 1);
         }
@@ -363,7 +410,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double *Wc, int k, int b,
     for (int i = g; i < bb; i += ng) {
       const int j = i + s - (i + s >= bb ? bb : 0);
       if (i < ni && j < nj) {
-        if (rotate_any(cols + i * ld, cols + (ni + j) * ld, k, gl, tol) && gl == 0)
+        if (rotate_any64(cols + i * ld, cols + (ni + j) * ld, k, gl, tol) && gl == 0)
           atomicAdd(&counter, 1);
       }
     }
@@ -571,8 +618,9 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
       LSPCA_HIP(hipStreamSynchronize(s));
     }
   } else {
-    // blocks of b columns, nb even, 2b padded columns of length k fit in LDS
-    const int bmax = kLdsAlloc / (2 * (k + 1));
+    // blocks of b columns, nb even, 2b padded columns of length k fit in LDS;
+    // one wave per pair, so b <= 16 pairs per round in a 1024-thread block
+    const int bmax = std::min(kLdsAlloc / (2 * (k + 1)), 16);
     if (bmax < 1) {
       set_error("jacobi: k = %d too large for the block kernel", k);
       return LSPCA_ENOTSUP;
@@ -583,7 +631,7 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
     for (int sweep = 0; sweep < 40; ++sweep) {
       LSPCA_TRY(zero_i32(dflag, 1, s));
       for (int round = 0; round < nb - 1; ++round) {
-        hipLaunchKernelGGL(k_jacobi_block, nb / 2, round_threads(b), 0, s, Wc, k, b, nb, round, tol, dflag);
+        hipLaunchKernelGGL(k_jacobi_block, nb / 2, 64 * b, 0, s, Wc, k, b, nb, round, tol, dflag);
         LSPCA_HIP(hipGetLastError());
       }
       LSPCA_HIP(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));

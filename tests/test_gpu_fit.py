@@ -188,7 +188,8 @@ def test_rank_deficient_X_gives_erank(gpu_lib):
 
 # ------------------------------------------------------------ small stage --
 
-@pytest.mark.parametrize("k,n", [(1, 9), (7, 40), (50, 1000), (128, 1500), (130, 700), (256, 4096)])
+@pytest.mark.parametrize("k,n", [(1, 9), (7, 40), (50, 1000), (128, 1500), (130, 700), (256, 4096),
+                                 (300, 700), (520, 1100)])
 def test_factor_matches_oracle_svd(gpu_lib, k, n):
     """Truncated SVD of a generated F = U diag(d) W^T with known, separated
     singular values (condition 1e3): V columns and D to 1e-10."""
