@@ -29,8 +29,9 @@
  *    process exit). Calls that overlap on one device from several host
  *    threads are serialised by a lock.
  *  - X is never centred (Sec. I-B: the SPCA subspace does not need it).
- *  - The projection server (lspca_server_*) is the one exception to
- *    "device pointers only": its requests may also live in host memory.
+ *  - Exceptions to "device pointers only": X of lspca_accumulate_host and
+ *    lspca_fit_host lives in host memory, and the projection server's
+ *    requests may.
  */
 #ifndef LSPCA_H
 #define LSPCA_H
@@ -180,6 +181,32 @@ LSPCA_API int lspca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n,
               int64_t ldx, int32_t k, lspca_omega_kind kind, uint64_t seed,
               const lspca_opts *opts, double *V, double *sigma,
               double *sigma_x);
+
+/*
+ * lspca_accumulate_host -- Algorithm 4 (Streaming Lazy SPCA) over X in
+ * HOST memory, the regime where X exceeds device memory: the rows stream
+ * through two device staging buffers of stripe_rows rows (0: about 1 GiB
+ * of X each), the copy of one stripe overlapping the pass over the
+ * previous one. F (k x n) and G (k x k or NULL) are FP64 device
+ * accumulators as in lspca_accumulate: together they are the whole state
+ * of a streaming fit, so a caller can save them after any call and resume
+ * with the remaining rows later. X should be pinned (hipHostMalloc) for
+ * full copy rate; pageable memory works, slower. Synchronous: X may be
+ * released on return. Errors as lspca_accumulate, EINVAL for device X or
+ * stripe_rows < 0.
+ */
+LSPCA_API int lspca_accumulate_host(const void *X, lspca_dtype xdt, int64_t m, int64_t n,
+                          int64_t ldx, int32_t k, lspca_omega_kind kind, uint64_t seed,
+                          const lspca_opts *opts, int64_t stripe_rows, double *F, double *G);
+
+/*
+ * lspca_fit_host -- Lazy SPCA (Algorithm 4) of X in host memory:
+ * lspca_accumulate_host over all rows, then lspca_factor. Outputs as
+ * lspca_fit (device pointers). Synchronous.
+ */
+LSPCA_API int lspca_fit_host(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx,
+                   int32_t k, lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts,
+                   int64_t stripe_rows, double *V, double *sigma, double *sigma_x);
 
 /*
  * spca_fit -- SPCA (Algorithm 1), the non-lazy baseline: Y = X Omega (pass 1,

@@ -14,6 +14,7 @@ import os
 __all__ = [
     "load", "LspcaError", "F64", "F32", "BF16", "F16", "GAUSSIAN", "VERY_SPARSE",
     "version", "omega", "accumulate", "factor", "fit", "spca_fit", "transform",
+    "accumulate_host", "fit_host",
     "last_timings", "exported_symbols", "LIB_PATH", "Server",
 ]
 
@@ -31,7 +32,7 @@ STATUS = {0: "LSPCA_OK", -1: "LSPCA_EINVAL", -2: "LSPCA_ENOMEM", -3: "LSPCA_EHIP
 # Every symbol include/lspca.h declares.
 EXPORTS = ["lspca_version", "lspca_strerror", "lspca_last_error", "lspca_last_timings",
            "lspca_omega", "lspca_accumulate", "lspca_factor", "lspca_fit", "spca_fit",
-           "lspca_transform", "lspca_server_create", "lspca_server_submit", "lspca_server_wait",
+           "lspca_transform", "lspca_accumulate_host", "lspca_fit_host", "lspca_server_create", "lspca_server_submit", "lspca_server_wait",
            "lspca_server_pause", "lspca_server_get_stats", "lspca_server_destroy"]
 
 
@@ -81,6 +82,10 @@ _SIGS = {
                   ctypes.POINTER(lspca_opts), _P, _P], ctypes.c_int),
     "lspca_transform": ([_P, ctypes.c_int, _I64, _I64, _I64, _P, _I32, _P,
                          ctypes.POINTER(lspca_opts)], ctypes.c_int),
+    "lspca_accumulate_host": ([_P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
+                               ctypes.POINTER(lspca_opts), _I64, _P, _P], ctypes.c_int),
+    "lspca_fit_host": ([_P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
+                        ctypes.POINTER(lspca_opts), _I64, _P, _P, _P], ctypes.c_int),
     "lspca_server_create": ([_P, _I64, _I32, ctypes.c_int, ctypes.c_size_t, _I32,
                              ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "lspca_server_submit": ([_P, _P, _I64, _P, ctypes.POINTER(_U64)], ctypes.c_int),
@@ -248,6 +253,41 @@ def transform(X, V, Z=None, **kw):
     _check(load().lspca_transform(X.data_ptr(), _dtype_code(X), r, n, ldx, _dev(V, "V").data_ptr(),
                                   k, Z.data_ptr(), ctypes.byref(o)))
     return Z
+
+
+def _host_rowmajor(X):
+    if X.is_cuda:
+        raise ValueError("X must be a host tensor (pinned for full copy rate)")
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be 2-D with unit column stride")
+    return X.stride(0)
+
+
+def accumulate_host(X, k, kind, seed, F, G=None, stripe_rows=0, **kw):
+    """Algorithm 4 over a host tensor X (streamed through the device):
+    F += U^T X, G += U^T U on the device accumulators (in place)."""
+    ldx = _host_rowmajor(X)
+    o = _opts(**kw)
+    _check(load().lspca_accumulate_host(X.data_ptr(), _dtype_code(X), X.shape[0], X.shape[1], ldx, k,
+                                        KIND[kind], seed, ctypes.byref(o), stripe_rows,
+                                        _dev(F, "F").data_ptr(),
+                                        _dev(G, "G").data_ptr() if G is not None else None))
+    return F, G
+
+
+def fit_host(X, k, kind="gaussian", seed=0, want_sigma_x=False, stripe_rows=0, device="cuda", **kw):
+    """Lazy SPCA (Algorithm 4) of a host tensor X: V (n x k), D (k)
+    [, Sigma^s (k)] on the device."""
+    ldx = _host_rowmajor(X)
+    m, n = X.shape
+    V = _f64_out((n, k), device)
+    s = _f64_out((k,), device)
+    sx = _f64_out((k,), device) if want_sigma_x else None
+    o = _opts(**kw)
+    _check(load().lspca_fit_host(X.data_ptr(), _dtype_code(X), m, n, ldx, k, KIND[kind], seed,
+                                 ctypes.byref(o), stripe_rows, V.data_ptr(), s.data_ptr(),
+                                 sx.data_ptr() if sx is not None else None))
+    return (V, s, sx) if want_sigma_x else (V, s)
 
 
 def last_timings():

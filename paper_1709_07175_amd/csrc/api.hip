@@ -52,9 +52,17 @@ int Workspace::ensure(size_t bytes) {
   return LSPCA_OK;
 }
 
+// Copy stream and staging events of the host-streamed pass (created on
+// first use; default priority).
+struct HostStreaming {
+  hipStream_t copy = nullptr;
+  hipEvent_t loaded[2] = {}, freed[2] = {};
+};
+
 struct DeviceState {
   std::mutex mu;
   Workspace ws;
+  HostStreaming hs;
 };
 
 static DeviceState &device_state(int dev) {
@@ -314,6 +322,68 @@ static size_t factor_bytes(int64_t n, int k) {
          ws_bytes<double>(3 * 128 * 128);
 }
 
+// Algorithm 4 over X in host memory: stripes of `stripe` rows go through two
+// device staging buffers; the copy of stripe s + 1 (copy stream) overlaps
+// the pass over stripe s (the caller's stream). F and G accumulate.
+static int host_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, int k, int kind,
+                     uint64_t seed, const Opts &o, int64_t stripe, double *F, double *G,
+                     DeviceState &st) {
+  const size_t xs = dtype_size(xdt);
+  HostStreaming &hs = st.hs;
+  if (!hs.copy) {
+    LSPCA_HIP(hipStreamCreateWithFlags(&hs.copy, hipStreamNonBlocking));
+    for (int b = 0; b < 2; ++b) {
+      LSPCA_HIP(hipEventCreateWithFlags(&hs.loaded[b], hipEventDisableTiming));
+      LSPCA_HIP(hipEventCreateWithFlags(&hs.freed[b], hipEventDisableTiming));
+    }
+  }
+  const PassPlan pl = plan_pass(xdt, stripe, n, k, G != nullptr, kind, o.p);
+  const size_t sbytes = ws_bytes<char>(xs * (size_t)stripe * n);
+  LSPCA_TRY(st.ws.ensure(2 * sbytes + pl.bytes));
+  Workspace &ws = st.ws;
+  char *stage[2] = {ws.take<char>(sbytes), ws.take<char>(sbytes)};
+  const size_t mark = ws.used;
+  hipStream_t s = o.stream;
+  PhaseTimer quiet;                                  // per-stripe phases are not recorded
+  for (int b = 0; b < 2; ++b) LSPCA_HIP(hipEventRecord(hs.freed[b], s));
+  int64_t it = 0;
+  for (int64_t r0 = 0; r0 < m; r0 += stripe, ++it) {
+    const int b = (int)(it & 1);
+    const int64_t rows = m - r0 < stripe ? m - r0 : stripe;
+    LSPCA_HIP(hipStreamWaitEvent(hs.copy, hs.freed[b], 0));
+    LSPCA_HIP(hipMemcpy2DAsync(stage[b], (size_t)n * xs, (const char *)X + (size_t)r0 * ldx * xs,
+                               (size_t)ldx * xs, (size_t)n * xs, (size_t)rows, hipMemcpyHostToDevice,
+                               hs.copy));
+    LSPCA_HIP(hipEventRecord(hs.loaded[b], hs.copy));
+    LSPCA_HIP(hipStreamWaitEvent(s, hs.loaded[b], 0));
+    ws.used = mark;
+    LSPCA_TRY(run_pass(stage[b], xdt, rows, n, n, k, kind, seed, o, F, G, pl, ws, quiet));
+    LSPCA_HIP(hipEventRecord(hs.freed[b], s));
+  }
+  // X may be released by the caller on return
+  LSPCA_HIP(hipStreamSynchronize(s));
+  return LSPCA_OK;
+}
+
+static int64_t host_stripe(int64_t m, int64_t n, lspca_dtype xdt, int64_t want) {
+  int64_t rows = want > 0 ? want : ((int64_t)1 << 30) / (n * (int64_t)dtype_size(xdt));
+  rows = (rows + 255) / 256 * 256;                   // whole tiles, vector-friendly
+  return rows < m ? rows : m;
+}
+
+static int check_host_ptr(const void *X) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, X) != hipSuccess) {
+    (void)hipGetLastError();
+    return LSPCA_OK;                                 // pageable host memory
+  }
+  if (a.type == hipMemoryTypeDevice) {
+    set_error("X is device memory: use lspca_accumulate / lspca_fit");
+    return LSPCA_EINVAL;
+  }
+  return LSPCA_OK;
+}
+
 struct Locked {
   DeviceState *st = nullptr;
   std::unique_lock<std::mutex> lk;
@@ -464,6 +534,65 @@ int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t n, int64_
   else
     LSPCA_TRY(launch_nt(xdt, X, ldx, VT, n, Z, k, r, k, (int)n, o.stream));
   tm.mark(PH_TRANSFORM);
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int lspca_accumulate_host(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx,
+                          int32_t k, lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts,
+                          int64_t stripe_rows, double *F, double *G) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  LSPCA_TRY(check_pass_args(X, xdt, m, n, ldx, k, kind, o));
+  if (!F) { set_error("F is NULL"); return LSPCA_EINVAL; }
+  if (stripe_rows < 0) { set_error("stripe_rows must be >= 0"); return LSPCA_EINVAL; }
+  LSPCA_TRY(check_host_ptr(X));
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, o.stream);
+  LSPCA_TRY(host_pass(X, xdt, m, n, ldx, k, kind, seed, o, host_stripe(m, n, xdt, stripe_rows), F, G, *L.st));
+  tm.mark(PH_FACTOR);
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int lspca_fit_host(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, int32_t k,
+                   lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts, int64_t stripe_rows,
+                   double *V, double *sigma, double *sigma_x) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  LSPCA_TRY(check_pass_args(X, xdt, m, n, ldx, k, kind, o));
+  if (!V || !sigma) { set_error("V and sigma must not be NULL"); return LSPCA_EINVAL; }
+  if (k > m) { set_error("k must satisfy k <= min(m, n) (k=%d m=%lld)", k, (long long)m); return LSPCA_EINVAL; }
+  if (stripe_rows < 0) { set_error("stripe_rows must be >= 0"); return LSPCA_EINVAL; }
+  LSPCA_TRY(check_host_ptr(X));
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  const bool want_g = sigma_x != nullptr;
+  // F and G live in their own allocation: the workspace is re-planned below
+  double *FG = nullptr;
+  const size_t fgn = (size_t)k * n + (size_t)k * k;
+  if (hipMalloc((void **)&FG, fgn * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("fit_host: hipMalloc of F and G failed");
+    return LSPCA_ENOMEM;
+  }
+  struct Free {
+    double *p;
+    ~Free() { (void)hipFree(p); }
+  } guard{FG};
+  double *F = FG, *G = FG + (size_t)k * n;
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, o.stream);
+  LSPCA_TRY(zero_f64(FG, (int64_t)fgn, o.stream));
+  LSPCA_TRY(host_pass(X, xdt, m, n, ldx, k, kind, seed, o, host_stripe(m, n, xdt, stripe_rows), F,
+                      want_g ? G : nullptr, *L.st));
+  tm.mark(PH_FACTOR);
+  LSPCA_TRY(L.st->ws.ensure(factor_bytes(n, k)));
+  int rank_flag = 0;
+  LSPCA_TRY(small_factor(F, want_g ? G : nullptr, k, n, V, sigma, sigma_x, L.st->ws, o.stream, &rank_flag));
+  tm.mark(PH_SMALL);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;
 }

@@ -122,3 +122,12 @@ def test_server_argument_checks(lib):
     st.struct_size = ctypes.sizeof(st)
     assert lib.lspca_server_get_stats(None, ctypes.byref(st)) == -1
     assert lib.lspca_server_destroy(None) == 0
+
+
+def test_host_stream_argument_checks(lib):
+    # NULL X, NULL F, negative stripe: refused before any device work
+    assert lib.lspca_accumulate_host(None, L.F32, 10, 10, 10, 3, L.GAUSSIAN, 1, None, 0, 1 << 20, None) == -1
+    assert lib.lspca_accumulate_host(1 << 20, L.F32, 10, 10, 10, 3, L.GAUSSIAN, 1, None, 0, None, None) == -1
+    assert lib.lspca_accumulate_host(1 << 20, L.F32, 10, 10, 10, 3, L.GAUSSIAN, 1, None, -5, 1 << 21, None) == -1
+    assert "stripe_rows" in lib.lspca_last_error().decode()
+    assert lib.lspca_fit_host(1 << 20, L.F32, 10, 10, 10, 11, L.GAUSSIAN, 1, None, 0, 1 << 21, 1 << 22, None) == -1
