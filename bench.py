@@ -354,6 +354,22 @@ def main():
                 "lazy_fit_speedup": round(sp_ms / fit_ms, 3),
             }
             log(f"spca_fit {sp_ms:.3f} ms vs lazy fit {fit_ms:.3f} ms")
+            # Algorithm 3: one pass with the R factor updated per stripe
+            lib.spca_fit_stream(X, k, cfg["kind"], cfg["omega_seed"], sparse_p=cfg.get("p", 64))
+            torch.cuda.synchronize()
+            ss = []
+            for _ in range(args.spca_steps):
+                lib.spca_fit_stream(X, k, cfg["kind"], cfg["omega_seed"], timing=True, sparse_p=cfg.get("p", 64))
+                ss.append(lib.last_timings())
+            ss_ms = sum(t["total_ms"] for t in ss) / len(ss)
+            out["spca_stream"] = {
+                "fit_ms": round(ss_ms, 4),
+                "fit_x_stream_GBs": round(xbytes / (ss_ms * 1e-3) / 1e9, 3),
+                "phases_ms": {key: round(sum(t[key + "_ms"] for t in ss) / len(ss), 4)
+                              for key in ("omega", "sketch", "qr", "factor", "reduce", "pass2", "small")},
+                "lazy_fit_speedup": round(ss_ms / fit_ms, 3),
+            }
+            log(f"spca_fit_stream {ss_ms:.3f} ms")
         except lib.LspcaError as e:
             out["spca"] = {"error": str(e)}
     if not args.no_host:

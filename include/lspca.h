@@ -220,6 +220,19 @@ LSPCA_API int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n,
              const lspca_opts *opts, double *V, double *sigma);
 
 /*
+ * spca_fit_stream -- Streaming SPCA (Algorithm 3), the one-pass baseline:
+ * per stripe U_s = X_s Omega, F += U_s^T X_s and R <- R of qr([R; U_s])
+ * (a tall-skinny Householder QR of U_s without Q, merged into the running
+ * R); then F = R^-T F and its truncated SVD. X is read once.
+ *  V: n x k FP64 (V^s); sigma: k FP64 (Sigma^s). Same conventions and
+ *  limits as spca_fit (k <= 256, FP64 data: k <= 128). Synchronous.
+ *  Errors: EINVAL, ENOMEM, EHIP, ERANK, ENOTSUP.
+ */
+LSPCA_API int spca_fit_stream(const void *X, lspca_dtype xdt, int64_t m, int64_t n,
+                    int64_t ldx, int32_t k, lspca_omega_kind kind, uint64_t seed,
+                    const lspca_opts *opts, double *V, double *sigma);
+
+/*
  * lspca_transform -- Z = X V, the map pi(x) = V^T x of eq.
  * (dim_reduction_maps) applied to each of the r rows of X.
  *  V: n x k FP64 (device). Z: r x k, FP64 for F64 data, FP32 otherwise.

@@ -14,7 +14,7 @@ import os
 __all__ = [
     "load", "LspcaError", "F64", "F32", "BF16", "F16", "GAUSSIAN", "VERY_SPARSE",
     "version", "omega", "accumulate", "factor", "fit", "spca_fit", "transform",
-    "accumulate_host", "fit_host",
+    "accumulate_host", "fit_host", "spca_fit_stream",
     "last_timings", "exported_symbols", "LIB_PATH", "Server",
 ]
 
@@ -32,7 +32,7 @@ STATUS = {0: "LSPCA_OK", -1: "LSPCA_EINVAL", -2: "LSPCA_ENOMEM", -3: "LSPCA_EHIP
 # Every symbol include/lspca.h declares.
 EXPORTS = ["lspca_version", "lspca_strerror", "lspca_last_error", "lspca_last_timings",
            "lspca_omega", "lspca_accumulate", "lspca_factor", "lspca_fit", "spca_fit",
-           "lspca_transform", "lspca_accumulate_host", "lspca_fit_host", "lspca_server_create", "lspca_server_submit", "lspca_server_wait",
+           "lspca_transform", "lspca_accumulate_host", "lspca_fit_host", "spca_fit_stream", "lspca_server_create", "lspca_server_submit", "lspca_server_wait",
            "lspca_server_pause", "lspca_server_get_stats", "lspca_server_destroy"]
 
 
@@ -82,6 +82,8 @@ _SIGS = {
                   ctypes.POINTER(lspca_opts), _P, _P], ctypes.c_int),
     "lspca_transform": ([_P, ctypes.c_int, _I64, _I64, _I64, _P, _I32, _P,
                          ctypes.POINTER(lspca_opts)], ctypes.c_int),
+    "spca_fit_stream": ([_P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
+                         ctypes.POINTER(lspca_opts), _P, _P], ctypes.c_int),
     "lspca_accumulate_host": ([_P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
                                ctypes.POINTER(lspca_opts), _I64, _P, _P], ctypes.c_int),
     "lspca_fit_host": ([_P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
@@ -235,6 +237,18 @@ def spca_fit(X, k, kind="gaussian", seed=0, **kw):
     o = _opts(**kw)
     _check(load().spca_fit(X.data_ptr(), _dtype_code(X), m, n, ldx, k, KIND[kind], seed,
                            ctypes.byref(o), V.data_ptr(), s.data_ptr()))
+    return V, s
+
+
+def spca_fit_stream(X, k, kind="gaussian", seed=0, **kw):
+    """Streaming SPCA (Algorithm 3), one pass over X: V^s, Sigma^s."""
+    ldx = _rowmajor(X)
+    m, n = X.shape
+    V = _f64_out((n, k), X.device)
+    s = _f64_out((k,), X.device)
+    o = _opts(**kw)
+    _check(load().spca_fit_stream(X.data_ptr(), _dtype_code(X), m, n, ldx, k, KIND[kind], seed,
+                                  ctypes.byref(o), V.data_ptr(), s.data_ptr()))
     return V, s
 
 

@@ -7,6 +7,9 @@
 
 #include "common.h"
 
+#include <cstdlib>
+#include <functional>
+
 namespace lspca {
 
 // ------------------------------------------------------------- errors ------
@@ -196,7 +199,13 @@ static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool wan
   p.cap = 0;
   p.gather = kind == LSPCA_OMEGA_VERY_SPARSE && sparse_sketch_ok(xdt, n, k, sp, &p.cap);
   p.esz = xdt == LSPCA_F64 ? 8 : 4;
-  const int64_t budget = (int64_t)2 << 30;              // Y stripe bytes
+  // Y stripe bytes: 2 GiB, or LSPCA_STRIPE_BYTES (a tuning and test knob:
+  // small values exercise the multi-stripe paths on small inputs)
+  int64_t budget = (int64_t)2 << 30;
+  if (const char *e = getenv("LSPCA_STRIPE_BYTES")) {
+    const long long v = atoll(e);
+    if (v > 0) budget = v;
+  }
   int64_t rows = budget / ((int64_t)k * p.esz);
   rows = rows < 1024 ? 1024 : rows;
   p.stripe = m < rows ? m : rows;
@@ -218,11 +227,16 @@ static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool wan
   return p;
 }
 
+// Called with each stripe's sketch Y (rows x k): row-major FP32/FP64 with
+// ld = k (transposed = false), or transposed FP32 with ld = rows for 16-bit
+// data (transposed = true). Used by Algorithm 3 to update its R.
+using StripeHook = std::function<int(const void *Y, int64_t rows, int64_t ld, bool transposed)>;
+
 // Algorithm 4 step 2 over all rows of X (stripe by stripe): F += Y^T X,
 // G += Y^T Y. Workspace must hold plan.bytes (already ensured).
 static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, int k,
                     int kind, uint64_t seed, const Opts &o, double *F, double *G,
-                    const PassPlan &pl, Workspace &ws, PhaseTimer &tm) {
+                    const PassPlan &pl, Workspace &ws, PhaseTimer &tm, const StripeHook *hook = nullptr) {
   hipStream_t s = o.stream;
   const size_t xs = dtype_size(xdt);
   const bool refine = o.refine != 0;                 // default (-1) and 1: on
@@ -265,6 +279,7 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
       // Y_s = X_s Omega (Algorithm 4 step 2a)
       LSPCA_TRY(launch_nt(xdt, Xs, ldx, OmT, n, Y, k, rows, k, (int)n, s));
       tm.mark(PH_SKETCH);
+      if (hook) LSPCA_TRY((*hook)(Y, rows, k, false));
       // F += Y_s^T X_s (step 2b); G += Y_s^T Y_s
       LSPCA_TRY(launch_tn(xdt, Y, k, Xs, ldx, PF, rows, k, (int)n, sf, s));
       int sg = 0;
@@ -278,24 +293,25 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
       tm.mark(PH_REDUCE);
     } else {
       // sketch, written transposed: BF16 directly split into Yh/Yl;
-      // FP16 as FP32 with column maxima, then scaled and split
+      // FP16 as FP32 with column maxima, then scaled and split. With a
+      // hook, BF16 also goes through FP32 (split without scaling).
       uint16_t *Ylo = refine ? Yl : nullptr;
+      const bool y32 = fp16 || hook;
       if (fp16) LSPCA_TRY(zero_i32((int *)colmax, k, s));
       if (pl.gather) {
         LSPCA_TRY(zero_i32(flags, 1, s));
         LSPCA_TRY(launch_sparse_sketch(xdt, Xs, rows, n, ldx, k, seed, o.p, pl.cap,
-                                       fp16 ? (float *)Y : nullptr, rows, fp16 ? colmax : nullptr,
+                                       y32 ? (float *)Y : nullptr, rows, fp16 ? colmax : nullptr,
                                        Yh, Ylo, flags, s));
       } else {
-        LSPCA_TRY(launch_nt16(xdt, Xs, ldx, OmT, nullptr, n, fp16 ? (float *)Y : nullptr, rows, rows,
-                              k, (int)n, fp16 ? colpart : nullptr, Yh, Ylo, fp16 ? 1 : 2, s));
+        LSPCA_TRY(launch_nt16(xdt, Xs, ldx, OmT, nullptr, n, y32 ? (float *)Y : nullptr, rows, rows,
+                              k, (int)n, fp16 ? colpart : nullptr, Yh, Ylo, y32 ? 1 : 2, s));
         if (fp16) LSPCA_TRY(launch_colmax_reduce(colpart, nt16_row_tiles(rows), k, colmax, s));
       }
-      if (fp16) {
-        LSPCA_TRY(launch_col_scales(colmax, k, scale, inv, s));
-        LSPCA_TRY(launch_split16(xdt, (const float *)Y, k, rows, scale, Yh, Ylo, s));
-      }
+      if (fp16) LSPCA_TRY(launch_col_scales(colmax, k, scale, inv, s));
+      if (y32) LSPCA_TRY(launch_split16(xdt, (const float *)Y, k, rows, fp16 ? scale : nullptr, Yh, Ylo, s));
       tm.mark(PH_SKETCH);
+      if (hook) LSPCA_TRY((*hook)(Y, rows, rows, true));
       LSPCA_TRY(launch_tn16(xdt, Yh, Ylo, rows, Xs, ldx, (float *)PF, rows, k, (int)n, sf, s));
       tm.mark(PH_FACTOR);
       const int accum = (r0 > 0) ? 1 : acc;
@@ -592,6 +608,70 @@ int lspca_fit_host(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t
   LSPCA_TRY(L.st->ws.ensure(factor_bytes(n, k)));
   int rank_flag = 0;
   LSPCA_TRY(small_factor(F, want_g ? G : nullptr, k, n, V, sigma, sigma_x, L.st->ws, o.stream, &rank_flag));
+  tm.mark(PH_SMALL);
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int spca_fit_stream(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, int32_t k,
+                    lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts, double *V,
+                    double *sigma) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  LSPCA_TRY(check_pass_args(X, xdt, m, n, ldx, k, kind, o));
+  if (!V || !sigma) { set_error("V and sigma must not be NULL"); return LSPCA_EINVAL; }
+  if (k > m) { set_error("k must satisfy k <= min(m, n) (k=%d m=%lld)", k, (long long)m); return LSPCA_EINVAL; }
+  const lspca_dtype ydt = xdt == LSPCA_F64 ? LSPCA_F64 : LSPCA_F32;
+  const int BR = tsqr_block_rows(ydt);
+  if (k > BR) {
+    set_error("spca_fit_stream: k = %d above the QR block height (%d)", k, BR);
+    return LSPCA_ENOTSUP;
+  }
+  const size_t ys = dtype_size(ydt);
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  PassPlan pl = plan_pass(xdt, m, n, k, false, kind, o.p);
+  const size_t kb = (size_t)k * BR;
+  const size_t keep = ws_bytes<double>((size_t)k * n) + 3 * ws_bytes<char>(ys * kb) +
+                      ws_bytes<double>((size_t)k * k);
+  const size_t during = pl.bytes + tsqr_r_workspace_bytes(pl.stripe, k, ydt);
+  const size_t after = factor_bytes(n, k) + ws_bytes<double>((size_t)k * n) +
+                       2 * ws_bytes<double>((size_t)k * k) + ws_bytes<double>(3 * 128 * 128);
+  LSPCA_TRY(L.st->ws.ensure(keep + (during > after ? during : after)));
+  Workspace &ws = L.st->ws;
+  hipStream_t s = o.stream;
+  double *F = ws.take<double>((size_t)k * n);
+  char *Rpair = ws.take<char>(2 * ys * kb);          // running R, then the stripe's R
+  char *Rnext = ws.take<char>(ys * kb);
+  double *Rd = ws.take<double>((size_t)k * k);
+  const size_t mark = ws.used;
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, s);
+  LSPCA_TRY(zero_f64(F, (int64_t)k * n, s));
+  // Algorithm 3 step 2c: R <- R of qr([R; U_s]) for every stripe U_s
+  bool first = true;
+  StripeHook hook = [&](const void *Y, int64_t rows, int64_t ld, bool transposed) -> int {
+    const size_t here = ws.used;
+    LSPCA_TRY(tsqr_r(Y, ydt, rows, ld, !transposed, k, ws, first ? (void *)Rpair : (void *)(Rpair + ys * kb), s));
+    if (!first) {
+      LSPCA_TRY(tsqr_r_merge(Rpair, ydt, k, Rnext, s));
+      LSPCA_HIP(hipMemcpyAsync(Rpair, Rnext, ys * kb, hipMemcpyDeviceToDevice, s));
+    }
+    first = false;
+    ws.used = here;
+    tm.mark(PH_QR);
+    return LSPCA_OK;
+  };
+  // one pass: U_s = X_s Omega, F += U_s^T X_s (steps 2a-2b), R updated per stripe
+  LSPCA_TRY(run_pass(X, xdt, m, n, ldx, k, kind, seed, o, F, nullptr, pl, ws, tm, &hook));
+  ws.used = mark;
+  // step 3: F = (R^-1)^T F; step 4: truncated SVD of F gives V^s, Sigma^s
+  LSPCA_TRY(tsqr_r_dense(Rpair, ydt, k, Rd, s));
+  LSPCA_TRY(apply_rinv_t(Rd, k, F, n, ws, s));
+  tm.mark(PH_PASS2);
+  ws.used = mark;
+  int rank_flag = 0;
+  LSPCA_TRY(small_factor(F, nullptr, k, n, V, sigma, nullptr, ws, s, &rank_flag));
   tm.mark(PH_SMALL);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;

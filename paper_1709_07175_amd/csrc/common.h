@@ -232,6 +232,17 @@ int64_t tsqr_ld(int64_t m, lspca_dtype ydt);
 size_t tsqr_workspace_bytes(int64_t m, int k, lspca_dtype ydt);
 int tsqr(void *Ut, lspca_dtype ydt, int64_t m, int64_t ldu, int k, Workspace &ws, int out_mode,
          lspca_dtype dt16, void *Q, void *Qh, void *Ql, int64_t ldq, hipStream_t s);
+// R factor only (no Q): U row-major or transposed; root R in slice order
+// (k x block-height entries of ydt); merge of two such R's stored back to
+// back; dense FP64 k x k copy (row-major, zeros below the diagonal).
+size_t tsqr_r_workspace_bytes(int64_t m, int k, lspca_dtype ydt);
+int tsqr_r(const void *U, lspca_dtype ydt, int64_t m, int64_t ldu, bool rowmajor, int k, Workspace &ws,
+           void *Rroot, hipStream_t s);
+int tsqr_r_merge(const void *Rpair, lspca_dtype ydt, int k, void *Rout, hipStream_t s);
+int tsqr_r_dense(const void *Rslice, lspca_dtype ydt, int k, double *Rd, hipStream_t s);
+int tsqr_block_rows(lspca_dtype ydt);
+// F <- R^-T F for an upper triangular k x k FP64 R (row-major), F k x n.
+int apply_rinv_t(const double *R, int k, double *F, int64_t n, Workspace &ws, hipStream_t s);
 
 size_t dtype_size(lspca_dtype dt);
 

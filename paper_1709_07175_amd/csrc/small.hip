@@ -649,6 +649,21 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
 
 }  // namespace
 
+// F <- R^-T F (k x n), R upper triangular k x k (row-major FP64): the
+// "F = (R^-1)^T F" step of Algorithm 3 (Streaming SPCA).
+int apply_rinv_t(const double *R, int k, double *F, int64_t n, Workspace &ws, hipStream_t s) {
+  const int64_t kk = (int64_t)k * k;
+  double *XT = ws.take<double>(kk), *Ri = ws.take<double>(kk);
+  double *scr = ws.take<double>(3 * 128 * 128);
+  double *Fo = ws.take<double>((size_t)k * n);
+  LSPCA_TRY(trinv_t(R, k, XT, scr, s));                 // XT = R^-T
+  LSPCA_TRY(launch_transpose_f64(XT, k, k, Ri, s));     // Ri = R^-1
+  // Fo[i][j] = sum_r Ri[r][i] F[r][j]: the split-row product with one split
+  LSPCA_TRY(launch_tn(LSPCA_F64, Ri, k, F, n, Fo, k, k, (int)n, 1, s));
+  LSPCA_HIP(hipMemcpyAsync(F, Fo, (size_t)k * n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return LSPCA_OK;
+}
+
 int small_factor(const double *F, const double *G, int k, int64_t n, double *V, double *sigma,
                  double *sigma_x, Workspace &ws, hipStream_t s, int *rank_flag) {
   const int64_t kk = (int64_t)k * k;

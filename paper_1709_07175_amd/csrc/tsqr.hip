@@ -112,7 +112,9 @@ __device__ inline void householder(T x0, T s, T &beta, T &tau, T &scale) {
 // U, into the LDS buffer for the other columns (double buffered: one barrier
 // per reflector), and R's column j (slice order, zeros below the diagonal)
 // to R_out[b].
-template <typename T>
+// RM: U row-major (row r at U + r * ldu) instead of transposed; WV: write
+// the reflectors and tau (needed for Q; an R-only factorisation skips them).
+template <typename T, bool RM = false, bool WV = true>
 __global__ __launch_bounds__(1024) void k_tsqr_leaf(T *__restrict__ U, int64_t ldu, int64_t m, int k,
                                                     T *__restrict__ tau_out, T *__restrict__ R_out) {
   constexpr int BR = TsqrCfg<T>::BR, NI = TsqrCfg<T>::NI, NQ = TsqrCfg<T>::NQ, SP = lds_stride<T>();
@@ -125,9 +127,15 @@ __global__ __launch_bounds__(1024) void k_tsqr_leaf(T *__restrict__ U, int64_t l
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
     const int c = w + 16 * cg + 64 * q;
-    const T *src = U + (int64_t)(c < k ? c : 0) * ldu + row0 + rg;
+    if constexpr (RM) {
+      const T *src = U + (row0 + rg) * ldu + (c < k ? c : 0);
 #pragma unroll
-    for (int i = 0; i < NI; ++i) a[q][i] = (c < k && rg + 16 * i < rows_here) ? src[16 * i] : (T)0;
+      for (int i = 0; i < NI; ++i) a[q][i] = (c < k && rg + 16 * i < rows_here) ? src[16 * i * ldu] : (T)0;
+    } else {
+      const T *src = U + (int64_t)(c < k ? c : 0) * ldu + row0 + rg;
+#pragma unroll
+      for (int i = 0; i < NI; ++i) a[q][i] = (c < k && rg + 16 * i < rows_here) ? src[16 * i] : (T)0;
+    }
   }
 #pragma unroll
   for (int bi = 0; bi < 4 * NQ; ++bi) {           // reflectors 16 bi .. 16 bi + 15
@@ -158,11 +166,11 @@ __global__ __launch_bounds__(1024) void k_tsqr_leaf(T *__restrict__ U, int64_t l
           rc[i] = r < j ? x : (r == j ? beta : (T)0);
         }
         put_slice<T>(vl[buf] + rg * SP, v);
-        put_slice<T>(U + (int64_t)j * ldu + row0 + rg * NI, v);
+        if constexpr (WV) put_slice<T>(U + (int64_t)j * ldu + row0 + rg * NI, v);
         put_slice<T>(R_out + ((int64_t)blockIdx.x * k + j) * BR + rg * NI, rc);
         if (rg == 0) {
           tl[buf] = tau;
-          tau_out[(int64_t)blockIdx.x * k + j] = tau;
+          if constexpr (WV) tau_out[(int64_t)blockIdx.x * k + j] = tau;
         }
       }
       __syncthreads();
@@ -196,7 +204,7 @@ __global__ __launch_bounds__(1024) void k_tsqr_leaf(T *__restrict__ U, int64_t l
 // only row j of R_a, so each lane reads its columns' entries of R_a's row j
 // one step ahead and writes the final row j of R_out. A node without a
 // second child copies R_in[2p].
-template <typename T>
+template <typename T, bool WV = true>
 __global__ __launch_bounds__(1024) void k_tsqr_node(const T *__restrict__ R_in, int nin, int k,
                                                     T *__restrict__ R_out, T *__restrict__ Vb,
                                                     T *__restrict__ tau_out) {
@@ -210,11 +218,12 @@ __global__ __launch_bounds__(1024) void k_tsqr_node(const T *__restrict__ R_in, 
   T *Rn = R_out + (int64_t)p * kb;
   if (2 * p + 1 >= nin) {                         // single child: pass R through
     for (int64_t e = threadIdx.x; e < kb; e += blockDim.x) Rn[e] = Ra[e];
-    for (int e = threadIdx.x; e < k; e += blockDim.x) tau_out[(int64_t)p * k + e] = 0;
+    if constexpr (WV)
+      for (int e = threadIdx.x; e < k; e += blockDim.x) tau_out[(int64_t)p * k + e] = 0;
     return;
   }
   const T *Rb = Ra + kb;
-  T *V = Vb + (int64_t)p * kb;
+  T *V = WV ? Vb + (int64_t)p * kb : nullptr;
   T b[NQ][NI], ra_next[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) {
@@ -255,10 +264,10 @@ __global__ __launch_bounds__(1024) void k_tsqr_node(const T *__restrict__ R_in, 
 #pragma unroll
         for (int i = 0; i < NI; ++i) v[i] = (i <= bi && rg + 16 * i <= j) ? b[q][i] * scale : (T)0;
         put_slice<T>(vl[buf] + rg * SP, v);
-        put_slice<T>(V + (int64_t)j * BR + rg * NI, v);
+        if constexpr (WV) put_slice<T>(V + (int64_t)j * BR + rg * NI, v);
         if (rg == 0) {
           tl[buf] = tau;
-          tau_out[(int64_t)p * k + j] = tau;
+          if constexpr (WV) tau_out[(int64_t)p * k + j] = tau;
           Rn[(int64_t)j * BR + spos<T>(j)] = beta;
         }
       }
@@ -528,6 +537,8 @@ template <typename T> __global__ void k_eye_slices(T *C, int k) {
 // ---------------------------------------------------------------- driver --
 static int tsqr_br(lspca_dtype ydt) { return ydt == LSPCA_F64 ? TsqrCfg<double>::BR : TsqrCfg<float>::BR; }
 
+int tsqr_block_rows(lspca_dtype ydt) { return tsqr_br(ydt); }
+
 int64_t tsqr_ld(int64_t m, lspca_dtype ydt) {
   const int BR = tsqr_br(ydt);
   return (m + BR - 1) / BR * BR;
@@ -603,6 +614,91 @@ static int tsqr_typed(T *U, int64_t m, int64_t ldu, int k, Workspace &ws, int ou
   else
     hipLaunchKernelGGL((k_tsqr_leaf_q<T, 1, LSPCA_F16>), (unsigned)nb, 1024, 0, s, U, ldu, m, k, tau[0], C[0], Q,
                        ldq, Qh, Ql);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+// ------------------------------------------------------------- R only --
+// The R factor of U (m x k) without Q: leaves and tree, no reflectors kept.
+// U row-major (ldu = row stride) or transposed (column c at U + c * ldu).
+// The root R (slice order, k x BR entries of the type) goes to Rroot.
+size_t tsqr_r_workspace_bytes(int64_t m, int k, lspca_dtype ydt) {
+  const size_t es = ydt == LSPCA_F64 ? 8 : 4;
+  const int BR = tsqr_br(ydt);
+  int64_t level = (m + BR - 1) / BR;
+  size_t total = 0;
+  while (true) {
+    total += ws_bytes<char>(es * (size_t)level * k * BR);
+    if (level == 1) break;
+    level = (level + 1) / 2;
+  }
+  return total + 4096;
+}
+
+template <typename T>
+static int tsqr_r_typed(const T *U, int64_t m, int64_t ldu, bool rowmajor, int k, Workspace &ws, T *Rroot,
+                        hipStream_t s) {
+  constexpr int BR = TsqrCfg<T>::BR;
+  if (k > BR) {
+    set_error("QR: k = %d exceeds the block height %d for this type", k, BR);
+    return LSPCA_ENOTSUP;
+  }
+  const int64_t nb = (m + BR - 1) / BR, kb = (int64_t)k * BR;
+  std::vector<int64_t> counts{nb};
+  while (counts.back() > 1) counts.push_back((counts.back() + 1) / 2);
+  std::vector<T *> R(counts.size());
+  for (size_t l = 0; l < counts.size(); ++l) R[l] = ws.take<T>((size_t)counts[l] * kb);
+  if (rowmajor)
+    hipLaunchKernelGGL((k_tsqr_leaf<T, true, false>), (unsigned)nb, 1024, 0, s, const_cast<T *>(U), ldu, m, k,
+                       nullptr, R[0]);
+  else
+    hipLaunchKernelGGL((k_tsqr_leaf<T, false, false>), (unsigned)nb, 1024, 0, s, const_cast<T *>(U), ldu, m, k,
+                       nullptr, R[0]);
+  LSPCA_HIP(hipGetLastError());
+  for (size_t l = 1; l < counts.size(); ++l) {
+    hipLaunchKernelGGL((k_tsqr_node<T, false>), (unsigned)counts[l], 1024, 0, s, R[l - 1], (int)counts[l - 1], k,
+                       R[l], nullptr, nullptr);
+    LSPCA_HIP(hipGetLastError());
+  }
+  LSPCA_HIP(hipMemcpyAsync(Rroot, R.back(), (size_t)kb * sizeof(T), hipMemcpyDeviceToDevice, s));
+  return LSPCA_OK;
+}
+
+int tsqr_r(const void *U, lspca_dtype ydt, int64_t m, int64_t ldu, bool rowmajor, int k, Workspace &ws,
+           void *Rroot, hipStream_t s) {
+  if (ydt == LSPCA_F64)
+    return tsqr_r_typed<double>((const double *)U, m, ldu, rowmajor, k, ws, (double *)Rroot, s);
+  return tsqr_r_typed<float>((const float *)U, m, ldu, rowmajor, k, ws, (float *)Rroot, s);
+}
+
+// R of [R_a; R_b] for the two slice-order R factors stored back to back at
+// Rpair; result to Rout (slice order).
+int tsqr_r_merge(const void *Rpair, lspca_dtype ydt, int k, void *Rout, hipStream_t s) {
+  if (ydt == LSPCA_F64)
+    hipLaunchKernelGGL((k_tsqr_node<double, false>), 1, 1024, 0, s, (const double *)Rpair, 2, k, (double *)Rout,
+                       nullptr, nullptr);
+  else
+    hipLaunchKernelGGL((k_tsqr_node<float, false>), 1, 1024, 0, s, (const float *)Rpair, 2, k, (float *)Rout,
+                       nullptr, nullptr);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+template <typename T> __global__ void k_slice_to_dense(const T *__restrict__ Rs, int k, double *__restrict__ Rd) {
+  constexpr int BR = TsqrCfg<T>::BR;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)k * k) return;
+  const int r = (int)(e / k), c = (int)(e % k);
+  Rd[e] = r <= c ? (double)Rs[(int64_t)c * BR + spos<T>(r)] : 0.0;
+}
+
+// Dense k x k row-major FP64 copy of a slice-order R (zeros below).
+int tsqr_r_dense(const void *Rslice, lspca_dtype ydt, int k, double *Rd, hipStream_t s) {
+  const unsigned grid = (unsigned)(((int64_t)k * k + 255) / 256);
+  if (ydt == LSPCA_F64)
+    hipLaunchKernelGGL(k_slice_to_dense<double>, grid, 256, 0, s, (const double *)Rslice, k, Rd);
+  else
+    hipLaunchKernelGGL(k_slice_to_dense<float>, grid, 256, 0, s, (const float *)Rslice, k, Rd);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }

@@ -131,3 +131,9 @@ def test_host_stream_argument_checks(lib):
     assert lib.lspca_accumulate_host(1 << 20, L.F32, 10, 10, 10, 3, L.GAUSSIAN, 1, None, -5, 1 << 21, None) == -1
     assert "stripe_rows" in lib.lspca_last_error().decode()
     assert lib.lspca_fit_host(1 << 20, L.F32, 10, 10, 10, 11, L.GAUSSIAN, 1, None, 0, 1 << 21, 1 << 22, None) == -1
+
+
+def test_spca_fit_stream_argument_checks(lib):
+    assert lib.spca_fit_stream(None, L.F32, 100, 50, 50, 5, L.GAUSSIAN, 1, None, 1 << 20, 1 << 21) == -1
+    assert lib.spca_fit_stream(1 << 20, L.F32, 4, 50, 50, 5, L.GAUSSIAN, 1, None, 1 << 21, 1 << 22) == -1  # k > m
+    assert lib.spca_fit_stream(1 << 20, L.F32, 100, 50, 50, 5, L.GAUSSIAN, 1, None, None, 1 << 22) == -1

@@ -90,3 +90,63 @@ def test_spca_fit_k_above_block_height_is_refused(gpu_lib):
     with pytest.raises(gpu_lib.LspcaError) as e:
         gpu_lib.spca_fit(to_device(Xs, "f64"), 129, "gaussian", 1)
     assert e.value.name == "LSPCA_ENOTSUP"
+
+
+# ------------------------------------------------- Algorithm 3 (streaming) --
+
+@pytest.fixture
+def small_stripes(monkeypatch):
+    """Per-stripe sketch budget of 256 KiB: several stripes (and R merges)
+    even for small inputs. The library reads it at every call."""
+    monkeypatch.setenv("LSPCA_STRIPE_BYTES", str(256 * 1024))
+    yield
+
+
+@pytest.mark.parametrize("m,n,k", [(1037, 203, 17), (3000, 80, 50), (129, 60, 7)])
+def test_spca_fit_stream_f64_matches_oracle(gpu_lib, m, n, k):
+    Xs, X64 = _data(m, n, k, "f64")
+    V, s = gpu_lib.spca_fit_stream(to_device(Xs, "f64"), k, "gaussian", 3)
+    ref = O.streaming_spca_fit(X64, P.omega(n, k, "gaussian", 3), k, S=3)
+    assert O.principal_sines(ref["V"], V.cpu().numpy()).max() < 1e-10
+    assert np.max(np.abs(s.cpu().numpy() - ref["sigma"]) / ref["sigma"]) < 1e-10
+
+
+@pytest.mark.parametrize("m,n,k,dtype", [(9000, 120, 24, "f64"), (9000, 200, 24, "f32"),
+                                         (9000, 256, 32, "bf16")])
+def test_spca_fit_stream_many_stripes(gpu_lib, small_stripes, m, n, k, dtype):
+    """Several stripes: the running R is merged with every stripe's R."""
+    Xs, X64 = _data(m, n, k, dtype)
+    V, s = gpu_lib.spca_fit_stream(to_device(Xs, dtype), k, "gaussian", 4)
+    om = P.omega(n, k, "gaussian", 4, dtype=dtype)
+    ref = O.spca_fit(X64, om, k)
+    if dtype == "f64":
+        assert O.principal_sines(ref["V"], V.cpu().numpy()).max() < 1e-10
+        assert np.max(np.abs(s.cpu().numpy() - ref["sigma"]) / ref["sigma"]) < 1e-10
+    else:
+        err = np.linalg.norm(_f_bound(X64, ref["Q"], k, dtype))
+        s = s.cpu().numpy()
+        assert np.max(np.abs(s - ref["sigma"]) / ref["sigma"]) <= err / ref["sigma"][-1] + 1e-12
+        assert O.principal_sines(ref["V"], V.cpu().numpy()).max() <= subspace_tol(ref["sigma"][-1], err) + 1e-12
+
+
+def test_streaming_and_two_pass_spca_agree(gpu_lib):
+    """Algorithm 3 and Algorithm 1 compute the same V^s and Sigma^s."""
+    m, n, k = 6000, 300, 30
+    Xs, _ = _data(m, n, k, "f64")
+    X = to_device(Xs, "f64")
+    V1, s1 = gpu_lib.spca_fit(X, k, "gaussian", 6)
+    V3, s3 = gpu_lib.spca_fit_stream(X, k, "gaussian", 6)
+    assert O.principal_sines(V1.cpu().numpy(), V3.cpu().numpy()).max() < 1e-10
+    assert np.max(np.abs(s1.cpu().numpy() - s3.cpu().numpy()) / s1.cpu().numpy()) < 1e-11
+
+
+def test_lazy_fit_many_stripes_matches_one_stripe(gpu_lib, monkeypatch):
+    """The fit's own stripe loop (Algorithm 4 over device-resident X)."""
+    m, n, k = 9000, 200, 20
+    Xs, X64 = _data(m, n, k, "f64")
+    X = to_device(Xs, "f64")
+    V1, s1 = gpu_lib.fit(X, k, "gaussian", 2)
+    monkeypatch.setenv("LSPCA_STRIPE_BYTES", str(128 * 1024))
+    V2, s2 = gpu_lib.fit(X, k, "gaussian", 2)
+    assert O.principal_sines(V1.cpu().numpy(), V2.cpu().numpy()).max() < 1e-10
+    assert np.max(np.abs(s1.cpu().numpy() - s2.cpu().numpy()) / s1.cpu().numpy()) < 1e-11
