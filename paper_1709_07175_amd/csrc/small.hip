@@ -113,46 +113,46 @@ __global__ void k_shift_diag(double *M, int k, double c) {
   for (int i = threadIdx.x; i < k; i += blockDim.x) M[(int64_t)i * k + i] += c * tr;
 }
 
-// In-place Cholesky M = R^T R of a symmetric n x n block (leading
-// dimension ld, n <= 128) held in LDS (padded stride n + 1); R is left in
-// the upper triangle, the block's lower triangle is zeroed. Right-looking:
-// pivot, scale row j, rank-1 update of the trailing upper triangle.
-// fail[0] is set when a pivot is not positive and finite.
+// Cholesky factor (upper triangular R, M = R^T R) of an n x n block (n <=
+// 128) in LDS, right-looking on the upper triangle with the pivot row kept
+// unscaled: every thread reads the pivot d_j itself and subtracts
+// M[j][a] M[j][b] / d_j from the trailing entries (j < a <= b), one barrier
+// per step; rows are scaled by 1/sqrt(d_j) when R is written. A pivot that
+// is not positive and finite sets fail[0] (the same value is seen by all
+// threads, so they leave the loop together).
 __global__ __launch_bounds__(1024) void k_chol_lds(double *Mg, int n, int64_t ld, int *fail) {
   __shared__ double M[128 * 129];
-  __shared__ double dj;
-  __shared__ int bad;
   const int tid = threadIdx.x, nt = blockDim.x, s = n + 1;
   const int tx = tid & 31, ty = tid >> 5;
   for (int e = tid; e < n * n; e += nt) M[(e / n) * s + e % n] = Mg[(int64_t)(e / n) * ld + e % n];
-  if (tid == 0) bad = 0;
   __syncthreads();
+  bool bad = false;
   for (int j = 0; j < n; ++j) {
-    if (tid == 0) {
-      double d = M[j * s + j];
-      if (!(d > 0.0) || !isfinite(d)) {
-        bad = 1;
-        d = 1.0;
-      }
-      dj = sqrt(d);
-      M[j * s + j] = dj;
+    const double d = M[j * s + j];
+    if (!(d > 0.0) || !isfinite(d)) {
+      bad = true;
+      break;
     }
-    __syncthreads();
-    if (bad) break;
-    const double inv = 1.0 / dj;
-    for (int c = j + 1 + tid; c < n; c += nt) M[j * s + c] *= inv;
-    __syncthreads();
+    const double inv = 1.0 / d;
     for (int a = j + 1 + ty; a < n; a += 32) {
-      const double ra = M[j * s + a];
+      const double ra = M[j * s + a] * inv;
       for (int b = a + tx; b < n; b += 32) M[a * s + b] -= ra * M[j * s + b];
     }
     __syncthreads();
   }
+  if (bad) {
+    if (tid == 0) fail[0] = 1;
+    return;
+  }
   for (int e = tid; e < n * n; e += nt) {
     const int a = e / n, b = e % n;
-    Mg[(int64_t)a * ld + b] = b < a ? 0.0 : M[a * s + b];
+    double v = 0.0;
+    if (b >= a) {
+      const double r = sqrt(M[a * s + a]);
+      v = b == a ? r : M[a * s + b] / r;
+    }
+    Mg[(int64_t)a * ld + b] = v;
   }
-  if (tid == 0 && bad) fail[0] = 1;
 }
 
 // Inverse X = R^-1 of an upper triangular n x n block (n <= 128) in LDS,
