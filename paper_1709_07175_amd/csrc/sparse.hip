@@ -14,6 +14,7 @@
 
 #include <cmath>
 #include <cstdlib>
+#include <cstring>
 
 namespace lspca {
 
@@ -219,27 +220,403 @@ __global__ __launch_bounds__(kSpThreads) void k_sparse_sketch(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Register-list variant: tiles of 8 rows, 1024 threads. Lane (c, q) owns
+// output column c and one of LPC parts of its work: parts 0..LPC/2-1 take the
+// column's +1 entries (ascending j, cut by position into runs of Lq entries),
+// the other parts its -1 entries. A lane keeps the LDS addresses of its run in
+// registers for the whole launch, so the step loop reads only X: one 16-byte
+// LDS read (the 8 rows of one feature) and 8 FP32 fmas with the lane's sign.
+// The parts are summed in a fixed tree (positives, negatives, then both), so
+// the result does not depend on timing. The X tile is double-buffered in LDS:
+// feature slots of the two buffers interleaved (slot address * 32 + 16 *
+// buffer), slots swizzled so that the staging writes spread over the banks;
+// slot `zslot` holds zeros and pads every run to a whole number of steps.
+// Runs longer than the register capacity (a far-tail event for the shapes the
+// host admits) switch the workgroup to regenerating Omega on the fly in the
+// same order.
+constexpr int kGxThreads = 1024;
+constexpr int kGxRows = 8;
+constexpr int kGxLQ = 40;               // register run capacity, multiple of 4
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int gx_slot(int f) { return f ^ ((f >> 4) & 7); }
+
+typedef __attribute__((address_space(3))) const u32x4 gx_lds_u32x4;
+// 16 bytes at an LDS byte address (the kernel has no static LDS, so its
+// dynamic LDS starts at address 0; the host checks this)
+__device__ __forceinline__ u32x4 gx_read(uint32_t a) { return *(gx_lds_u32x4 *)(uintptr_t)a; }
+
+template <int CTRL> __device__ __forceinline__ float gx_dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Sum (MAX = false) or maximum over the LPC consecutive lanes of a column:
+// lane xor 1, xor 2 (quad permutes), then the mirrors within 8 and 16 lanes.
+// Every step combines two equal-shaped halves, so all lanes end bitwise equal.
+template <int LPC, bool MAX> __device__ __forceinline__ float gx_reduce(float v) {
+  auto op = [](float a, float b) { return MAX ? fmaxf(a, b) : a + b; };
+  v = op(v, gx_dpp<0xB1>(v));
+  v = op(v, gx_dpp<0x4E>(v));
+  if (LPC >= 8) v = op(v, gx_dpp<0x141>(v));
+  if (LPC >= 16) v = op(v, gx_dpp<0x140>(v));
+  return v;
+}
+
+// One step: +-x for the 8 rows of a feature (4 dwords, row 2d in the low and
+// row 2d+1 in the high half of dword d), each an FP32 fma with s = +-1, i.e.
+// one correctly rounded addition. FP16 halves convert inside the fma
+// (v_fma_mix_f32); a BF16 half is the FP32 with the same top 16 bits.
+template <int DT>
+__device__ __forceinline__ void gx_step(u32x4 xv, float s, float (&acc)[kGxRows]) {
+#pragma unroll
+  for (int d = 0; d < 4; ++d) {
+    float lo, hi;
+    if (DT == LSPCA_BF16) {
+      lo = __uint_as_float(xv[d] << 16);
+      hi = __uint_as_float(xv[d] & 0xffff0000u);
+    } else {
+      lo = f16_bits_to_f32((uint16_t)xv[d]);
+      hi = f16_bits_to_f32((uint16_t)(xv[d] >> 16));
+    }
+    acc[2 * d] = fmaf(lo, s, acc[2 * d]);
+    acc[2 * d + 1] = fmaf(hi, s, acc[2 * d + 1]);
+  }
+}
+
+// The run of one lane over buffer BUF: blocks of 4 steps, the next block's
+// reads issued before the current block's arithmetic (the padding addresses
+// past the run point at the zero slot, so reading ahead is always in bounds).
+template <int DT, int BUF>
+__device__ __forceinline__ void gx_run(const uint32_t (&ent)[kGxLQ], int lq, float sg, float (&acc)[kGxRows]) {
+  u32x4 cur[4], nxt[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) cur[t] = gx_read(ent[t] + 16 * BUF);
+#pragma unroll
+  for (int b = 0; b < kGxLQ / 4; ++b) {
+    if (4 * b >= lq) break;
+    if (b + 1 < kGxLQ / 4) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) nxt[t] = gx_read(ent[4 * b + 4 + t] + 16 * BUF);
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) gx_step<DT>(cur[t], sg, acc);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) cur[t] = nxt[t];
+  }
+  // A use of the last read-ahead on the way out (never taken: lq >= 0) keeps
+  // the compiler from sinking each block's read-ahead below its exit test.
+  if (lq < 0) acc[0] = __uint_as_float(cur[0][0] ^ cur[1][1] ^ cur[2][2] ^ cur[3][3]);
+}
+
+// Sum of the LPC parts of a column, scattered: a lane keeps half of its
+// values and adds its partner's copy of them (lane xor 1, xor 2, then the
+// mirrors within 8 and 16 lanes). The half a lane keeps at each step is
+// chosen so that the partners of the next step hold the same rows. Parts
+// 0..LPC/2-1 (+1 entries) meet first, then the two signs. Afterwards lane q
+// holds rows row0, row0 + 1 (LPC = 4) or row row0 (LPC = 8, 16; for 16 the
+// lanes q and 15 - q both hold it).
+template <int LPC>
+__device__ __forceinline__ void gx_scatter(float (&v)[kGxRows], int q, int &row0) {
+  const int b0 = q & 1, b1 = (q >> 1) & 1, b2 = (q >> 2) & 1, b3 = (q >> 3) & 1;
+  const bool k1 = LPC == 4 ? b0 : (b0 ^ b2);
+  const bool k2 = LPC == 4 ? b1 : (b1 ^ b2);
+  const bool k3 = LPC == 8 ? b2 : (b2 ^ b3);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float keep = k1 ? v[i + 4] : v[i], send = k1 ? v[i] : v[i + 4];
+    v[i] = keep + gx_dpp<0xB1>(send);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float keep = k2 ? v[i + 2] : v[i], send = k2 ? v[i] : v[i + 2];
+    v[i] = keep + gx_dpp<0x4E>(send);
+  }
+  row0 = 4 * k1 + 2 * k2;
+  if (LPC >= 8) {
+    const float keep = k3 ? v[1] : v[0], send = k3 ? v[0] : v[1];
+    v[0] = keep + gx_dpp<0x141>(send);
+    row0 += k3;
+  }
+  if (LPC >= 16) v[0] = v[0] + gx_dpp<0x140>(v[0]);
+}
+
+// Dynamic LDS: generation [ counts: 2k ints | max run | buckets: 2k x CAP
+// 16-bit ], then reused as the two interleaved X buffers ((8 ceil(n/8) + 1)
+// slots x 32 bytes). tiles_per_wg consecutive 8-row tiles per workgroup, so
+// the transposed outputs of neighbouring tiles are written from one CU.
+template <int DT, int LPC>
+__global__ __launch_bounds__(kGxThreads) void k_sparse_sketch_reg(
+    const uint16_t *__restrict__ X, int64_t m, int n, int64_t ldx, int k, uint32_t key0,
+    uint32_t key1, uint32_t t_plus, uint64_t t_minus, int lq_cap, int64_t tiles_per_wg,
+    float *__restrict__ Y, int64_t ldy, unsigned *__restrict__ colmax, uint16_t *__restrict__ Yh,
+    uint16_t *__restrict__ Yl, int *__restrict__ overflow) {
+  constexpr int HALF = LPC / 2;
+  constexpr int CAP = HALF * kGxLQ;                // bucket capacity per (column, sign)
+  extern __shared__ __align__(16) unsigned char lds[];
+  const int tid = threadIdx.x;
+  const int col = tid / LPC, q = tid % LPC;
+  const int sgn = q / HALF, part = q % HALF;
+  const bool live = col < k;
+  const int ngroups = (n + 7) >> 3;
+  const int zslot = ngroups * 8;
+  const int qk = (k + 3) >> 2;
+
+  // ---- Omega's nonzeros per (column, sign): count, bucket, sort by j
+  int *cnt = (int *)lds;
+  int *lqmax = cnt + 2 * k;
+  uint16_t *bucket = (uint16_t *)(lds + ((8 * k + 4 + 15) & ~15));
+  for (int i = tid; i < 2 * k; i += kGxThreads) cnt[i] = 0;
+  if (tid == 0) *lqmax = 0;
+  __syncthreads();
+  const int calls = n * qk;
+  for (int idx = tid; idx < calls; idx += kGxThreads) {
+    const int j = idx / qk, q4 = idx - j * qk;
+    uint32_t x[4];
+    philox4x32_10((uint32_t)q4, (uint32_t)j, 0u, kTagSparse, key0, key1, x);
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int c = 4 * q4 + t;
+      if (c < k && (uint64_t)x[t] < t_minus) {
+        const int b = 2 * c + (x[t] < t_plus ? 0 : 1);
+        const int pos = atomicAdd(&cnt[b], 1);
+        if (pos < CAP) bucket[b * CAP + pos] = (uint16_t)j;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < 2 * k; i += kGxThreads) atomicMax(lqmax, (cnt[i] + HALF - 1) / HALF);
+  __syncthreads();
+  const int lq = *lqmax;
+  const bool fits = lq <= kGxLQ && lq <= lq_cap;
+  if (!fits && tid == 0) atomicOr(overflow, 1);
+  for (int b = tid; fits && b < 2 * k; b += kGxThreads) {
+    uint16_t *e = bucket + b * CAP;
+    const int len = cnt[b];
+    for (int i = 1; i < len; ++i) {
+      const uint16_t v = e[i];
+      int t = i - 1;
+      while (t >= 0 && e[t] > v) {
+        e[t + 1] = e[t];
+        --t;
+      }
+      e[t + 1] = v;
+    }
+  }
+  __syncthreads();
+  uint32_t ent[kGxLQ];
+  {
+    const int b = 2 * col + sgn;
+    const int len = live ? cnt[b] : 0;
+#pragma unroll
+    for (int s = 0; s < kGxLQ; ++s) {
+      const int i = part * lq + s;
+      int slot = zslot;
+      if (fits && s < lq && i < len) slot = gx_slot(bucket[b * CAP + i]);
+      ent[s] = (uint32_t)slot * 32;
+      // hide the alignment of the address, so that + 16 (the second buffer)
+      // stays an add and folds into the read's offset field
+      asm volatile("" : "+v"(ent[s]));
+    }
+  }
+  __syncthreads();                                 // the X buffers overwrite the buckets
+
+  // ---- 8-row tiles
+  const int64_t ntiles = (m + kGxRows - 1) / kGxRows;
+  const int64_t t0 = (int64_t)blockIdx.x * tiles_per_wg;
+  const int64_t t1 = t0 + tiles_per_wg < ntiles ? t0 + tiles_per_wg : ntiles;
+  if (tid < 2) *(u32x4 *)(lds + (2 * zslot + tid) * 16) = u32x4{0u, 0u, 0u, 0u};
+  const bool vec = (ldx % 8) == 0 && ((uintptr_t)X % 16) == 0;
+  // staging: thread = feature group g (8 features) x row half h (4 rows);
+  // 2 ceil(n/8) <= 1024 units (the host admits n <= 4096)
+  const int ug = tid % ngroups, uh = tid / ngroups;      // uh >= 2: idle
+  u16x8 v[4];
+  auto load = [&](int64_t tile) {
+    const int64_t r0 = tile * kGxRows;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + 4 * uh + r;
+      u16x8 x = {};
+      if (uh < 2 && row < m) {
+        const uint16_t *src = X + row * ldx + 8 * ug;
+        if (vec && 8 * ug + 7 < n) {
+          x = *(const u16x8 *)src;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) x[e] = 8 * ug + e < n ? src[e] : (uint16_t)0;
+        }
+      }
+      v[r] = x;
+    }
+  };
+  auto store = [&](int buf) {
+    if (uh >= 2) return;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const u16x4 w = {v[0][e], v[1][e], v[2][e], v[3][e]};
+      *(u16x4 *)(lds + (2 * gx_slot(8 * ug + e) + buf) * 16 + 8 * uh) = w;
+    }
+  };
+  const float sg = sgn ? -1.f : 1.f;
+  float amax = 0.f;
+  if (t0 < t1) {
+    load(t0);
+    store(0);
+  }
+  __syncthreads();
+  for (int64_t tile = t0; tile < t1; ++tile) {
+    const int buf = (int)((tile - t0) & 1);
+    if (tile + 1 < t1) load(tile + 1);
+    float acc[kGxRows];
+#pragma unroll
+    for (int r = 0; r < kGxRows; ++r) acc[r] = 0.f;
+    if (fits) {
+      if (buf == 0) gx_run<DT, 0>(ent, lq, sg, acc);
+      else gx_run<DT, 1>(ent, lq, sg, acc);
+    } else if (live) {
+      // on the fly, same entries in the same order as the run
+      const int lo = part * lq, hi = lo + lq;
+      int rank = 0;
+      for (int j = 0; j < n && rank < hi; ++j) {
+        uint32_t x[4];
+        philox4x32_10((uint32_t)(col >> 2), (uint32_t)j, 0u, kTagSparse, key0, key1, x);
+        const uint32_t w = (col & 3) == 0 ? x[0] : (col & 3) == 1 ? x[1] : (col & 3) == 2 ? x[2] : x[3];
+        if ((uint64_t)w < t_minus && (w < t_plus ? 0 : 1) == sgn) {
+          if (rank >= lo) {
+            const u32x4 xv = *(const u32x4 *)(lds + (2 * gx_slot(j) + buf) * 16);
+            gx_step<DT>(xv, sg, acc);
+          }
+          ++rank;
+        }
+      }
+    }
+    if (tile + 1 < t1) store(buf ^ 1);
+    int row0;
+    gx_scatter<LPC>(acc, q, row0);
+    const int64_t r0 = tile * kGxRows;
+    constexpr int RPL = LPC == 4 ? 2 : 1;
+    const bool writer = live && (LPC < 16 || q < 8);
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int rr = row0 + i;
+      if (!writer || r0 + rr >= m) continue;
+      const float val = acc[i];
+      const int64_t o = (int64_t)col * ldy + r0 + rr;
+      if (Y) {
+        Y[o] = val;
+      } else {
+        const uint16_t hv = f2h<DT>(val);
+        Yh[o] = hv;
+        if (Yl) Yl[o] = f2h<DT>(val - h2f<DT>(hv));
+      }
+      amax = fmaxf(amax, fabsf(val));
+    }
+    __syncthreads();
+  }
+  if (colmax) {
+    amax = gx_reduce<LPC, true>(amax);
+    if (live && q == 0) atomicMax(colmax + col, __float_as_uint(amax));
+  }
+}
+
 // LDS needed for n features and a list capacity of cap entries.
 static size_t sparse_lds_bytes(int n, int k, int cap) {
   return (((size_t)n * kSpRows * 2 + 15) & ~(size_t)15) + (size_t)(2 * k + 1) * 4 + (size_t)cap * 2;
 }
 
-// Whether the gather path applies: 16-bit X, n < 2^15, k <= 1024, and the
-// expected number of nonzeros n k / p with a 10-sigma margin fits the list.
-bool sparse_sketch_ok(lspca_dtype dt, int64_t n, int k, uint32_t p, int *cap_out) {
+// Plan of the register-list kernel: lanes per column, LDS bytes.
+struct GxPlan {
+  int lpc = 0;
+  size_t lds = 0;
+};
+
+// Chernoff bound on log P(Binomial(n, r) >= x).
+static double binom_tail_log(double n, double r, double x) {
+  const double a = x / n;
+  if (a <= r) return 0.0;
+  if (a > 1.0) return -INFINITY;
+  if (a == 1.0) return n * log(r);
+  return -n * (a * log(a / r) + (1 - a) * log((1 - a) / (1 - r)));
+}
+
+// Whether the register-list kernel applies: 16-bit X, n <= 4096, k <= 256,
+// and every one of the 2k sign lists (each Binomial(n, 1/(2p)) long) within
+// the LPC/2 runs of the registers except with probability below 1e-6 (union
+// bound; an overflow costs time, not accuracy: the on-the-fly path gives the
+// same bits). LSPCA_SPARSE_KERNEL=lds selects the LDS-list kernel, =reg
+// requires this one (test knobs).
+static bool gx_plan(lspca_dtype dt, int64_t n, int k, uint32_t p, GxPlan &g) {
   if (dt != LSPCA_BF16 && dt != LSPCA_F16) return false;
-  if (n >= 32768 || k > 1024) return false;
+  if (n < 1 || n > 4096 || k < 1 || k > 256) return false;
+  if (const char *e = getenv("LSPCA_SPARSE_KERNEL"))
+    if (!strcmp(e, "lds")) return false;
+  g.lpc = k > 128 ? 4 : (k > 64 ? 8 : 16);
+  const int cap = g.lpc / 2 * kGxLQ;
+  const int64_t ngroups = (n + 7) / 8;
+  const size_t xb = (size_t)(8 * ngroups + 1) * 32;
+  const size_t gen = ((8 * (size_t)k + 4 + 15) & ~(size_t)15) + (size_t)2 * k * cap * 2;
+  g.lds = xb > gen ? xb : gen;
+  if (g.lds > 160 * 1024) return false;
+  return binom_tail_log((double)n, 0.5 / p, cap + 1.0) + log(2.0 * k) <= log(1e-6);
+}
+
+// Whether a gather path applies (16-bit X): the register-list kernel, or the
+// LDS-list kernel when n < 2^15, k <= 1024 and the expected number of
+// nonzeros n k / p with a 10-sigma margin fits its list; *cap_out is that
+// list's capacity (0 when only the register kernel applies).
+bool sparse_sketch_ok(lspca_dtype dt, int64_t n, int k, uint32_t p, int *cap_out) {
+  *cap_out = 0;
+  GxPlan g;
+  const bool reg = gx_plan(dt, n, k, p, g);
+  if (dt != LSPCA_BF16 && dt != LSPCA_F16) return false;
+  if (n >= 32768 || k > 1024) return reg;
   const size_t budget = 160 * 1024;
   const size_t fixed = sparse_lds_bytes((int)n, k, 0);
-  if (fixed >= budget) return false;
+  if (fixed >= budget) return reg;
   const double mu = (double)n * k / p;                 // expected nonzeros
   const double want = mu + 10.0 * sqrt(mu) + 64;       // 10 sigma margin
   const double room = (double)(budget - fixed) / 2;
-  if (want > room) return false;
+  if (want > room) return reg;
   *cap_out = ((int)want + 63) & ~63;
   // test hook: a smaller capacity forces the on-the-fly fallback
   if (const char *e = getenv("LSPCA_SPARSE_CAP")) *cap_out = atoi(e);
   return true;
+}
+
+template <int DT, int LPC>
+static int launch_reg(const GxPlan &g, unsigned grid, const void *X, int64_t m, int64_t n, int64_t ldx,
+                      int k, uint32_t key0, uint32_t key1, uint32_t t_plus, uint64_t t_minus, int lq_cap,
+                      int64_t per, float *Y, int64_t ldy, unsigned *colmax, void *Yh, void *Yl,
+                      int *overflow, hipStream_t s) {
+  const void *fn = (const void *)k_sparse_sketch_reg<DT, LPC>;
+  hipFuncAttributes fa;
+  LSPCA_HIP(hipFuncGetAttributes(&fa, fn));
+  if (fa.sharedSizeBytes != 0) {           // LDS addresses assume dynamic LDS at 0
+    set_error("sparse sketch: unexpected static LDS (%zu bytes)", (size_t)fa.sharedSizeBytes);
+    return LSPCA_EINVAL;
+  }
+  LSPCA_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds));
+  hipLaunchKernelGGL((k_sparse_sketch_reg<DT, LPC>), grid, kGxThreads, g.lds, s, (const uint16_t *)X, m,
+                     (int)n, ldx, k, key0, key1, t_plus, t_minus, lq_cap, per, Y, ldy, colmax,
+                     (uint16_t *)Yh, (uint16_t *)Yl, overflow);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+template <int DT>
+static int launch_reg_dt(const GxPlan &g, unsigned grid, const void *X, int64_t m, int64_t n, int64_t ldx,
+                         int k, uint32_t key0, uint32_t key1, uint32_t t_plus, uint64_t t_minus, int lq_cap,
+                         int64_t per, float *Y, int64_t ldy, unsigned *colmax, void *Yh, void *Yl,
+                         int *overflow, hipStream_t s) {
+  if (g.lpc == 4)
+    return launch_reg<DT, 4>(g, grid, X, m, n, ldx, k, key0, key1, t_plus, t_minus, lq_cap, per, Y, ldy, colmax,
+                             Yh, Yl, overflow, s);
+  if (g.lpc == 8)
+    return launch_reg<DT, 8>(g, grid, X, m, n, ldx, k, key0, key1, t_plus, t_minus, lq_cap, per, Y, ldy, colmax,
+                             Yh, Yl, overflow, s);
+  return launch_reg<DT, 16>(g, grid, X, m, n, ldx, k, key0, key1, t_plus, t_minus, lq_cap, per, Y, ldy, colmax,
+                            Yh, Yl, overflow, s);
 }
 
 int launch_sparse_sketch(lspca_dtype dt, const void *X, int64_t m, int64_t n, int64_t ldx, int k,
@@ -248,11 +625,34 @@ int launch_sparse_sketch(lspca_dtype dt, const void *X, int64_t m, int64_t n, in
   const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
   const uint32_t t_plus = (uint32_t)((1ull << 32) / (2ull * p));
   const uint64_t t_minus = (1ull << 32) / (uint64_t)p;
-  const size_t lds = sparse_lds_bytes((int)n, k, cap);
-  const int64_t ntiles = (m + kSpRows - 1) / kSpRows;
+  if (m <= 0) return LSPCA_OK;
   int dev = 0, cus = 256;
   LSPCA_HIP(hipGetDevice(&dev));
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+  GxPlan g;
+  if (gx_plan(dt, n, k, p, g)) {
+    // one workgroup per CU, each on a contiguous range of 8-row tiles;
+    // LSPCA_SPARSE_LQ lowers the register run capacity (a test knob that
+    // forces the on-the-fly fallback)
+    int lq_cap = kGxLQ;
+    if (const char *e = getenv("LSPCA_SPARSE_LQ")) lq_cap = atoi(e);
+    const int64_t ntiles = (m + kGxRows - 1) / kGxRows;
+    const int64_t g0 = ntiles < cus ? ntiles : cus;
+    const int64_t per = (ntiles + g0 - 1) / g0;
+    const unsigned grid = (unsigned)((ntiles + per - 1) / per);
+    if (dt == LSPCA_BF16)
+      return launch_reg_dt<LSPCA_BF16>(g, grid, X, m, n, ldx, k, key0, key1, t_plus, t_minus, lq_cap, per, Y,
+                                       ldy, colmax, Yh, Yl, overflow, s);
+    return launch_reg_dt<LSPCA_F16>(g, grid, X, m, n, ldx, k, key0, key1, t_plus, t_minus, lq_cap, per, Y, ldy,
+                                    colmax, Yh, Yl, overflow, s);
+  }
+  const char *knob = getenv("LSPCA_SPARSE_KERNEL");
+  if (cap <= 0 || (knob && !strcmp(knob, "reg"))) {
+    set_error("sparse sketch: shape (n=%lld, k=%d, p=%u) not supported", (long long)n, k, p);
+    return LSPCA_EINVAL;
+  }
+  const size_t lds = sparse_lds_bytes((int)n, k, cap);
+  const int64_t ntiles = (m + kSpRows - 1) / kSpRows;
   const int64_t want = (int64_t)cus * (lds <= 80 * 1024 ? 2 : 1);
   const unsigned grid = (unsigned)(ntiles < want ? ntiles : want);
   if (dt == LSPCA_BF16) {

@@ -306,14 +306,26 @@ def test_sparse_omega_fit_16bit(gpu_lib, dtype):
     assert np.max(np.abs(s.cpu().numpy() - ref["sigma"]) / ref["sigma"]) <= err / ref["sigma"][-1] + 1e-12
 
 
-@pytest.mark.parametrize("dtype,p", [("bf16", 64), ("f16", 64), ("bf16", 1), ("bf16", 8)])
-def test_sparse_sketch_accumulate_matches_oracle(gpu_lib, dtype, p):
+# (dtype, p, m, n, k, kernel): kernel "reg" requires the register-list kernel
+# (lanes per column 16, 8, 4 for k <= 64, <= 128, <= 256; n <= 4096), "lds"
+# selects the LDS-list kernel, None leaves the choice to the shape (p = 1:
+# dense lists and n > 4096 take the LDS-list kernel)
+SPARSE_CASES = [("bf16", 64, 2001, 517, 40, "reg"), ("f16", 64, 2001, 517, 40, "reg"),
+                ("bf16", 1, 2001, 517, 40, None), ("bf16", 8, 2001, 517, 40, "reg"),
+                ("f16", 16, 1999, 1000, 100, "reg"), ("bf16", 64, 3001, 4096, 256, "reg"),
+                ("f16", 64, 1003, 4096, 256, "reg"), ("bf16", 64, 2001, 517, 40, "lds"),
+                ("bf16", 32, 1500, 5000, 64, None), ("bf16", 64, 1007, 4096, 256, "lds")]
+
+
+@pytest.mark.parametrize("dtype,p,m,n,k,kernel", SPARSE_CASES)
+def test_sparse_sketch_accumulate_matches_oracle(gpu_lib, monkeypatch, dtype, p, m, n, k, kernel):
     """Gather-add sketch (Omega regenerated per workgroup, never stored):
     F and G within the componentwise bound of the oracle's, on ragged
-    sizes (m not a multiple of the 4-row tile, n not of 8)."""
+    sizes (m not a multiple of the 8- or 4-row tile, n not of 8)."""
     import torch
-    m, n, k = 2001, 517, 40
-    Xs, X64 = _data(m, n, k, dtype)
+    if kernel:
+        monkeypatch.setenv("LSPCA_SPARSE_KERNEL", kernel)
+    Xs, X64 = _data(m, n, min(k, 64), dtype)
     om = P.omega(n, k, "sparse", 1234, p=p, dtype=dtype)
     F = torch.zeros((k, n), dtype=torch.float64, device="cuda")
     G = torch.zeros((k, k), dtype=torch.float64, device="cuda")
@@ -325,20 +337,27 @@ def test_sparse_sketch_accumulate_matches_oracle(gpu_lib, dtype, p):
     assert np.all(np.abs(G.cpu().numpy() - ref["G"]) <= bG)
 
 
-def test_sparse_sketch_fallback_gives_the_same_bits(gpu_lib, monkeypatch):
+@pytest.mark.parametrize("kernel,env,m,n,k,p", [("reg", {"LSPCA_SPARSE_LQ": "1"}, 1500, 300, 32, 4),
+                                                ("reg", {"LSPCA_SPARSE_LQ": "2"}, 1203, 777, 200, 16),
+                                                ("reg", {"LSPCA_SPARSE_LQ": "3"}, 999, 640, 90, 8),
+                                                ("lds", {"LSPCA_SPARSE_KERNEL": "lds", "LSPCA_SPARSE_CAP": "64"},
+                                                 1500, 300, 32, 4)])
+def test_sparse_sketch_fallback_gives_the_same_bits(gpu_lib, monkeypatch, kernel, env, m, n, k, p):
     """A list capacity below the number of nonzeros (forced from the host)
     switches the workgroups to on-the-fly regeneration: same summation
     order, so the same F bit for bit."""
     import torch
-    m, n, k = 1500, 300, 32
-    Xs, _ = _data(m, n, k, "bf16")
+    Xs, _ = _data(m, n, min(k, 32), "bf16")
     X = to_device(Xs, "bf16")
+    monkeypatch.setenv("LSPCA_SPARSE_KERNEL", kernel)
     F1 = torch.zeros((k, n), dtype=torch.float64, device="cuda")
-    gpu_lib.accumulate(X, k, "sparse", 9, F1, sparse_p=4)
+    gpu_lib.accumulate(X, k, "sparse", 9, F1, sparse_p=p)
     torch.cuda.synchronize()
-    monkeypatch.setenv("LSPCA_SPARSE_CAP", "64")
+    for key, val in env.items():
+        monkeypatch.setenv(key, val)
     F2 = torch.zeros((k, n), dtype=torch.float64, device="cuda")
-    gpu_lib.accumulate(X, k, "sparse", 9, F2, sparse_p=4)
+    gpu_lib.accumulate(X, k, "sparse", 9, F2, sparse_p=p)
     torch.cuda.synchronize()
-    monkeypatch.delenv("LSPCA_SPARSE_CAP")
+    for key in env:
+        monkeypatch.delenv(key)
     assert np.array_equal(F1.cpu().numpy(), F2.cpu().numpy())
