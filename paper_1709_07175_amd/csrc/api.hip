@@ -216,7 +216,7 @@ static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool wan
             + ws_bytes<char>(p.esz * tn_partial_elems(k, (int)n, p.splits_f))
             + (p.splits_g ? ws_bytes<char>(p.esz * tn_partial_elems(k, k, p.splits_g)) : 0);
   if (p.h16) {
-    p.bytes += 2 * ws_bytes<uint16_t>((size_t)p.stripe * k);                    // Yh, Yl
+    p.bytes += 2 * ws_bytes<uint16_t>((size_t)(p.stripe + 8) * k);              // Yh, Yl (+ block padding)
     p.bytes += ws_bytes<unsigned>(k) + ws_bytes<float>(k) + ws_bytes<double>(k);  // FP16 scales
     p.bytes += ws_bytes<unsigned>((size_t)nt16_row_tiles(p.stripe) * k);           // tile maxima
     p.bytes += ws_bytes<int>(4);                                                 // flags
@@ -250,8 +250,8 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
   int *flags = nullptr;
   uint16_t *Yh = nullptr, *Yl = nullptr;
   if (pl.h16) {
-    Yh = ws.take<uint16_t>((size_t)pl.stripe * k);
-    Yl = ws.take<uint16_t>((size_t)pl.stripe * k);
+    Yh = ws.take<uint16_t>((size_t)(pl.stripe + 8) * k);
+    Yl = ws.take<uint16_t>((size_t)(pl.stripe + 8) * k);
     colmax = ws.take<unsigned>(k);
     colpart = ws.take<unsigned>((size_t)nt16_row_tiles(pl.stripe) * k);
     scale = ws.take<float>(k);
@@ -292,9 +292,10 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
       if (G) LSPCA_TRY(launch_reduce_add(xdt, PG, sg, (int64_t)k * k, G, 1, s));
       tm.mark(PH_REDUCE);
     } else {
-      // sketch, written transposed: BF16 directly split into Yh/Yl;
-      // FP16 as FP32 with column maxima, then scaled and split. With a
-      // hook, BF16 also goes through FP32 (split without scaling).
+      // sketch: BF16 directly split into Yh/Yl (transposed; in 8-row blocks
+      // from the gather kernel); FP16 as FP32 transposed with column maxima,
+      // then scaled and split. With a hook, BF16 also goes through FP32
+      // (split without scaling).
       uint16_t *Ylo = refine ? Yl : nullptr;
       const bool y32 = fp16 || hook;
       if (fp16) LSPCA_TRY(zero_i32((int *)colmax, k, s));
@@ -312,7 +313,9 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
       if (y32) LSPCA_TRY(launch_split16(xdt, (const float *)Y, k, rows, fp16 ? scale : nullptr, Yh, Ylo, s));
       tm.mark(PH_SKETCH);
       if (hook) LSPCA_TRY((*hook)(Y, rows, rows, true));
-      LSPCA_TRY(launch_tn16(xdt, Yh, Ylo, rows, Xs, ldx, (float *)PF, rows, k, (int)n, sf, s));
+      // the gather kernel writes its split sketch in 8-row blocks
+      LSPCA_TRY(launch_tn16(xdt, Yh, Ylo, rows, Xs, ldx, (float *)PF, rows, k, (int)n, sf, s,
+                            pl.gather && !y32));
       tm.mark(PH_FACTOR);
       const int accum = (r0 > 0) ? 1 : acc;
       LSPCA_TRY(launch_reduce_add(LSPCA_F32, PF, sf, (int64_t)k * n, Fdst, accum, s,

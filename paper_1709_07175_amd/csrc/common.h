@@ -165,10 +165,12 @@ int launch_nt16(lspca_dtype dt, const void *A, int64_t lda, const void *Bh,
                 const void *Bl, int64_t ldb, float *C, int64_t ldc, int64_t M,
                 int N, int K, unsigned *colmax, void *Ch, void *Cl, int mode,
                 hipStream_t s);
-// F partials from the transposed split sketch Yh/Yl[i*ldyt + r] and X.
+// F partials from the transposed split sketch Yh/Yl[i*ldyt + r] and X, or
+// (yblocked) from the sketch in 8-row blocks, (i, r) at ((r / 8) * Mi + i)
+// * 8 + r % 8, rows padded to a multiple of 8 (ldyt unused).
 int launch_tn16(lspca_dtype dt, const void *Yh, const void *Yl, int64_t ldyt,
                 const void *X, int64_t ldx, float *P, int64_t rows, int Mi, int Nj,
-                int splits, hipStream_t s);
+                int splits, hipStream_t s, bool yblocked = false);
 // Scale row c of Yt (rows_k x ld) by scale[c] and split into 16-bit parts.
 int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld,
                    const float *scale, void *Yh, void *Yl, hipStream_t s);
@@ -180,7 +182,9 @@ int launch_col_scales(const unsigned *colmax, int k, float *scale, double *inv,
                       hipStream_t s);
 // Very sparse sketch by gather-adds (sparse.hip).
 bool sparse_sketch_ok(lspca_dtype dt, int64_t n, int k, uint32_t p, int *cap_out);
-// Output as launch_nt16 modes 1 (Y FP32 + colmax) or 2 (Yh, Yl split).
+// Output as launch_nt16 mode 1 (Y FP32 transposed + colmax), or split into
+// Yh, Yl in 8-row blocks (the yblocked layout of launch_tn16; rows padded to
+// a multiple of 8, the padding rows left unwritten).
 int launch_sparse_sketch(lspca_dtype dt, const void *X, int64_t m, int64_t n, int64_t ldx, int k,
                          uint64_t seed, uint32_t p, int cap, float *Y, int64_t ldy,
                          unsigned *colmax, void *Yh, void *Yl, int *overflow, hipStream_t s);

@@ -317,14 +317,16 @@ __global__ void k_split16(const float *__restrict__ Yt, int64_t count, int64_t l
 
 // ------------------------------------------------------------------- TN16 --
 // Tile: BM (columns of Y) x 128 (columns of X) x BK rows; 4 waves as 2 x 2.
-// Y arrives transposed and already split into 16-bit parts, Yh[i][r] and
-// Yl[i][r] (leading dimension ldyt, rows contiguous; Yl NULL without
-// refinement), so its tiles go to LDS with 16-byte copies. X (16-bit rows,
+// Y arrives transposed and already split into 16-bit parts Yh, Yl (Yl NULL
+// without refinement), 8 consecutive rows of one column contiguous: element
+// (i, r) at (r / 8) * ysb + i * ysc + r % 8 (transposed: ysb = 8, ysc = the
+// leading dimension; blocked in 8-row blocks: ysb = 8 * columns, ysc = 8),
+// rows valid up to ylim, so its tiles go to LDS with 16-byte copies. X (16-bit rows,
 // leading dimension ldx): each thread loads pieces of 2 rows x 8 columns
 // and transposes them in registers into eight 2-row pieces of the
 // column-major LDS tile Bs[j][r]. Both LDS tiles are row-index contiguous,
 // so every MFMA fragment is one 16-byte read.
-// VEC (16-byte aligned rows, ldyt, ldx and Nj multiples of 8): loads are
+// VEC (16-byte aligned rows, ysc, ylim, ldx and Nj multiples of 8): loads are
 // issued unconditionally from clamped addresses and rows past the chunk are
 // zeroed at the LDS store, so the steady-state loop is branch-free and
 // LSPCA_TN16_STAGES register stages of K tiles stay in flight.
@@ -337,7 +339,8 @@ __global__ void k_split16(const float *__restrict__ Yt, int64_t count, int64_t l
 
 template <int DT, int BM, int BN, bool REFINE, bool VEC>
 __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
-                                              const uint16_t *__restrict__ Yl, int64_t ldyt,
+                                              const uint16_t *__restrict__ Yl, int64_t ysb, int64_t ysc,
+                                              int64_t ylim,
                                               const uint16_t *__restrict__ X, int64_t ldx,
                                               float *__restrict__ P, int64_t rows, int Mi, int Nj,
                                               int64_t chunk) {
@@ -375,12 +378,12 @@ __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
         const int64_t gr = r0 + kr;
         if constexpr (VEC) {
           const int ii = i0 + i < Mi ? i0 + i : Mi - 1;
-          const int64_t rr = gr + 8 <= ldyt ? gr : ldyt - 8;
-          ra[sl][part][v] = *(const u16x8 *)(Ysrc + (int64_t)ii * ldyt + rr);
+          const int64_t rr = gr + 8 <= ylim ? gr : ylim - 8;      // gr, ylim: multiples of 8
+          ra[sl][part][v] = *(const u16x8 *)(Ysrc + (rr >> 3) * ysb + (int64_t)ii * ysc);
         } else {
           u16x8 x = {};
           if (i0 + i < Mi) {
-            const uint16_t *src = Ysrc + (int64_t)(i0 + i) * ldyt + gr;
+            const uint16_t *src = Ysrc + (gr >> 3) * ysb + (int64_t)(i0 + i) * ysc;   // gr % 8 == 0
 #pragma unroll
             for (int e = 0; e < 8; ++e) x[e] = gr + e < rend ? src[e] : (uint16_t)0;
           }
@@ -640,41 +643,51 @@ int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld, 
 #endif
 
 template <int DT, int BM, bool REFINE>
-static int tn16_typed(const uint16_t *Yh, const uint16_t *Yl, int64_t ldyt, const uint16_t *X,
-                      int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
+static int tn16_typed(const uint16_t *Yh, const uint16_t *Yl, int64_t ysb, int64_t ysc, int64_t ylim,
+                      const uint16_t *X, int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
                       hipStream_t s) {
   constexpr int BN = (BM <= 128 || LSPCA_TN16_WIDE_ALL) ? LSPCA_TN16_WIDE_BN : 128;
   int64_t chunk = (rows + splits - 1) / splits;
   chunk = (chunk + 63) / 64 * 64;                 // a multiple of every K-tile depth
   dim3 grid((unsigned)((Nj + BN - 1) / BN), (unsigned)((Mi + BM - 1) / BM), (unsigned)splits);
-  const bool vec = (ldyt % 8 == 0) && ((uintptr_t)Yh % 16 == 0) && (!REFINE || (uintptr_t)Yl % 16 == 0) &&
-                   (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0) && (Nj % 8 == 0) && Nj >= 8 && ldyt >= 8;
+  const bool vec = (ysc % 8 == 0) && (ylim % 8 == 0) && ((uintptr_t)Yh % 16 == 0) &&
+                   (!REFINE || (uintptr_t)Yl % 16 == 0) && (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0) &&
+                   (Nj % 8 == 0) && Nj >= 8 && ylim >= 8;
   if (vec)
-    hipLaunchKernelGGL((k_tn16<DT, BM, BN, REFINE, true>), grid, dim3(256), 0, s, Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, chunk);
+    hipLaunchKernelGGL((k_tn16<DT, BM, BN, REFINE, true>), grid, dim3(256), 0, s, Yh, Yl, ysb, ysc, ylim, X, ldx,
+                       P, rows, Mi, Nj, chunk);
   else
-    hipLaunchKernelGGL((k_tn16<DT, BM, BN, REFINE, false>), grid, dim3(256), 0, s, Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, chunk);
+    hipLaunchKernelGGL((k_tn16<DT, BM, BN, REFINE, false>), grid, dim3(256), 0, s, Yh, Yl, ysb, ysc, ylim, X, ldx,
+                       P, rows, Mi, Nj, chunk);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }
 
 template <int DT>
-static int tn16_dt(const uint16_t *Yh, const uint16_t *Yl, int64_t ldyt, const uint16_t *X,
-                   int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits, hipStream_t s) {
+static int tn16_dt(const uint16_t *Yh, const uint16_t *Yl, int64_t ysb, int64_t ysc, int64_t ylim,
+                   const uint16_t *X, int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
+                   hipStream_t s) {
   if (Mi > 128) {
-    if (Yl) return tn16_typed<DT, 256, true>(Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, splits, s);
-    return tn16_typed<DT, 256, false>(Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, splits, s);
+    if (Yl) return tn16_typed<DT, 256, true>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
+    return tn16_typed<DT, 256, false>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
   }
-  if (Yl) return tn16_typed<DT, 128, true>(Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, splits, s);
-  return tn16_typed<DT, 128, false>(Yh, Yl, ldyt, X, ldx, P, rows, Mi, Nj, splits, s);
+  if (Yl) return tn16_typed<DT, 128, true>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
+  return tn16_typed<DT, 128, false>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
 }
 
 int launch_tn16(lspca_dtype dt, const void *Yh, const void *Yl, int64_t ldyt, const void *X,
-                int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits, hipStream_t s) {
+                int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits, hipStream_t s,
+                bool yblocked) {
   if (Mi <= 0 || Nj <= 0 || splits <= 0) return LSPCA_OK;
+  // transposed: (i, r) at i * ldyt + r; blocked: 8-row blocks of Mi columns
+  const int64_t ysb = yblocked ? 8 * (int64_t)Mi : 8, ysc = yblocked ? 8 : ldyt;
+  const int64_t ylim = yblocked ? (rows + 7) / 8 * 8 : ldyt;
   if (dt == LSPCA_BF16)
-    return tn16_dt<LSPCA_BF16>((const uint16_t *)Yh, (const uint16_t *)Yl, ldyt, (const uint16_t *)X, ldx, P, rows, Mi, Nj, splits, s);
+    return tn16_dt<LSPCA_BF16>((const uint16_t *)Yh, (const uint16_t *)Yl, ysb, ysc, ylim, (const uint16_t *)X,
+                               ldx, P, rows, Mi, Nj, splits, s);
   if (dt == LSPCA_F16)
-    return tn16_dt<LSPCA_F16>((const uint16_t *)Yh, (const uint16_t *)Yl, ldyt, (const uint16_t *)X, ldx, P, rows, Mi, Nj, splits, s);
+    return tn16_dt<LSPCA_F16>((const uint16_t *)Yh, (const uint16_t *)Yl, ysb, ysc, ylim, (const uint16_t *)X,
+                              ldx, P, rows, Mi, Nj, splits, s);
   set_error("tn16 product: dtype %d", (int)dt);
   return LSPCA_ENOTSUP;
 }

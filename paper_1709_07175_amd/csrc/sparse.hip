@@ -169,8 +169,8 @@ __global__ __launch_bounds__(kSpThreads) void k_sparse_sketch(
             }
           }
         }
-        // Y is written transposed (ldy = rows of the stripe): as FP32 Yt[c][r]
-        // (Y != NULL), or split into 16-bit parts Yh[c][r], Yl[c][r]
+        // Y is written as FP32 transposed, Yt[c][r] (Y != NULL, ldy = rows of
+        // the stripe), or split into 16-bit parts Yh, Yl in 8-row blocks
         const f32x4 a = {a0, a1, a2, a3};
         const bool full = r0 + 3 < m && (ldy & 3) == 0;
         if (Y) {
@@ -189,9 +189,11 @@ __global__ __launch_bounds__(kSpThreads) void k_sparse_sketch(
             hv[r] = f2h<DT>(a[r]);
             lv[r] = f2h<DT>(a[r] - h2f<DT>(hv[r]));
           }
-          uint16_t *dh = Yh + (int64_t)c * ldy + r0;
-          uint16_t *dl = Yl ? Yl + (int64_t)c * ldy + r0 : nullptr;
-          if (full) {
+          // in 8-row blocks of k columns (r0 % 8 is 0 or 4)
+          const int64_t ob = ((r0 >> 3) * k + c) * 8 + (r0 & 7);
+          uint16_t *dh = Yh + ob;
+          uint16_t *dl = Yl ? Yl + ob : nullptr;
+          if (r0 + 3 < m) {
             *(u16x4 *)dh = hv;
             if (dl) *(u16x4 *)dl = lv;
           } else {
@@ -229,8 +231,9 @@ __global__ __launch_bounds__(kSpThreads) void k_sparse_sketch(
 // LDS read (the 8 rows of one feature) and 8 FP32 fmas with the lane's sign.
 // The parts are summed in a fixed tree (positives, negatives, then both), so
 // the result does not depend on timing. The X tile is double-buffered in LDS:
-// feature slots of the two buffers interleaved (slot address * 32 + 16 *
-// buffer), slots swizzled so that the staging writes spread over the banks;
+// the buffers alternate every 16 slots (256 bytes, so a buffer keeps all
+// banks and the second is the first plus 256), slots swizzled so that the
+// staging writes spread over the banks;
 // slot `zslot` holds zeros and pads every run to a whole number of steps.
 // Runs longer than the register capacity (a far-tail event for the shapes the
 // host admits) switch the workgroup to regenerating Omega on the fly in the
@@ -242,6 +245,9 @@ constexpr int kGxLQ = 40;               // register run capacity, multiple of 4
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int gx_slot(int f) { return f ^ ((f >> 4) & 7); }
+// LDS byte address of slot s in buffer 0; buffer 1 is 256 bytes further:
+// groups of 16 slots (256 bytes, every bank once) alternate between buffers
+__device__ __forceinline__ uint32_t gx_addr(int s) { return (uint32_t)(((s >> 4) * 2) * 256 + (s & 15) * 16); }
 
 typedef __attribute__((address_space(3))) const u32x4 gx_lds_u32x4;
 // 16 bytes at an LDS byte address (the kernel has no static LDS, so its
@@ -267,7 +273,10 @@ template <int LPC, bool MAX> __device__ __forceinline__ float gx_reduce(float v)
 // One step: +-x for the 8 rows of a feature (4 dwords, row 2d in the low and
 // row 2d+1 in the high half of dword d), each an FP32 fma with s = +-1, i.e.
 // one correctly rounded addition. FP16 halves convert inside the fma
-// (v_fma_mix_f32); a BF16 half is the FP32 with the same top 16 bits.
+// (v_fma_mix_f32); a BF16 half is the FP32 with the same top 16 bits (one
+// shift or mask). (The BF16 dot2 instruction would do both in one
+// instruction but issues at under half the rate of an fma here and rounds
+// its addition only faithfully.)
 template <int DT>
 __device__ __forceinline__ void gx_step(u32x4 xv, float s, float (&acc)[kGxRows]) {
 #pragma unroll
@@ -285,29 +294,28 @@ __device__ __forceinline__ void gx_step(u32x4 xv, float s, float (&acc)[kGxRows]
   }
 }
 
-// The run of one lane over buffer BUF: blocks of 4 steps, the next block's
-// reads issued before the current block's arithmetic (the padding addresses
-// past the run point at the zero slot, so reading ahead is always in bounds).
+// The run of one lane over buffer BUF in blocks of 4 steps (lq rounded up;
+// the padding addresses past the run point at the zero slot): a step's
+// registers are refilled with the read 4 steps ahead right after they are
+// taken, so 4 reads stay in flight (reading ahead is always in bounds).
 template <int DT, int BUF>
 __device__ __forceinline__ void gx_run(const uint32_t (&ent)[kGxLQ], int lq, float sg, float (&acc)[kGxRows]) {
-  u32x4 cur[4], nxt[4];
+  u32x4 buf[4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) cur[t] = gx_read(ent[t] + 16 * BUF);
+  for (int t = 0; t < 4; ++t) buf[t] = gx_read(ent[t] + 256 * BUF);
 #pragma unroll
   for (int b = 0; b < kGxLQ / 4; ++b) {
     if (4 * b >= lq) break;
-    if (b + 1 < kGxLQ / 4) {
 #pragma unroll
-      for (int t = 0; t < 4; ++t) nxt[t] = gx_read(ent[4 * b + 4 + t] + 16 * BUF);
+    for (int t = 0; t < 4; ++t) {
+      const u32x4 x = buf[t];
+      if (b + 1 < kGxLQ / 4) buf[t] = gx_read(ent[4 * b + 4 + t] + 256 * BUF);
+      gx_step<DT>(x, sg, acc);
     }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) gx_step<DT>(cur[t], sg, acc);
-#pragma unroll
-    for (int t = 0; t < 4; ++t) cur[t] = nxt[t];
   }
   // A use of the last read-ahead on the way out (never taken: lq >= 0) keeps
   // the compiler from sinking each block's read-ahead below its exit test.
-  if (lq < 0) acc[0] = __uint_as_float(cur[0][0] ^ cur[1][1] ^ cur[2][2] ^ cur[3][3]);
+  if (lq < 0) acc[0] = __uint_as_float(buf[0][0] ^ buf[1][1] ^ buf[2][2] ^ buf[3][3]);
 }
 
 // Sum of the LPC parts of a column, scattered: a lane keeps half of its
@@ -346,7 +354,8 @@ __device__ __forceinline__ void gx_scatter(float (&v)[kGxRows], int q, int &row0
 // 16-bit ], then reused as the two interleaved X buffers ((8 ceil(n/8) + 1)
 // slots x 32 bytes). tiles_per_wg consecutive 8-row tiles per workgroup, so
 // the transposed outputs of neighbouring tiles are written from one CU.
-template <int DT, int LPC>
+// VEC: n and ldx multiples of 8 and X 16-byte aligned (16-byte row loads).
+template <int DT, int LPC, bool VEC>
 __global__ __launch_bounds__(kGxThreads) void k_sparse_sketch_reg(
     const uint16_t *__restrict__ X, int64_t m, int n, int64_t ldx, int k, uint32_t key0,
     uint32_t key1, uint32_t t_plus, uint64_t t_minus, int lq_cap, int64_t tiles_per_wg,
@@ -410,14 +419,14 @@ __global__ __launch_bounds__(kGxThreads) void k_sparse_sketch_reg(
     const int b = 2 * col + sgn;
     const int len = live ? cnt[b] : 0;
 #pragma unroll
-    for (int s = 0; s < kGxLQ; ++s) {
-      const int i = part * lq + s;
+    for (int st = 0; st < kGxLQ; ++st) {
+      const int i = part * lq + st;
       int slot = zslot;
-      if (fits && s < lq && i < len) slot = gx_slot(bucket[b * CAP + i]);
-      ent[s] = (uint32_t)slot * 32;
-      // hide the alignment of the address, so that + 16 (the second buffer)
+      if (fits && st < lq && i < len) slot = gx_slot(bucket[b * CAP + i]);
+      ent[st] = gx_addr(slot);
+      // hide the alignment of the address, so that + 256 (the second buffer)
       // stays an add and folds into the read's offset field
-      asm volatile("" : "+v"(ent[s]));
+      asm volatile("" : "+v"(ent[st]));
     }
   }
   __syncthreads();                                 // the X buffers overwrite the buckets
@@ -426,8 +435,7 @@ __global__ __launch_bounds__(kGxThreads) void k_sparse_sketch_reg(
   const int64_t ntiles = (m + kGxRows - 1) / kGxRows;
   const int64_t t0 = (int64_t)blockIdx.x * tiles_per_wg;
   const int64_t t1 = t0 + tiles_per_wg < ntiles ? t0 + tiles_per_wg : ntiles;
-  if (tid < 2) *(u32x4 *)(lds + (2 * zslot + tid) * 16) = u32x4{0u, 0u, 0u, 0u};
-  const bool vec = (ldx % 8) == 0 && ((uintptr_t)X % 16) == 0;
+  if (tid < 2) *(u32x4 *)(lds + gx_addr(zslot) + 256 * tid) = u32x4{0u, 0u, 0u, 0u};
   // staging: thread = feature group g (8 features) x row half h (4 rows);
   // 2 ceil(n/8) <= 1024 units (the host admits n <= 4096)
   const int ug = tid % ngroups, uh = tid / ngroups;      // uh >= 2: idle
@@ -436,18 +444,23 @@ __global__ __launch_bounds__(kGxThreads) void k_sparse_sketch_reg(
     const int64_t r0 = tile * kGxRows;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + 4 * uh + r;
-      u16x8 x = {};
-      if (uh < 2 && row < m) {
-        const uint16_t *src = X + row * ldx + 8 * ug;
-        if (vec && 8 * ug + 7 < n) {
-          x = *(const u16x8 *)src;
-        } else {
+      if (VEC) {
+        // one unconditional 16-byte load per row, the row clamped into X:
+        // rows past m only feed their own (unwritten) outputs, and a load
+        // with no branch around it stays in flight through the compute
+        int64_t row = r0 + 4 * (uh < 2 ? uh : 1) + r;
+        row = row < m ? row : m - 1;
+        v[r] = *(const u16x8 *)(X + row * ldx + 8 * ug);
+      } else {
+        const int64_t row = r0 + 4 * uh + r;
+        u16x8 x = {};
+        if (uh < 2 && row < m) {
+          const uint16_t *src = X + row * ldx + 8 * ug;
 #pragma unroll
           for (int e = 0; e < 8; ++e) x[e] = 8 * ug + e < n ? src[e] : (uint16_t)0;
         }
+        v[r] = x;
       }
-      v[r] = x;
     }
   };
   auto store = [&](int buf) {
@@ -455,7 +468,7 @@ __global__ __launch_bounds__(kGxThreads) void k_sparse_sketch_reg(
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const u16x4 w = {v[0][e], v[1][e], v[2][e], v[3][e]};
-      *(u16x4 *)(lds + (2 * gx_slot(8 * ug + e) + buf) * 16 + 8 * uh) = w;
+      *(u16x4 *)(lds + gx_addr(gx_slot(8 * ug + e)) + 256 * buf + 8 * uh) = w;
     }
   };
   const float sg = sgn ? -1.f : 1.f;
@@ -472,8 +485,13 @@ __global__ __launch_bounds__(kGxThreads) void k_sparse_sketch_reg(
 #pragma unroll
     for (int r = 0; r < kGxRows; ++r) acc[r] = 0.f;
     if (fits) {
-      if (buf == 0) gx_run<DT, 0>(ent, lq, sg, acc);
-      else gx_run<DT, 1>(ent, lq, sg, acc);
+      // the run length made opaque per tile (it is uniform: an SGPR), so
+      // the block exit tests are made where they are used instead of being
+      // hoisted out of the tile loop into spilled masks
+      int lqt = lq;
+      asm volatile("" : "+s"(lqt));
+      if (buf == 0) gx_run<DT, 0>(ent, lqt, sg, acc);
+      else gx_run<DT, 1>(ent, lqt, sg, acc);
     } else if (live) {
       // on the fly, same entries in the same order as the run
       const int lo = part * lq, hi = lo + lq;
@@ -484,7 +502,7 @@ __global__ __launch_bounds__(kGxThreads) void k_sparse_sketch_reg(
         const uint32_t w = (col & 3) == 0 ? x[0] : (col & 3) == 1 ? x[1] : (col & 3) == 2 ? x[2] : x[3];
         if ((uint64_t)w < t_minus && (w < t_plus ? 0 : 1) == sgn) {
           if (rank >= lo) {
-            const u32x4 xv = *(const u32x4 *)(lds + (2 * gx_slot(j) + buf) * 16);
+            const u32x4 xv = *(const u32x4 *)(lds + gx_addr(gx_slot(j)) + 256 * buf);
             gx_step<DT>(xv, sg, acc);
           }
           ++rank;
@@ -497,21 +515,32 @@ __global__ __launch_bounds__(kGxThreads) void k_sparse_sketch_reg(
     const int64_t r0 = tile * kGxRows;
     constexpr int RPL = LPC == 4 ? 2 : 1;
     const bool writer = live && (LPC < 16 || q < 8);
+    if (Y) {
+      // FP32, transposed: Y[c * ldy + r]
 #pragma unroll
-    for (int i = 0; i < RPL; ++i) {
-      const int rr = row0 + i;
-      if (!writer || r0 + rr >= m) continue;
-      const float val = acc[i];
-      const int64_t o = (int64_t)col * ldy + r0 + rr;
-      if (Y) {
-        Y[o] = val;
-      } else {
-        const uint16_t hv = f2h<DT>(val);
-        Yh[o] = hv;
-        if (Yl) Yl[o] = f2h<DT>(val - h2f<DT>(hv));
+      for (int i = 0; i < RPL; ++i)
+        if (writer && r0 + row0 + i < m) Y[(int64_t)col * ldy + r0 + row0 + i] = acc[i];
+    } else if (writer) {
+      // split, in 8-row blocks: the tile's block is k columns x 8 rows, so a
+      // wave's stores cover 16 columns x 16 bytes contiguously
+      const int64_t o = ((int64_t)tile * k + col) * kGxRows + row0;
+      uint16_t hv[RPL], lv[RPL];
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        hv[i] = f2h<DT>(acc[i]);
+        lv[i] = f2h<DT>(acc[i] - h2f<DT>(hv[i]));
       }
-      amax = fmaxf(amax, fabsf(val));
+      if (RPL == 2 && r0 + row0 + 1 < m) {
+        *(uint32_t *)(Yh + o) = (uint32_t)hv[0] | ((uint32_t)hv[RPL - 1] << 16);
+        if (Yl) *(uint32_t *)(Yl + o) = (uint32_t)lv[0] | ((uint32_t)lv[RPL - 1] << 16);
+      } else if (r0 + row0 < m) {
+        Yh[o] = hv[0];
+        if (Yl) Yl[o] = lv[0];
+      }
     }
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+      if (writer && r0 + row0 + i < m) amax = fmaxf(amax, fabsf(acc[i]));
     __syncthreads();
   }
   if (colmax) {
@@ -554,7 +583,7 @@ static bool gx_plan(lspca_dtype dt, int64_t n, int k, uint32_t p, GxPlan &g) {
   g.lpc = k > 128 ? 4 : (k > 64 ? 8 : 16);
   const int cap = g.lpc / 2 * kGxLQ;
   const int64_t ngroups = (n + 7) / 8;
-  const size_t xb = (size_t)(8 * ngroups + 1) * 32;
+  const size_t xb = (size_t)((8 * ngroups) / 16 * 2 + 2) * 256;   // through the zero slot of buffer 1
   const size_t gen = ((8 * (size_t)k + 4 + 15) & ~(size_t)15) + (size_t)2 * k * cap * 2;
   g.lds = xb > gen ? xb : gen;
   if (g.lds > 160 * 1024) return false;
@@ -584,12 +613,12 @@ bool sparse_sketch_ok(lspca_dtype dt, int64_t n, int k, uint32_t p, int *cap_out
   return true;
 }
 
-template <int DT, int LPC>
+template <int DT, int LPC, bool VEC>
 static int launch_reg(const GxPlan &g, unsigned grid, const void *X, int64_t m, int64_t n, int64_t ldx,
                       int k, uint32_t key0, uint32_t key1, uint32_t t_plus, uint64_t t_minus, int lq_cap,
                       int64_t per, float *Y, int64_t ldy, unsigned *colmax, void *Yh, void *Yl,
                       int *overflow, hipStream_t s) {
-  const void *fn = (const void *)k_sparse_sketch_reg<DT, LPC>;
+  const void *fn = (const void *)k_sparse_sketch_reg<DT, LPC, VEC>;
   hipFuncAttributes fa;
   LSPCA_HIP(hipFuncGetAttributes(&fa, fn));
   if (fa.sharedSizeBytes != 0) {           // LDS addresses assume dynamic LDS at 0
@@ -597,7 +626,7 @@ static int launch_reg(const GxPlan &g, unsigned grid, const void *X, int64_t m, 
     return LSPCA_EINVAL;
   }
   LSPCA_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)g.lds));
-  hipLaunchKernelGGL((k_sparse_sketch_reg<DT, LPC>), grid, kGxThreads, g.lds, s, (const uint16_t *)X, m,
+  hipLaunchKernelGGL((k_sparse_sketch_reg<DT, LPC, VEC>), grid, kGxThreads, g.lds, s, (const uint16_t *)X, m,
                      (int)n, ldx, k, key0, key1, t_plus, t_minus, lq_cap, per, Y, ldy, colmax,
                      (uint16_t *)Yh, (uint16_t *)Yl, overflow);
   LSPCA_HIP(hipGetLastError());
@@ -609,14 +638,16 @@ static int launch_reg_dt(const GxPlan &g, unsigned grid, const void *X, int64_t 
                          int k, uint32_t key0, uint32_t key1, uint32_t t_plus, uint64_t t_minus, int lq_cap,
                          int64_t per, float *Y, int64_t ldy, unsigned *colmax, void *Yh, void *Yl,
                          int *overflow, hipStream_t s) {
-  if (g.lpc == 4)
-    return launch_reg<DT, 4>(g, grid, X, m, n, ldx, k, key0, key1, t_plus, t_minus, lq_cap, per, Y, ldy, colmax,
-                             Yh, Yl, overflow, s);
-  if (g.lpc == 8)
-    return launch_reg<DT, 8>(g, grid, X, m, n, ldx, k, key0, key1, t_plus, t_minus, lq_cap, per, Y, ldy, colmax,
-                             Yh, Yl, overflow, s);
-  return launch_reg<DT, 16>(g, grid, X, m, n, ldx, k, key0, key1, t_plus, t_minus, lq_cap, per, Y, ldy, colmax,
-                            Yh, Yl, overflow, s);
+  const bool vec = n % 8 == 0 && ldx % 8 == 0 && (uintptr_t)X % 16 == 0;
+#define LSPCA_GX(L, V)                                                                                     \
+  if (g.lpc == L && vec == V)                                                                              \
+    return launch_reg<DT, L, V>(g, grid, X, m, n, ldx, k, key0, key1, t_plus, t_minus, lq_cap, per, Y, ldy, \
+                                colmax, Yh, Yl, overflow, s);
+  LSPCA_GX(4, true) LSPCA_GX(8, true) LSPCA_GX(16, true) LSPCA_GX(4, false) LSPCA_GX(8, false)
+  LSPCA_GX(16, false)
+#undef LSPCA_GX
+  set_error("sparse sketch: no kernel for %d lanes per column", g.lpc);
+  return LSPCA_EINVAL;
 }
 
 int launch_sparse_sketch(lspca_dtype dt, const void *X, int64_t m, int64_t n, int64_t ldx, int k,
