@@ -336,7 +336,7 @@ static size_t factor_bytes(int64_t n, int k) {
   const int splits = tn_pick_splits(n, k, k);
   const size_t kk = (size_t)k * k;
   return 4 * ws_bytes<double>((size_t)n * k) + ws_bytes<double>(tn_partial_elems(k, k, splits)) +
-         6 * ws_bytes<double>(kk) + 2 * ws_bytes<double>(k) + ws_bytes<int>(4) +
+         6 * ws_bytes<double>(kk) + 2 * ws_bytes<double>(k) + ws_bytes<int>(kSmallFlags) +
          ws_bytes<double>(4 * kk) +
          ws_bytes<double>(3 * 128 * 128);
 }

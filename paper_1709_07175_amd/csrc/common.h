@@ -191,6 +191,7 @@ int launch_sparse_sketch(lspca_dtype dt, const void *X, int64_t m, int64_t n, in
 size_t tn_partial_elems(int Mi, int Nj, int splits);
 
 // Reductions and small FP64 stage (small.hip).
+constexpr int kSmallFlags = 128;   // flag and sweep-counter ints of the small stage
 // out[e] (+)= rowscale[e / ncols] * sum_s P[s][e] (rowscale may be NULL).
 int launch_reduce_add(lspca_dtype pdt, const void *P, int splits, int64_t count,
                       double *out, int accumulate, hipStream_t s,

@@ -15,10 +15,13 @@
 //      Q^T X of eq. (approx_svd) without a tall QR).
 #include "common.h"
 
+#include <hip/hip_cooperative_groups.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <vector>
 
 namespace lspca {
@@ -207,8 +210,9 @@ __global__ void k_to_cols(const double *__restrict__ A, int k, double *__restric
 // ------------------------------------------------ one-sided Jacobi ------
 // Columns live in LDS with a padded stride (len + 1 doubles) so that the
 // groups of one wave, each reading a different column, hit different banks.
-constexpr int kLdsDoubles = 16384;   // problem size limit: k*k or 2b*k doubles
 constexpr int kLdsAlloc = 16640;     // allocation incl. padding (130 KB)
+constexpr int kJacobiMaxSweeps = 40;
+namespace cg = cooperative_groups;
 
 // Sum over G lanes (16: one DPP row; 32, 64: rows combined by lane
 // exchanges). Every lane receives the same bits (each step adds the same
@@ -297,12 +301,80 @@ __device__ inline bool rotate_any(double *ap, double *aq, int len, int gl, doubl
   return rotate_long<16>(ap, aq, len, gl, tol);
 }
 
-// The same with a whole wave (64 lanes) per pair.
-__device__ inline bool rotate_any64(double *ap, double *aq, int len, int gl, double tol) {
-  if (len <= 128) return rotate_pair<2, 64>(ap, aq, len, gl, tol);
-  if (len <= 256) return rotate_pair<4, 64>(ap, aq, len, gl, tol);
-  if (len <= 512) return rotate_pair<8, 64>(ap, aq, len, gl, tol);
-  return rotate_long<64>(ap, aq, len, gl, tol);
+
+// Rotation of a pair from al, be, ga as jacobi_cs, also returning t = s / c,
+// with the square roots and reciprocals from the hardware estimates and one
+// Newton step each (relative error a few ulps; c^2 + s^2 = 1 to a few ulps,
+// which is what keeps the rotation orthogonal).
+__device__ inline double rsqrt_nr(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-0.5 * x * y, y, 1.5);
+}
+__device__ inline double rcp_nr(double x) {
+  const double y = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ inline bool jacobi_cst(double al, double be, double ga, double tol, double &c, double &sn,
+                                  double &t) {
+  if (!(ga != 0.0 && ga * ga > (tol * tol) * (al * be))) return false;
+  const double d = be - al, h2 = fma(d, d, 4.0 * ga * ga);
+  const double h = h2 * rsqrt_nr(h2);                         // sqrt(d^2 + 4 ga^2) > 0
+  t = (d >= 0 ? 2.0 * ga : -2.0 * ga) * rcp_nr(fabs(d) + h);
+  c = rsqrt_nr(fma(t, t, 1.0));
+  sn = c * t;
+  return true;
+}
+
+// G lanes per pair (rows gl + G i) with the squared norms kept in LDS (np,
+// nq): only ga = a_p.a_q is summed over lanes, and the norms are updated with
+// the identities |c a_p - s a_q|^2 = al - t ga, |s a_p + c a_q|^2 = be + t ga
+// (t = s / c, which makes the new pair orthogonal); lane 0 of the group
+// writes them. The caller recomputes the norms from the columns whenever it
+// loads them. ROWS = 0: any length, two passes over LDS.
+template <int G, int ROWS>
+__device__ inline bool rotate_nrm(double *ap, double *aq, double *np, double *nq, int len, int gl,
+                                  double tol) {
+  const double al = *np, be = *nq;
+  double c, sn, t, ga = 0;
+  double x[ROWS > 0 ? ROWS : 1], y[ROWS > 0 ? ROWS : 1];
+  if constexpr (ROWS > 0) {
+    double gb = 0;                                  // two chains of fmas
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      const int r = gl + G * i;
+      x[i] = r < len ? ap[r] : 0.0;
+      y[i] = r < len ? aq[r] : 0.0;
+      if (i & 1) gb = fma(x[i], y[i], gb);
+      else ga = fma(x[i], y[i], ga);
+    }
+    ga += gb;
+  } else {
+    for (int r = gl; r < len; r += G) ga = fma(ap[r], aq[r], ga);
+  }
+  ga = sum_lanes<G>(ga);
+  if (!jacobi_cst(al, be, ga, tol, c, sn, t)) return false;
+  if constexpr (ROWS > 0) {
+#pragma unroll
+    for (int i = 0; i < ROWS; ++i) {
+      const int r = gl + G * i;
+      if (r < len) {
+        ap[r] = c * x[i] - sn * y[i];
+        aq[r] = sn * x[i] + c * y[i];
+      }
+    }
+  } else {
+    for (int r = gl; r < len; r += G) {
+      const double xv = ap[r], yv = aq[r];
+      ap[r] = c * xv - sn * yv;
+      aq[r] = sn * xv + c * yv;
+    }
+  }
+  if (gl == 0) {
+    *np = fmax(fma(-t, ga, al), 0.0);
+    *nq = fma(t, ga, be);
+  }
+  return true;
 }
 
 // Round-robin pair (i-th of round s) over nc' = even(nc) columns:
@@ -339,7 +411,7 @@ __device__ void lds_sweep_all(double *cols, int nc, int len, int ld, double tol,
   }
 }
 
-// Whole k x k problem in one workgroup (k*k <= kLdsDoubles): Wc (column
+// Whole k x k problem in one workgroup (k (k + 1) <= kLdsAlloc): Wc (column
 // storage, global) is loaded into LDS, swept to convergence, written back.
 __global__ __launch_bounds__(1024) void k_jacobi_lds(double *Wc, int k, double tol, int max_sweeps,
                                                      int *sweeps_out) {
@@ -368,25 +440,46 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(double *Wc, int k, double t
 // of b disjoint pairs: p = i, q = (i + s) mod b). In round 0 it first
 // rotates the pairs inside I and inside J, so one outer sweep (nb - 1
 // rounds) visits every column pair exactly once. Rotations set flag[0].
-__global__ __launch_bounds__(1024) void k_jacobi_block(double *Wc, int k, int b, int nb, int round,
-                                                       double tol, int *flag) {
-  __shared__ double cols[kLdsAlloc];
-  __shared__ int counter;
+// One outer round for workgroup `wg` (G lanes per column or column pair, b
+// groups): returns (in every thread) the number of rotations it made. cols:
+// LDS for 2b columns of stride k + 1; nrm: their squared norms.
+template <int G, int ROWS>
+__device__ int jacobi_block_round(double *Wc, int k, int b, int nb, int round, int wg, double tol,
+                                  double *cols, double *nrm, int *counter) {
   const int L = nb - 1, ld = k + 1;
   int I, J;
-  rr_pair(round, blockIdx.x, L, I, J);
+  rr_pair(round, wg, L, I, J);
   const int i0 = I * b, j0 = J * b;
   const int ni = max(0, min(k, i0 + b) - i0), nj = max(0, min(k, j0 + b) - j0);
   const int nc = ni + nj;
-  for (int64_t e = threadIdx.x; e < (int64_t)nc * k; e += blockDim.x) {
-    const int c = (int)(e / k), r = (int)(e % k);
-    const int gc = c < ni ? i0 + c : j0 + (c - ni);
-    cols[c * ld + r] = Wc[(int64_t)gc * k + r];
+  // one group per column: load it (contiguous) and its squared norm; then
+  // one group per column pair
+  const int g = threadIdx.x / G, gl = threadIdx.x % G, ng = blockDim.x / G;
+  if (threadIdx.x == 0) *counter = 0;
+  for (int c = g; c < nc; c += ng) {
+    const double *src = Wc + (int64_t)(c < ni ? i0 + c : j0 + (c - ni)) * k;
+    double v = 0;
+    if constexpr (ROWS > 0) {
+      double x[ROWS];                               // all loads in flight at once
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) x[i] = gl + G * i < k ? src[gl + G * i] : 0.0;
+#pragma unroll
+      for (int i = 0; i < ROWS; ++i) {
+        if (gl + G * i < k) cols[c * ld + gl + G * i] = x[i];
+        v = fma(x[i], x[i], v);
+      }
+    } else {
+      for (int r = gl; r < k; r += G) {
+        const double x = src[r];
+        cols[c * ld + r] = x;
+        v = fma(x, x, v);
+      }
+    }
+    v = sum_lanes<G>(v);
+    if (gl == 0) nrm[c] = v;
   }
-  if (threadIdx.x == 0) counter = 0;
   __syncthreads();
-  // one wave per column pair
-  const int g = threadIdx.x >> 6, gl = threadIdx.x & 63, ng = blockDim.x >> 6;
+  int rot = 0;
   if (round == 0) {
     // pairs inside I and inside J: two interleaved round-robins
     const int bp = (max(ni, nj) + 1) & ~1, Lb = bp - 1, half = bp / 2;
@@ -397,9 +490,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double *Wc, int k, int b,
         int p, q;
         rr_pair(s, i, Lb, p, q);
         if (p < nside && q < nside) {
-          if (rotate_any64(cols + (base + min(p, q)) * ld, cols + (base + max(p, q)) * ld, k, gl, tol) &&
-              gl == 0)
-            atomicAdd(&counter, 1);
+          const int a = base + min(p, q), bq = base + max(p, q);
+          rot += rotate_nrm<G, ROWS>(cols + a * ld, cols + bq * ld, nrm + a, nrm + bq, k, gl, tol);
         }
       }
       __syncthreads();
@@ -409,19 +501,57 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double *Wc, int k, int b,
   for (int s = 0; s < bb; ++s) {
     for (int i = g; i < bb; i += ng) {
       const int j = i + s - (i + s >= bb ? bb : 0);
-      if (i < ni && j < nj) {
-        if (rotate_any64(cols + i * ld, cols + (ni + j) * ld, k, gl, tol) && gl == 0)
-          atomicAdd(&counter, 1);
-      }
+      if (i < ni && j < nj)
+        rot += rotate_nrm<G, ROWS>(cols + i * ld, cols + (ni + j) * ld, nrm + i, nrm + ni + j, k, gl, tol);
     }
     __syncthreads();
   }
-  for (int64_t e = threadIdx.x; e < (int64_t)nc * k; e += blockDim.x) {
-    const int c = (int)(e / k), r = (int)(e % k);
-    const int gc = c < ni ? i0 + c : j0 + (c - ni);
-    Wc[(int64_t)gc * k + r] = cols[c * ld + r];
+  for (int c = g; c < nc; c += ng) {
+    double *dst = Wc + (int64_t)(c < ni ? i0 + c : j0 + (c - ni)) * k;
+    for (int r = gl; r < k; r += G) dst[r] = cols[c * ld + r];
   }
-  if (threadIdx.x == 0 && counter) atomicOr(flag, 1);
+  if (gl == 0 && rot) atomicAdd(counter, rot);
+  __syncthreads();
+  return *counter;
+}
+
+template <int G, int ROWS>
+__global__ __launch_bounds__(1024) void k_jacobi_block(double *Wc, int k, int b, int nb, int round,
+                                                       double tol, int *flag) {
+  __shared__ double cols[kLdsAlloc];
+  __shared__ double nrm[64];
+  __shared__ int counter;
+  const int n = jacobi_block_round<G, ROWS>(Wc, k, b, nb, round, blockIdx.x, tol, cols, nrm, &counter);
+  if (threadIdx.x == 0 && n) atomicOr(flag, 1);
+}
+
+// All sweeps in one cooperative launch (every workgroup resident): outer
+// rounds separated by grid barriers (device-scope release and acquire, so
+// the columns stored in one round are seen by the next round's loads).
+// counts[sweep] (zeroed by the caller) sums the sweep's rotations; every
+// workgroup reads it after the sweep's last barrier, so all stop together.
+template <int G, int ROWS>
+__global__ __launch_bounds__(1024) void k_jacobi_coop(double *Wc, int k, int b, int nb, double tol,
+                                                      int max_sweeps, int *counts, int *sweeps_out) {
+  __shared__ double cols[kLdsAlloc];
+  __shared__ double nrm[64];
+  __shared__ int counter, total;
+  cg::grid_group grid = cg::this_grid();
+  int sweep = 0;
+  while (sweep < max_sweeps) {
+    for (int round = 0; round < nb - 1; ++round) {
+      const int n = jacobi_block_round<G, ROWS>(Wc, k, b, nb, round, blockIdx.x, tol, cols, nrm, &counter);
+      if (threadIdx.x == 0 && n) atomicAdd(counts + sweep, n);
+      __threadfence();
+      grid.sync();
+    }
+    if (threadIdx.x == 0) total = atomicAdd(counts + sweep, 0);
+    __syncthreads();
+    ++sweep;
+    if (total == 0) break;
+    __syncthreads();
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *sweeps_out = sweep;
 }
 
 // Column norms sigma_c = |Wc[c]|, ranks by decreasing sigma (ties: lower c
@@ -618,20 +748,51 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
       LSPCA_HIP(hipStreamSynchronize(s));
     }
   } else {
-    // blocks of b columns, nb even, 2b padded columns of length k fit in LDS;
-    // one wave per pair, so b <= 16 pairs per round in a 1024-thread block
-    const int bmax = std::min(kLdsAlloc / (2 * (k + 1)), 16);
+    // blocks of b <= 32 columns, nb even, 2b padded columns of length k fit
+    // in LDS; b groups of G lanes per workgroup, G = 16 (one DPP row, up to
+    // 16 rows each) up to k = 256, 32 up to 512, else 64 looping over rows
+    const int G = k <= 256 ? 16 : (k <= 512 ? 32 : 64);
+    const int bmax = std::min(std::min(kLdsAlloc / (2 * (k + 1)), 1024 / G), 32);
     if (bmax < 1) {
       set_error("jacobi: k = %d too large for the block kernel", k);
       return LSPCA_ENOTSUP;
     }
     const int nb = 2 * ((k + 2 * bmax - 1) / (2 * bmax));
     const int b = (k + nb - 1) / nb;
+    // one cooperative launch for all sweeps (no host round trip per sweep);
+    // LSPCA_JACOBI=launches keeps one launch per round (a test knob)
+    const char *knob = getenv("LSPCA_JACOBI");
+    bool done = false;
+    if (!(knob && !strcmp(knob, "launches"))) {
+      LSPCA_TRY(zero_i32(dflag, kJacobiMaxSweeps, s));
+      int *counts = dflag, *swo = dflag + kJacobiMaxSweeps;
+      double *wc = Wc;
+      int kk2 = k, bb = b, nbb = nb, ms = kJacobiMaxSweeps;
+      double tl = tol;
+      void *args[] = {&wc, &kk2, &bb, &nbb, &tl, &ms, &counts, &swo};
+      const void *fn = G == 16 ? (const void *)k_jacobi_coop<16, 16>
+                               : G == 32 ? (const void *)k_jacobi_coop<32, 16> : (const void *)k_jacobi_coop<64, 0>;
+      const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(nb / 2), dim3(G * b), args, 0, s);
+      if (e == hipSuccess) {
+        done = true;
+        if (debug_on()) {
+          LSPCA_HIP(hipMemcpyAsync(&sweeps, swo, sizeof(int), hipMemcpyDeviceToHost, s));
+          LSPCA_HIP(hipStreamSynchronize(s));
+        }
+      } else {
+        (void)hipGetLastError();                 // not co-resident: per-round launches
+      }
+    }
     int hflag = 0;
-    for (int sweep = 0; sweep < 40; ++sweep) {
+    for (int sweep = 0; !done && sweep < kJacobiMaxSweeps; ++sweep) {
       LSPCA_TRY(zero_i32(dflag, 1, s));
       for (int round = 0; round < nb - 1; ++round) {
-        hipLaunchKernelGGL(k_jacobi_block, nb / 2, 64 * b, 0, s, Wc, k, b, nb, round, tol, dflag);
+        if (G == 16)
+          hipLaunchKernelGGL((k_jacobi_block<16, 16>), nb / 2, G * b, 0, s, Wc, k, b, nb, round, tol, dflag);
+        else if (G == 32)
+          hipLaunchKernelGGL((k_jacobi_block<32, 16>), nb / 2, G * b, 0, s, Wc, k, b, nb, round, tol, dflag);
+        else
+          hipLaunchKernelGGL((k_jacobi_block<64, 0>), nb / 2, G * b, 0, s, Wc, k, b, nb, round, tol, dflag);
         LSPCA_HIP(hipGetLastError());
       }
       LSPCA_HIP(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -683,7 +844,7 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
   double *scr = ws.take<double>(3 * 128 * 128);
   double *prebuf = ws.take<double>(4 * kk);
   double *sw = ws.take<double>(k);
-  int *dflag = ws.take<int>(4);
+  int *dflag = ws.take<int>(kSmallFlags);
   int hflag[4];
 
   LSPCA_TRY(launch_transpose_f64(F, k, (int)n, Ft, s));   // F (k x n) -> F^T (n x k)
@@ -768,9 +929,9 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
       }
     }
     // the rows of R2 are the columns of R2^T: column storage as is
-    if (pre) LSPCA_TRY(jacobi_svd(R2, true, k, Wc, UT, sw, dflag + 1, s));
+    if (pre) LSPCA_TRY(jacobi_svd(R2, true, k, Wc, UT, sw, dflag + 8, s));
   }
-  if (!pre) LSPCA_TRY(jacobi_svd(Rall, false, k, Wc, UT, sw, dflag + 1, s));
+  if (!pre) LSPCA_TRY(jacobi_svd(Rall, false, k, Wc, UT, sw, dflag + 8, s));
   LSPCA_TRY(launch_nt(LSPCA_F64, Q, k, UT, k, Vw, k, n, k, k, s));
   hipLaunchKernelGGL(k_sign_fix, k, 256, 0, s, Vw, n, k);
   LSPCA_HIP(hipGetLastError());
@@ -782,7 +943,7 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
     LSPCA_TRY(chol(M, k, dflag, scr, s));
     LSPCA_TRY(trinv_t(M, k, XT, scr, s));
     LSPCA_TRY(launch_nt(LSPCA_F64, Rall, k, XT, k, Rtmp, k, k, k, k, s));
-    LSPCA_TRY(jacobi_svd(Rtmp, false, k, Wc, nullptr, sx, dflag + 2, s));
+    LSPCA_TRY(jacobi_svd(Rtmp, false, k, Wc, nullptr, sx, dflag + 64, s));
     LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
     LSPCA_HIP(hipStreamSynchronize(s));
     if (hflag[0]) {

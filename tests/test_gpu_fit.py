@@ -207,6 +207,24 @@ def test_factor_matches_oracle_svd(gpu_lib, k, n):
     assert np.max(np.abs(V.T @ V - np.eye(k))) < 16 * max(k, 16) * U64
 
 
+@pytest.mark.parametrize("k,n", [(256, 4096), (300, 700), (520, 1100)])
+def test_factor_jacobi_cooperative_and_per_round_launches_agree(gpu_lib, monkeypatch, k, n):
+    """The block Jacobi of k > 128 runs all sweeps in one cooperative launch;
+    LSPCA_JACOBI=launches runs the same rounds as separate launches: the
+    same rotations in the same order, so the same bits."""
+    import torch
+    rng = np.random.default_rng(k + 1)
+    F = (random_orthonormal_np(k, k, rng) * np.geomspace(30.0, 1.0, k)) @ random_orthonormal_np(n, k, rng).T
+    Ft = torch.from_numpy(F).cuda()
+    V1, s1 = gpu_lib.factor(Ft)
+    monkeypatch.setenv("LSPCA_JACOBI", "launches")
+    V2, s2 = gpu_lib.factor(Ft)
+    monkeypatch.delenv("LSPCA_JACOBI")
+    assert torch.equal(V1, V2) and torch.equal(s1, s2)
+    Vr, dr = O.truncated_svd(F, k)
+    assert np.max(np.abs(s1.cpu().numpy() - dr) / dr) < 1e-12
+
+
 def test_factor_ill_conditioned_uses_shifted_path(gpu_lib):
     """Condition 1e9: the first Cholesky of F F^T fails in FP64, the shifted
     pass takes over. Any backward-stable SVD (the oracle's LAPACK one too)
