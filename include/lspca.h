@@ -102,6 +102,17 @@ typedef struct lspca_opts {
   int32_t timing;       /* nonzero: record per-phase device times, read back
                            with lspca_last_timings() */
   void *stream;         /* hipStream_t; NULL = null stream */
+  int32_t small_route;  /* truncated SVD of F (Algorithm 2 step 3): 0 = Cholesky
+                           QR of F^T (twice) and one-sided Jacobi SVD of R
+                           (default; relative accuracy ~ u kappa(F)); 1 = the
+                           route of the caption of the paper's algorithm table:
+                           eigendecomposition F F^T = W Lambda W^T, D =
+                           Lambda^(1/2), V = F^T W D^-1, then one Cholesky QR
+                           pass on V (accuracy ~ u kappa(F)^2: D_k is resolved
+                           only down to about sqrt(u) D_1) */
+  int32_t reserved;     /* 0 */
+  int64_t stripe_rows;  /* rows per stripe of the pass (Algorithm 4's slices);
+                           0 = auto (a 2 GiB sketch stripe) */
 } lspca_opts;
 
 /* Per-phase device times (ms) of the last call on this thread that had

@@ -46,7 +46,8 @@ class LspcaError(RuntimeError):
 class lspca_opts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("sparse_p", ctypes.c_uint32),
                 ("refine", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("small_route", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("stripe_rows", ctypes.c_int64)]
 
 
 class lspca_timings(ctypes.Structure):
@@ -162,7 +163,10 @@ def _rowmajor(X, name="X"):
     return X.stride(0)
 
 
-def _opts(stream=None, sparse_p=0, refine=-1, timing=False):
+SMALL_ROUTE = {"qr": 0, "eig": 1}
+
+
+def _opts(stream=None, sparse_p=0, refine=-1, timing=False, small_route="qr", stripe_rows=0):
     torch = _torch()
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -172,6 +176,8 @@ def _opts(stream=None, sparse_p=0, refine=-1, timing=False):
     o.refine = refine
     o.timing = 1 if timing else 0
     o.stream = ctypes.c_void_p(stream.cuda_stream)
+    o.small_route = SMALL_ROUTE[small_route] if isinstance(small_route, str) else int(small_route)
+    o.stripe_rows = stripe_rows
     return o
 
 

@@ -128,6 +128,8 @@ struct Opts {
   int refine = -1;
   int timing = 0;
   hipStream_t stream = nullptr;
+  int small_route = 0;
+  int64_t stripe_rows = 0;
 };
 
 static int read_opts(const lspca_opts *o, Opts &out) {
@@ -139,6 +141,20 @@ static int read_opts(const lspca_opts *o, Opts &out) {
   if (sz >= offsetof(lspca_opts, refine) + sizeof(int32_t)) out.refine = o->refine;
   if (sz >= offsetof(lspca_opts, timing) + sizeof(int32_t)) out.timing = o->timing;
   if (sz >= offsetof(lspca_opts, stream) + sizeof(void *)) out.stream = (hipStream_t)o->stream;
+  if (sz >= offsetof(lspca_opts, small_route) + sizeof(int32_t)) {
+    if (o->small_route != 0 && o->small_route != 1) {
+      set_error("small_route must be 0 or 1 (got %d)", o->small_route);
+      return LSPCA_EINVAL;
+    }
+    out.small_route = o->small_route;
+  }
+  if (sz >= offsetof(lspca_opts, stripe_rows) + sizeof(int64_t)) {
+    if (o->stripe_rows < 0) {
+      set_error("stripe_rows must be >= 0 (got %lld)", (long long)o->stripe_rows);
+      return LSPCA_EINVAL;
+    }
+    out.stripe_rows = o->stripe_rows;
+  }
   return LSPCA_OK;
 }
 
@@ -193,7 +209,7 @@ struct PassPlan {
 static bool is16(lspca_dtype dt) { return dt == LSPCA_BF16 || dt == LSPCA_F16; }
 
 static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool want_g, int kind,
-                          uint32_t sp) {
+                          uint32_t sp, int64_t stripe_rows = 0) {
   PassPlan p;
   p.h16 = is16(xdt);
   p.cap = 0;
@@ -208,6 +224,7 @@ static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool wan
   }
   int64_t rows = budget / ((int64_t)k * p.esz);
   rows = rows < 1024 ? 1024 : rows;
+  if (stripe_rows > 0) rows = stripe_rows;            // the caller's slices
   p.stripe = m < rows ? m : rows;
   p.splits_f = tn_pick_splits(p.stripe, k, (int)n);
   p.splits_g = (want_g && !p.h16) ? tn_pick_splits(p.stripe, k, k) : 0;
@@ -468,7 +485,7 @@ int lspca_accumulate(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64
   if (!F) { set_error("F is NULL"); return LSPCA_EINVAL; }
   Locked L;
   LSPCA_TRY(lock_device(L));
-  PassPlan pl = plan_pass(xdt, m, n, k, G != nullptr, kind, o.p);
+  PassPlan pl = plan_pass(xdt, m, n, k, G != nullptr, kind, o.p, o.stripe_rows);
   LSPCA_TRY(L.st->ws.ensure(pl.bytes));
   PhaseTimer tm;
   tm.begin(o.timing != 0, o.stream);
@@ -491,7 +508,7 @@ int lspca_factor(const double *F, const double *G, int32_t k, int64_t n, const l
   PhaseTimer tm;
   tm.begin(o.timing != 0, o.stream);
   int rank_flag = 0;
-  LSPCA_TRY(small_factor(F, G, k, n, V, sigma, sigma_x, L.st->ws, o.stream, &rank_flag));
+  LSPCA_TRY(small_factor(F, G, k, n, V, sigma, sigma_x, L.st->ws, o.stream, &rank_flag, o.small_route));
   tm.mark(PH_SMALL);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;
@@ -508,7 +525,7 @@ int lspca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx,
   Locked L;
   LSPCA_TRY(lock_device(L));
   const bool want_g = sigma_x != nullptr;
-  PassPlan pl = plan_pass(xdt, m, n, k, want_g, kind, o.p);
+  PassPlan pl = plan_pass(xdt, m, n, k, want_g, kind, o.p, o.stripe_rows);
   const size_t fg = ws_bytes<double>((size_t)k * n) + ws_bytes<double>((size_t)k * k);
   const size_t fb = factor_bytes(n, k);
   LSPCA_TRY(L.st->ws.ensure(fg + (pl.bytes > fb ? pl.bytes : fb)));
@@ -523,7 +540,7 @@ int lspca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx,
   LSPCA_TRY(run_pass(X, xdt, m, n, ldx, k, kind, seed, o, F, want_g ? G : nullptr, pl, ws, tm));
   ws.used = mark;                                    // the pass's slots are free again
   int rank_flag = 0;
-  LSPCA_TRY(small_factor(F, want_g ? G : nullptr, k, n, V, sigma, sigma_x, ws, o.stream, &rank_flag));
+  LSPCA_TRY(small_factor(F, want_g ? G : nullptr, k, n, V, sigma, sigma_x, ws, o.stream, &rank_flag, o.small_route));
   tm.mark(PH_SMALL);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;
@@ -610,7 +627,7 @@ int lspca_fit_host(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t
   tm.mark(PH_FACTOR);
   LSPCA_TRY(L.st->ws.ensure(factor_bytes(n, k)));
   int rank_flag = 0;
-  LSPCA_TRY(small_factor(F, want_g ? G : nullptr, k, n, V, sigma, sigma_x, L.st->ws, o.stream, &rank_flag));
+  LSPCA_TRY(small_factor(F, want_g ? G : nullptr, k, n, V, sigma, sigma_x, L.st->ws, o.stream, &rank_flag, o.small_route));
   tm.mark(PH_SMALL);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;
@@ -633,7 +650,7 @@ int spca_fit_stream(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
   const size_t ys = dtype_size(ydt);
   Locked L;
   LSPCA_TRY(lock_device(L));
-  PassPlan pl = plan_pass(xdt, m, n, k, false, kind, o.p);
+  PassPlan pl = plan_pass(xdt, m, n, k, false, kind, o.p, o.stripe_rows);
   const size_t kb = (size_t)k * BR;
   const size_t keep = ws_bytes<double>((size_t)k * n) + 3 * ws_bytes<char>(ys * kb) +
                       ws_bytes<double>((size_t)k * k);
@@ -674,7 +691,7 @@ int spca_fit_stream(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
   tm.mark(PH_PASS2);
   ws.used = mark;
   int rank_flag = 0;
-  LSPCA_TRY(small_factor(F, nullptr, k, n, V, sigma, nullptr, ws, s, &rank_flag));
+  LSPCA_TRY(small_factor(F, nullptr, k, n, V, sigma, nullptr, ws, s, &rank_flag, o.small_route));
   tm.mark(PH_SMALL);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;
@@ -749,7 +766,7 @@ int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, 
   tm.mark(PH_REDUCE);
   // step 4: truncated SVD of F gives V^s, Sigma^s
   int rank_flag = 0;
-  LSPCA_TRY(small_factor(F, nullptr, k, n, V, sigma, nullptr, ws, s, &rank_flag));
+  LSPCA_TRY(small_factor(F, nullptr, k, n, V, sigma, nullptr, ws, s, &rank_flag, o.small_route));
   tm.mark(PH_SMALL);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;

@@ -199,7 +199,7 @@ int launch_reduce_add(lspca_dtype pdt, const void *P, int splits, int64_t count,
 int zero_i32(int *p, int count, hipStream_t s);
 int small_factor(const double *F, const double *G, int k, int64_t n,
                  double *V, double *sigma, double *sigma_x, Workspace &ws,
-                 hipStream_t s, int *rank_flag);
+                 hipStream_t s, int *rank_flag, int route = 0);
 int launch_transpose_f64(const double *src, int64_t rows, int cols,
                          double *dst, hipStream_t s);
 // Request table of one batched projection launch (the projection server):

@@ -590,6 +590,16 @@ __global__ __launch_bounds__(1024) void k_jacobi_finish(const double *Wc, int k,
 
 // Sign convention: the largest-magnitude entry of each column of V (n x k)
 // is made positive; the lowest row index wins ties. One block per column.
+__global__ void k_sqrt_vec(double *v, int k) {
+  for (int i = threadIdx.x; i < k; i += blockDim.x) v[i] = sqrt(v[i]);
+}
+
+// V[r][c] /= d[c] (V n x k row-major)
+__global__ void k_scale_cols_inv(double *V, int64_t n, int k, const double *d) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n * k) V[e] /= d[e % k];
+}
+
 __global__ __launch_bounds__(256) void k_sign_fix(double *V, int64_t n, int k) {
   __shared__ double bv[256];
   __shared__ int64_t bi[256];
@@ -826,7 +836,7 @@ int apply_rinv_t(const double *R, int k, double *F, int64_t n, Workspace &ws, hi
 }
 
 int small_factor(const double *F, const double *G, int k, int64_t n, double *V, double *sigma,
-                 double *sigma_x, Workspace &ws, hipStream_t s, int *rank_flag) {
+                 double *sigma_x, Workspace &ws, hipStream_t s, int *rank_flag, int route) {
   const int64_t kk = (int64_t)k * k;
   const int splits = tn_pick_splits(n, k, k);
   double *Ft = ws.take<double>((size_t)n * k);
@@ -849,90 +859,119 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
 
   LSPCA_TRY(launch_transpose_f64(F, k, (int)n, Ft, s));   // F (k x n) -> F^T (n x k)
 
-  // Cholesky QR passes on F^T: Q <- Q R_p^-1, R <- R_p R.
-  const double *Qin = Ft;
-  double *Qout = Qa;
-  bool shifted = false;
-  int passes = 0;
-  for (int attempt = 0; attempt < 2 && passes == 0; ++attempt) {
-    const int npass = shifted ? 3 : 2;
-    Qin = Ft;
-    Qout = Qa;
-    bool failed = false;
-    for (int pss = 0; pss < npass; ++pss) {
-      LSPCA_TRY(zero_i32(dflag, 4, s));
-      LSPCA_TRY(gram(Qin, n, k, M, part, splits, s));
-      if (shifted && pss == 0) {
-        // shift = 11 (n k + k (k + 1)) u ||F||_F^2 (shifted Cholesky QR;
-        // Fukaya et al., SIAM J. Sci. Comput. 42, 2020)
-        const double c = 11.0 * ((double)n * k + (double)k * (k + 1)) * 0x1p-53;
-        hipLaunchKernelGGL(k_shift_diag, 1, 256, 0, s, M, k, c);
-        LSPCA_HIP(hipGetLastError());
+  if (route == 0) {
+    // Cholesky QR passes on F^T: Q <- Q R_p^-1, R <- R_p R.
+    const double *Qin = Ft;
+    double *Qout = Qa;
+    bool shifted = false;
+    int passes = 0;
+    for (int attempt = 0; attempt < 2 && passes == 0; ++attempt) {
+      const int npass = shifted ? 3 : 2;
+      Qin = Ft;
+      Qout = Qa;
+      bool failed = false;
+      for (int pss = 0; pss < npass; ++pss) {
+        LSPCA_TRY(zero_i32(dflag, 4, s));
+        LSPCA_TRY(gram(Qin, n, k, M, part, splits, s));
+        if (shifted && pss == 0) {
+          // shift = 11 (n k + k (k + 1)) u ||F||_F^2 (shifted Cholesky QR;
+          // Fukaya et al., SIAM J. Sci. Comput. 42, 2020)
+          const double c = 11.0 * ((double)n * k + (double)k * (k + 1)) * 0x1p-53;
+          hipLaunchKernelGGL(k_shift_diag, 1, 256, 0, s, M, k, c);
+          LSPCA_HIP(hipGetLastError());
+        }
+        LSPCA_TRY(chol(M, k, dflag, scr, s));
+        LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+        LSPCA_HIP(hipStreamSynchronize(s));
+        if (hflag[0]) {
+          failed = true;
+          break;
+        }
+        LSPCA_TRY(trinv_t(M, k, XT, scr, s));
+        LSPCA_TRY(launch_nt(LSPCA_F64, Qin, k, XT, k, Qout, k, n, k, k, s));
+        if (pss == 0) {
+          LSPCA_HIP(hipMemcpyAsync(Rall, M, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
+        } else {
+          // Rall <- M * Rall  (nt with B = Rall^T)
+          LSPCA_TRY(launch_transpose_f64(Rall, k, k, Rtmp, s));
+          LSPCA_TRY(launch_nt(LSPCA_F64, M, k, Rtmp, k, Rall, k, k, k, k, s));
+        }
+        Qin = Qout;
+        Qout = (Qout == Qa) ? Qb : Qa;
       }
-      LSPCA_TRY(chol(M, k, dflag, scr, s));
-      LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
-      LSPCA_HIP(hipStreamSynchronize(s));
-      if (hflag[0]) {
-        failed = true;
-        break;
-      }
-      LSPCA_TRY(trinv_t(M, k, XT, scr, s));
-      LSPCA_TRY(launch_nt(LSPCA_F64, Qin, k, XT, k, Qout, k, n, k, k, s));
-      if (pss == 0) {
-        LSPCA_HIP(hipMemcpyAsync(Rall, M, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
-      } else {
-        // Rall <- M * Rall  (nt with B = Rall^T)
-        LSPCA_TRY(launch_transpose_f64(Rall, k, k, Rtmp, s));
-        LSPCA_TRY(launch_nt(LSPCA_F64, M, k, Rtmp, k, Rall, k, k, k, k, s));
-      }
-      Qin = Qout;
-      Qout = (Qout == Qa) ? Qb : Qa;
+      if (!failed) passes = npass;
+      else if (!shifted) shifted = true;
+      else break;
     }
-    if (!failed) passes = npass;
-    else if (!shifted) shifted = true;
-    else break;
-  }
-  if (passes == 0) {
-    set_error("factor: Cholesky QR of F^T failed (F is numerically rank deficient)");
-    *rank_flag = 1;
-    return LSPCA_ERANK;
-  }
-  const double *Q = Qin;
+    if (passes == 0) {
+      set_error("factor: Cholesky QR of F^T failed (F is numerically rank deficient)");
+      *rank_flag = 1;
+      return LSPCA_ERANK;
+    }
+    const double *Q = Qin;
 
-  // SVD of R: R W = U_R Sigma; V = Q U_R. Preconditioning: with
-  // R^T = Q2 R2 (Cholesky QR twice on the k x k matrix R^T), R2^T has the
-  // same left singular vectors U_R and singular values as R, and one-sided
-  // Jacobi on the columns of R2^T (= the rows of R2) needs far fewer sweeps
-  // than on R (Drmac and Veselic, SIAM J. Matrix Anal. Appl. 29, 2008).
-  bool pre = !shifted;
-  if (pre) {
-    double *T = prebuf;                              // 4 k x k scratch matrices
-    double *S1 = T + kk, *P = T + 2 * kk, *R2 = T + 3 * kk;
-    LSPCA_TRY(launch_transpose_f64(Rall, k, k, T, s));            // T = R^T
-    for (int pss = 0; pss < 2 && pre; ++pss) {
-      const double *Tin = pss == 0 ? T : P;
-      LSPCA_TRY(zero_i32(dflag, 1, s));
-      LSPCA_TRY(gram(Tin, k, k, M, part, tn_pick_splits(k, k, k), s));
-      LSPCA_TRY(chol(M, k, dflag, scr, s));
-      LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
-      LSPCA_HIP(hipStreamSynchronize(s));
-      if (hflag[0]) { pre = false; break; }
-      LSPCA_TRY(trinv_t(M, k, XT, scr, s));
-      double *Pout = pss == 0 ? P : S1;              // P = T S^-1
-      LSPCA_TRY(launch_nt(LSPCA_F64, Tin, k, XT, k, Pout, k, k, k, k, s));
-      if (pss == 0) {
-        LSPCA_HIP(hipMemcpyAsync(R2, M, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
-      } else {
-        // R2 <- S2 R2  (nt with B = R2^T)
-        LSPCA_TRY(launch_transpose_f64(R2, k, k, Rtmp, s));
-        LSPCA_TRY(launch_nt(LSPCA_F64, M, k, Rtmp, k, R2, k, k, k, k, s));
+    // SVD of R: R W = U_R Sigma; V = Q U_R. Preconditioning: with
+    // R^T = Q2 R2 (Cholesky QR twice on the k x k matrix R^T), R2^T has the
+    // same left singular vectors U_R and singular values as R, and one-sided
+    // Jacobi on the columns of R2^T (= the rows of R2) needs far fewer sweeps
+    // than on R (Drmac and Veselic, SIAM J. Matrix Anal. Appl. 29, 2008).
+    bool pre = !shifted;
+    if (pre) {
+      double *T = prebuf;                              // 4 k x k scratch matrices
+      double *S1 = T + kk, *P = T + 2 * kk, *R2 = T + 3 * kk;
+      LSPCA_TRY(launch_transpose_f64(Rall, k, k, T, s));            // T = R^T
+      for (int pss = 0; pss < 2 && pre; ++pss) {
+        const double *Tin = pss == 0 ? T : P;
+        LSPCA_TRY(zero_i32(dflag, 1, s));
+        LSPCA_TRY(gram(Tin, k, k, M, part, tn_pick_splits(k, k, k), s));
+        LSPCA_TRY(chol(M, k, dflag, scr, s));
+        LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+        LSPCA_HIP(hipStreamSynchronize(s));
+        if (hflag[0]) { pre = false; break; }
+        LSPCA_TRY(trinv_t(M, k, XT, scr, s));
+        double *Pout = pss == 0 ? P : S1;              // P = T S^-1
+        LSPCA_TRY(launch_nt(LSPCA_F64, Tin, k, XT, k, Pout, k, k, k, k, s));
+        if (pss == 0) {
+          LSPCA_HIP(hipMemcpyAsync(R2, M, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
+        } else {
+          // R2 <- S2 R2  (nt with B = R2^T)
+          LSPCA_TRY(launch_transpose_f64(R2, k, k, Rtmp, s));
+          LSPCA_TRY(launch_nt(LSPCA_F64, M, k, Rtmp, k, R2, k, k, k, k, s));
+        }
       }
+      // the rows of R2 are the columns of R2^T: column storage as is
+      if (pre) LSPCA_TRY(jacobi_svd(R2, true, k, Wc, UT, sw, dflag + 8, s));
     }
-    // the rows of R2 are the columns of R2^T: column storage as is
-    if (pre) LSPCA_TRY(jacobi_svd(R2, true, k, Wc, UT, sw, dflag + 8, s));
+    if (!pre) LSPCA_TRY(jacobi_svd(Rall, false, k, Wc, UT, sw, dflag + 8, s));
+    LSPCA_TRY(launch_nt(LSPCA_F64, Q, k, UT, k, Vw, k, n, k, k, s));
+  } else {
+    // The route of the caption of the algorithm table: F F^T = W Lambda W^T
+    // by one-sided Jacobi on the symmetric positive semidefinite F F^T (its
+    // left singular vectors are W, its singular values Lambda), D =
+    // Lambda^(1/2), V = F^T W D^-1, then one Cholesky QR pass on V.
+    LSPCA_TRY(gram(Ft, n, k, M, part, splits, s));                 // M = F F^T
+    LSPCA_HIP(hipMemcpyAsync(Rall, M, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    LSPCA_TRY(jacobi_svd(M, false, k, Wc, UT, sw, dflag + 8, s));   // UT = W^T, sw = Lambda
+    hipLaunchKernelGGL(k_sqrt_vec, 1, 256, 0, s, sw, k);            // D
+    LSPCA_HIP(hipGetLastError());
+    LSPCA_TRY(launch_nt(LSPCA_F64, Ft, k, UT, k, Qa, k, n, k, k, s));      // F^T W
+    hipLaunchKernelGGL(k_scale_cols_inv, (unsigned)(((int64_t)n * k + 255) / 256), 256, 0, s, Qa, n, k, sw);
+    LSPCA_HIP(hipGetLastError());
+    LSPCA_TRY(zero_i32(dflag, 1, s));
+    LSPCA_TRY(gram(Qa, n, k, M, part, splits, s));                  // Cholesky QR: V = Qa R^-1
+    LSPCA_TRY(chol(M, k, dflag, scr, s));
+    if (sigma_x) LSPCA_TRY(chol(Rall, k, dflag, scr, s));         // R^T R = F F^T, for Sigma^s
+    LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+    LSPCA_HIP(hipStreamSynchronize(s));
+    if (hflag[0]) {
+      set_error("factor: F is numerically rank deficient (the eigenvalue route resolves D_k only "
+                "down to about sqrt(u) D_1)");
+      *rank_flag = 1;
+      return LSPCA_ERANK;
+    }
+    LSPCA_TRY(trinv_t(M, k, XT, scr, s));
+    LSPCA_TRY(launch_nt(LSPCA_F64, Qa, k, XT, k, Vw, k, n, k, k, s));
   }
-  if (!pre) LSPCA_TRY(jacobi_svd(Rall, false, k, Wc, UT, sw, dflag + 8, s));
-  LSPCA_TRY(launch_nt(LSPCA_F64, Q, k, UT, k, Vw, k, n, k, k, s));
   hipLaunchKernelGGL(k_sign_fix, k, 256, 0, s, Vw, n, k);
   LSPCA_HIP(hipGetLastError());
 
@@ -953,11 +992,13 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
     }
   }
 
-  // Rank check on D: D_k <= 64 n eps D_1 means F is numerically rank deficient.
+  // Rank check on D: D_k <= 64 n eps D_1 means F is numerically rank deficient
+  // (the eigenvalue route squares: sqrt(64 n eps) D_1).
   std::vector<double> hs(k);
   LSPCA_HIP(hipMemcpyAsync(hs.data(), sw, k * sizeof(double), hipMemcpyDeviceToHost, s));
   LSPCA_HIP(hipStreamSynchronize(s));
-  if (!(hs[k - 1] > 64.0 * (double)n * 0x1p-52 * hs[0])) {
+  const double rel = 64.0 * (double)n * 0x1p-52;
+  if (!(hs[k - 1] > (route == 0 ? rel : std::sqrt(rel)) * hs[0])) {
     set_error("factor: F is numerically rank deficient (D_k = %g, D_1 = %g)", hs[k - 1], hs[0]);
     *rank_flag = 1;
     return LSPCA_ERANK;

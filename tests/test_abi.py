@@ -87,6 +87,18 @@ def test_sparse_p_must_be_power_of_two(lib):
     assert st == -1
 
 
+def test_small_route_and_stripe_rows_are_checked(lib):
+    o = L.lspca_opts()
+    o.struct_size = ctypes.sizeof(o)
+    o.small_route = 2
+    st = lib.lspca_fit(1 << 20, L.F32, 100, 50, 50, 5, L.GAUSSIAN, 1, ctypes.byref(o), 1 << 21, 1 << 22, None)
+    assert st == -1 and "small_route" in lib.lspca_last_error().decode()
+    o.small_route = 1
+    o.stripe_rows = -5
+    st = lib.lspca_fit(1 << 20, L.F32, 100, 50, 50, 5, L.GAUSSIAN, 1, ctypes.byref(o), 1 << 21, 1 << 22, None)
+    assert st == -1 and "stripe_rows" in lib.lspca_last_error().decode()
+
+
 def test_factor_and_transform_argument_checks(lib):
     assert lib.lspca_factor(None, None, 3, 10, None, 1, 1, None) == -1
     assert lib.lspca_factor(1 << 20, None, 3, 10, None, 1 << 21, 1 << 22, 1 << 23) == -1  # sigma_x needs G

@@ -225,6 +225,47 @@ def test_factor_jacobi_cooperative_and_per_round_launches_agree(gpu_lib, monkeyp
     assert np.max(np.abs(s1.cpu().numpy() - dr) / dr) < 1e-12
 
 
+@pytest.mark.parametrize("k,n", [(7, 40), (50, 1000), (130, 700), (256, 4096)])
+def test_factor_eigenvalue_route_matches_oracle_svd(gpu_lib, k, n):
+    """small_route = eig (F F^T = W Lambda W^T, D = Lambda^(1/2), V = F^T W
+    D^-1, then a Cholesky QR pass): squaring the problem costs a factor
+    kappa(F) against the default route, so D and span(V) agree with the
+    oracle's SVD to c u kappa^2 (condition 30 here)."""
+    import torch
+    rng = np.random.default_rng(k + 7)
+    d = np.geomspace(30.0, 1.0, k)
+    F = (random_orthonormal_np(k, k, rng) * d) @ random_orthonormal_np(n, k, rng).T
+    V, s = gpu_lib.factor(torch.from_numpy(F).cuda(), small_route="eig")
+    V, s = V.cpu().numpy(), s.cpu().numpy()
+    Vr, dr = O.truncated_svd(F, k)
+    tol = 64 * k * U64 * (dr[0] / dr[-1]) ** 2
+    assert np.max(np.abs(s - dr) / dr) < tol
+    assert O.principal_sines(Vr, V).max() < tol
+    assert np.max(np.abs(V.T @ V - np.eye(k))) < 16 * max(k, 16) * U64
+    # the oracle's own eigenvalue route agrees as well
+    Ve, de = O.eig_route_svd(F, k)
+    assert np.max(np.abs(s - de) / de) < tol
+
+
+def test_fit_eigenvalue_route_and_stripe_rows(gpu_lib):
+    """lspca_fit with small_route = eig, and with caller-chosen stripes
+    (stripe_rows), against the default fit on the same X."""
+    import torch
+    m, n, k = 5003, 300, 20
+    Xs, X64 = _data(m, n, k, "f64")
+    X = to_device(Xs, "f64")
+    V0, s0 = gpu_lib.fit(X, k, "gaussian", 4)
+    V1, s1 = gpu_lib.fit(X, k, "gaussian", 4, small_route="eig")
+    V2, s2 = gpu_lib.fit(X, k, "gaussian", 4, stripe_rows=1000)
+    V0, s0 = V0.cpu().numpy(), s0.cpu().numpy()
+    kappa = s0[0] / s0[-1]
+    assert O.principal_sines(V0, V1.cpu().numpy()).max() < 64 * k * U64 * kappa ** 2
+    assert np.max(np.abs(s1.cpu().numpy() - s0) / s0) < 64 * k * U64 * kappa ** 2
+    # stripes change only the FP64 summation order of F
+    assert O.principal_sines(V0, V2.cpu().numpy()).max() < 1e-10
+    assert np.max(np.abs(s2.cpu().numpy() - s0) / s0) < 1e-12
+
+
 def test_factor_ill_conditioned_uses_shifted_path(gpu_lib):
     """Condition 1e9: the first Cholesky of F F^T fails in FP64, the shifted
     pass takes over. Any backward-stable SVD (the oracle's LAPACK one too)
