@@ -37,8 +37,14 @@ PEAKS = {  # MI355X published dense peaks
 MEASURED_TRAFFIC = {
     ("f32", 1_000_000, 4096, 256, "gaussian"): {
         "sources": ["paper_1709_07175_amd/csrc/gemm.hip", "paper_1709_07175_amd/csrc/common.h"],
-        "sha256": "17d3b4e54b56fe2226290bc623acdfd168dad250043a71fb3503fbcd58a2b64c",
-        "bytes": 2.0162e10,
+        "sha256": "bd27d5164d8566b767de902642b05dc29aa6b26280dd2ad34032babf0db30b6d",
+        "bytes": 2.0118e10,
+    },
+    ("bf16", 1_000_000, 4096, 256, "sparse"): {
+        "sources": ["paper_1709_07175_amd/csrc/sparse.hip", "paper_1709_07175_amd/csrc/philox.h",
+                    "paper_1709_07175_amd/csrc/common.h"],
+        "sha256": "f196c74cc83612f933f55b7979b1c32282398a8b4ada7e84c569f52f700b4f00",
+        "bytes": 9.2162e9,
     },
 }
 
