@@ -227,6 +227,144 @@ def serving(lib, V, Xsrc, levels, counts, modes, seed=7175 + 5, log_every=500):
     return out
 
 
+def csr_roofline(c, cnt, rows, esz, factor_ms_per_launch):
+    """The column sums F += Y^T X of one stripe (k_csc_factor): algorithmic
+    bytes = the stripe's column-ordered entries (row index + value) once, its
+    sketch rows once, F read and written once."""
+    n, k = c["n"], c["k"]
+    alg = cnt * (4 + esz) + rows * k * esz + 2 * k * n * 8
+    achieved = alg / (factor_ms_per_launch * 1e-3) / 1e9
+    return {"kernel": "k_csc_factor (F += Y^T X, column order)", "bound": "hbm",
+            "achieved": round(achieved, 3), "peak": PEAKS["hbm_GBs"], "unit": "GB/s",
+            "frac": round(achieved / PEAKS["hbm_GBs"], 4), "traffic": None,
+            "algorithmic": f"entries (4 + {esz} B) + Y rows once + F in and out = {alg:.4g} bytes per launch",
+            "algorithmic_bytes": alg,
+            "gathered_GBs": round(cnt * k * esz / (factor_ms_per_launch * 1e-3) / 1e9, 3)}
+
+
+def csr_cpu_baseline(c, rph, cih, vvh, budget_s=20.0):
+    """FP64 oracle on a bounded row sample of the same CSR X: the dense
+    matrix of those rows (oracle.csr_dense), one Lazy SPCA fit plus Z = X V,
+    scaled to CSR-stream GB/s."""
+    import numpy as np
+    from oracle import lspca_oracle as O
+    from oracle import philox as P
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        cores = os.cpu_count()
+    n, k = c["n"], c["k"]
+    om = P.omega(n, k, c["kind"], c["omega_seed"], c["p"], dtype=c["dtype"])
+
+    def one(rows):
+        t0 = time.perf_counter()
+        Xd = O.csr_dense(rph[:rows + 1], cih, vvh, n)
+        fit = O.lazy_fit(Xd, om, k)
+        O.transform(Xd, fit["V"])
+        return time.perf_counter() - t0
+
+    rows = k
+    dt = one(rows)
+    while rows < len(rph) - 1 and dt * 2.2 <= budget_s:
+        rows = min(len(rph) - 1, rows * 2)
+        dt = one(rows)
+    times = [dt]
+    while sum(times) < 10.0 and len(times) < 200:
+        times.append(one(rows))
+    total = sum(times)
+    nbytes = 2 * (8 * (rows + 1) + int(rph[rows]) * (4 + vvh.itemsize))
+    return {"value": round(nbytes * len(times) / total / 1e9, 4), "unit": "GB/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": f"first {rows} rows of the same CSR X: FP64 oracle fit (dense rows, numpy/BLAS) "
+                      f"plus Z = X V, timed {len(times)}x, {total:.2f} s in all"}
+
+
+def csr_main(args, lib, torch):
+    """One step = lspca_fit_csr + lspca_transform_csr over the whole CSR X
+    (resident on the device). Value: bytes of the CSR arrays the step streams
+    (twice: fit and projection) over the step time."""
+    from synth import CSR_CONFIG, csr_torch
+    c = dict(CSR_CONFIG)
+    if args.m:
+        c["m"] = args.m
+    m, n, k = c["m"], c["n"], c["k"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"generating CSR X {m}x{n} at density {c['density']} (seed {c['data_seed']})")
+    t0 = time.time()
+    rp, ci, vv = csr_torch(m, n, c["density"], c["data_seed"], c["alpha"], c["binary"], c["dtype"],
+                           device=dev)
+    torch.cuda.synchronize()
+    X = lib.CSR(rp, ci, vv, n)
+    log(f"generated in {time.time() - t0:.1f}s: nnz {X.nnz}")
+    xbytes = rp.numel() * 8 + X.nnz * (4 + vv.element_size())
+    stream = torch.cuda.current_stream()
+
+    def step(timing):
+        V, s = lib.fit_csr(X, k, c["kind"], c["omega_seed"], timing=timing, sparse_p=c["p"])
+        tf = lib.last_timings() if timing else None
+        Z = lib.transform_csr(X, V, timing=timing)
+        tt = lib.last_timings() if timing else None
+        return V, Z, tf, tt
+
+    for i in range(args.warmup):
+        step(False)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    phases = []
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for i in range(args.steps):
+        _, _, tf, tt = step(True)
+        phases.append((tf, tt))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = ev0.elapsed_time(ev1) / args.steps
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step")
+
+    def avg(key, which=0):
+        return sum(p[which][key] for p in phases) / len(phases)
+
+    # stripes of the pass (the library's plan: entries per stripe <= 2^28 on
+    # 64-row boundaries, rows <= the 2 GiB sketch budget)
+    rph = rp.cpu().numpy()
+    starts, r0 = [0], 0
+    rows_cap = min((2 << 30) // (k * vv.element_size()), 1 << 24)
+    while r0 < m:
+        r1 = r0 + 64
+        while r1 < m and r1 + 64 - r0 <= rows_cap and rph[min(r1 + 64, m)] - rph[r0] <= (1 << 28):
+            r1 += 64
+        r0 = min(r1, m)
+        starts.append(r0)
+    nstripes = len(starts) - 1
+    big = max(range(nstripes), key=lambda t: rph[starts[t + 1]] - rph[starts[t]])
+    cnt = int(rph[starts[big + 1]] - rph[starts[big]])
+    fit_ms, tr_ms = avg("total_ms", 0), avg("transform_ms", 1)
+    value = 2 * xbytes / (ms_step * 1e-3) / 1e9
+    out = {
+        "metric": "X-stream GB/s (% HBM/MFMA roofline) per Lazy SPCA fit vs SPCA; projection p99 ms",
+        "value": round(value, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": c["dtype"], "data": "synthetic",
+        "config": {"workload": f"lazy-spca fit+projection, sparse X (CSR) {m}x{n} density {c['density']} "
+                               f"{c['dtype']} values, {c['kind']} Omega, k={k}",
+                   "m": m, "n": n, "k": k, "nnz": X.nnz, "x_bytes": xbytes, "stripes": nstripes,
+                   "parallelism": "single-gpu"},
+        "phases_ms": {"fit_total": round(fit_ms, 4), "omega": round(avg("omega_ms"), 4),
+                      "sketch_spmm": round(avg("sketch_ms"), 4), "csc_build": round(avg("layout_ms"), 4),
+                      "factor_F": round(avg("factor_ms"), 4), "reduce_G": round(avg("reduce_ms"), 4),
+                      "small_fp64": round(avg("small_ms"), 4), "transform": round(tr_ms, 4)},
+        "roofline": csr_roofline(c, cnt, starts[big + 1] - starts[big], vv.element_size(),
+                                 avg("factor_ms") / nstripes),
+    }
+    if not args.no_cpu:
+        log("cpu baseline (oracle on a row sample)")
+        out["cpu_baseline"] = csr_cpu_baseline(c, rph, ci.cpu().numpy(), vv.cpu().numpy())
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -243,6 +381,9 @@ def main():
     ap.add_argument("--serve-counts", type=str, default="200,600,2000",
                     help="requests at 50,200,800 QPS")
     ap.add_argument("--serve-modes", type=str, default="device,host")
+    ap.add_argument("--csr", action="store_true",
+                    help="the sparse-X workload instead: CSR X 131,072 x 98,450 at density 0.0244 "
+                         "(Experiment 1's feature matrix shape), very sparse Omega, k = 500")
     ap.add_argument("--calib-gib", type=float, default=0.0,
                     help="run y = 2 x over this many GiB (FP32) before timing: a reference of "
                          "known traffic for HBM byte counters")
@@ -257,6 +398,8 @@ def main():
     from synth import config, lowrank_torch
 
     lib.load()
+    if args.csr:
+        return csr_main(args, lib, torch)
     cfg = config(args.config)
     if args.m:
         cfg["m"] = args.m

@@ -127,6 +127,7 @@ typedef struct lspca_timings {
   double pass2_ms;      /* spca_fit: F = Q^T X */
   double transform_ms;  /* Z = X V */
   double total_ms;      /* whole call */
+  double layout_ms;     /* sparse X: column-order (CSC) build of each stripe */
 } lspca_timings;
 
 /* Version string, e.g. "lspca 0.1 gfx950". */
@@ -256,6 +257,65 @@ LSPCA_API int spca_fit_stream(const void *X, lspca_dtype xdt, int64_t m, int64_t
 LSPCA_API int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t n,
                     int64_t ldx, const double *V, int32_t k, void *Z,
                     const lspca_opts *opts);
+
+/*
+ * Sparse X (Experiment 1, "Data and Method": the data are horizontal slices
+ * of a sparse matrix with FP32 values; Proposition 4 prices both products
+ * of the pass at O(nnz(X) l)). X is given in CSR form, all arrays on the
+ * device and owned by the caller:
+ *  rowptr: m + 1 int64; row i's entries are at positions
+ *     [rowptr[i], rowptr[i + 1]) of colidx and values. rowptr[0] >= 0 (a
+ *     row slice of a larger CSR matrix is rowptr + r0 with the same colidx
+ *     and values), nondecreasing, rowptr[m] = nnz.
+ *  colidx: int32 column indices in [0, n), at least nnz entries; order
+ *     within a row is free and repeated columns add (X[i][j] is the sum of
+ *     row i's values with column j).
+ *  values: FP32 or FP64 (vdt), at least nnz entries.
+ * The arrays are checked on the device before any other kernel reads them
+ * (EINVAL names the broken array); these calls wait for that check.
+ * Products run in the value type (FP32 sums for FP32 data) except F, which
+ * accumulates in FP64; each row's and each column's entries are summed in
+ * storage / row order, so results are deterministic. Omega is the one of
+ * lspca_omega for the value type.
+ */
+
+/*
+ * lspca_accumulate_csr -- Algorithm 4 step for a CSR slice: U_s = X Omega,
+ * F += U_s^T X, G += U_s^T U_s (G may be NULL). F k x n and G k x k FP64
+ * device accumulators as in lspca_accumulate. Rows are processed in
+ * stripes; each stripe's X is also put in column order on the device (a
+ * stable sort; workspace about 28 bytes per entry of the stripe).
+ *  Errors: EINVAL (bad sizes, NULL pointers, bad CSR arrays, bad kind or
+ *  p), ENOTSUP (values not FP32/FP64, k > 4096, 2^31 entries in one stripe
+ *  of 64 rows), ENOMEM, EHIP. Returns once the work is queued after the
+ *  check; outputs are ready when opts->stream is.
+ */
+LSPCA_API int lspca_accumulate_csr(const int64_t *rowptr, const int32_t *colidx, const void *values,
+                                   lspca_dtype vdt, int64_t m, int64_t n, int64_t nnz, int32_t k,
+                                   lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts,
+                                   double *F, double *G);
+
+/*
+ * lspca_fit_csr -- Lazy SPCA (Algorithm 2) of a CSR X resident on the
+ * device: lspca_accumulate_csr over all rows, then lspca_factor. Outputs as
+ * lspca_fit; 1 <= k <= min(m, n). Synchronous. Errors as
+ * lspca_accumulate_csr and lspca_factor.
+ */
+LSPCA_API int lspca_fit_csr(const int64_t *rowptr, const int32_t *colidx, const void *values,
+                            lspca_dtype vdt, int64_t m, int64_t n, int64_t nnz, int32_t k,
+                            lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts, double *V,
+                            double *sigma, double *sigma_x);
+
+/*
+ * lspca_transform_csr -- Z = X V (eq. (dim_reduction_maps)) for the r rows
+ * of a CSR X. V: n x k FP64 (device; rounded to FP32 for FP32 values).
+ * Z: r x k of the value type. Each row of Z is the sum of its row's
+ * entries times rows of V, in storage order. r = 0: no work. Errors:
+ * EINVAL, ENOTSUP, ENOMEM, EHIP. Asynchronous after the check.
+ */
+LSPCA_API int lspca_transform_csr(const int64_t *rowptr, const int32_t *colidx, const void *values,
+                                  lspca_dtype vdt, int64_t r, int64_t n, int64_t nnz, const double *V,
+                                  int32_t k, void *Z, const lspca_opts *opts);
 
 /*
  * Projection server: continuous batching of requests Z = X V, the map

@@ -30,6 +30,7 @@ __all__ = [
     "lazy_fit", "spca_fit", "streaming_lazy_fit", "streaming_spca_fit",
     "transform", "eig_route_svd", "closed_form_basis", "sigma_x_kxk",
     "factor_probe", "principal_sines", "chordal_distance", "pairwise_distances",
+    "csr_dense", "csr_factor_rows",
 ]
 
 
@@ -178,6 +179,34 @@ def factor_probe(X, Omega, w):
     this way at any m without forming U."""
     X = _f64(X)
     return _f64(Omega).T @ (X.T @ (X @ _f64(w)))
+
+
+def csr_dense(rowptr, colidx, values, n):
+    """The m x n matrix a CSR triple stands for (the sparse slices of
+    Experiment 1, "Data and Method"): row i holds value values[e] at column
+    colidx[e] for e in [rowptr[i], rowptr[i + 1]); repeated columns of a row
+    add. rowptr[0] may be positive (a row slice of a larger matrix)."""
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    m = rowptr.size - 1
+    e0, e1 = int(rowptr[0]), int(rowptr[-1])
+    rows = np.repeat(np.arange(m), np.diff(rowptr))
+    X = np.zeros((m, n), dtype=np.float64)
+    np.add.at(X, (rows, np.asarray(colidx[e0:e1], dtype=np.int64)), _f64(values[e0:e1]))
+    return X
+
+
+def csr_factor_rows(rowptr, colidx, values, n, Omega_C):
+    """U_C = X Omega_C and F_C = U_C^T X (Algorithm 2 steps 1 and 2 for a few
+    columns C of Omega) for the CSR matrix of csr_dense, at any m: the two
+    sparse products are the matrix-product step, by scipy.sparse (no dense
+    X is formed). Returns (U_C, F_C)."""
+    import scipy.sparse as sp
+    rowptr = np.asarray(rowptr, dtype=np.int64)
+    m = rowptr.size - 1
+    e0, e1 = int(rowptr[0]), int(rowptr[-1])
+    X = sp.csr_matrix((_f64(values[e0:e1]), np.asarray(colidx[e0:e1]), rowptr - e0), shape=(m, n))
+    U = X @ _f64(Omega_C)
+    return U, np.asarray((X.T @ U).T)
 
 
 def principal_sines(Va, Vb):

@@ -32,7 +32,9 @@ STATUS = {0: "LSPCA_OK", -1: "LSPCA_EINVAL", -2: "LSPCA_ENOMEM", -3: "LSPCA_EHIP
 # Every symbol include/lspca.h declares.
 EXPORTS = ["lspca_version", "lspca_strerror", "lspca_last_error", "lspca_last_timings",
            "lspca_omega", "lspca_accumulate", "lspca_factor", "lspca_fit", "spca_fit",
-           "lspca_transform", "lspca_accumulate_host", "lspca_fit_host", "spca_fit_stream", "lspca_server_create", "lspca_server_submit", "lspca_server_wait",
+           "lspca_transform", "lspca_accumulate_host", "lspca_fit_host", "spca_fit_stream",
+           "lspca_accumulate_csr", "lspca_fit_csr", "lspca_transform_csr",
+           "lspca_server_create", "lspca_server_submit", "lspca_server_wait",
            "lspca_server_pause", "lspca_server_get_stats", "lspca_server_destroy"]
 
 
@@ -53,7 +55,7 @@ class lspca_opts(ctypes.Structure):
 class lspca_timings(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in
                 ("omega_ms", "sketch_ms", "factor_ms", "reduce_ms", "small_ms", "qr_ms",
-                 "pass2_ms", "transform_ms", "total_ms")]
+                 "pass2_ms", "transform_ms", "total_ms", "layout_ms")]
 
 
 class lspca_server_stats(ctypes.Structure):
@@ -89,6 +91,12 @@ _SIGS = {
                                ctypes.POINTER(lspca_opts), _I64, _P, _P], ctypes.c_int),
     "lspca_fit_host": ([_P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
                         ctypes.POINTER(lspca_opts), _I64, _P, _P, _P], ctypes.c_int),
+    "lspca_accumulate_csr": ([_P, _P, _P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
+                              ctypes.POINTER(lspca_opts), _P, _P], ctypes.c_int),
+    "lspca_fit_csr": ([_P, _P, _P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
+                       ctypes.POINTER(lspca_opts), _P, _P, _P], ctypes.c_int),
+    "lspca_transform_csr": ([_P, _P, _P, ctypes.c_int, _I64, _I64, _I64, _P, _I32, _P,
+                             ctypes.POINTER(lspca_opts)], ctypes.c_int),
     "lspca_server_create": ([_P, _I64, _I32, ctypes.c_int, ctypes.c_size_t, _I32,
                              ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "lspca_server_submit": ([_P, _P, _I64, _P, ctypes.POINTER(_U64)], ctypes.c_int),
@@ -272,6 +280,73 @@ def transform(X, V, Z=None, **kw):
     o = _opts(**kw)
     _check(load().lspca_transform(X.data_ptr(), _dtype_code(X), r, n, ldx, _dev(V, "V").data_ptr(),
                                   k, Z.data_ptr(), ctypes.byref(o)))
+    return Z
+
+
+class CSR:
+    """A CSR matrix on the device: rowptr (m + 1, int64), colidx (int32) and
+    values (FP32 or FP64), n columns. rowptr may be a row slice of a larger
+    matrix (rowptr[0] > 0) sharing colidx and values."""
+
+    def __init__(self, rowptr, colidx, values, n):
+        torch = _torch()
+        for t, name in ((rowptr, "rowptr"), (colidx, "colidx"), (values, "values")):
+            _dev(t, name)
+            if t.dim() != 1 or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous 1-D device tensor")
+        if rowptr.dtype != torch.int64 or colidx.dtype != torch.int32:
+            raise TypeError("rowptr must be int64 and colidx int32")
+        if values.dtype not in (torch.float32, torch.float64):
+            raise TypeError("values must be float32 or float64")
+        if rowptr.numel() < 1:
+            raise ValueError("rowptr needs m + 1 >= 1 entries")
+        self.rowptr, self.colidx, self.values, self.n = rowptr, colidx, values, int(n)
+        self.m = rowptr.numel() - 1
+        self.nnz = int(rowptr[-1].item())              # end position of the last row
+        if self.nnz > min(colidx.numel(), values.numel()):
+            raise ValueError("rowptr[-1] exceeds the entries of colidx / values")
+
+    def rows(self, r0, r1):
+        """The row slice [r0, r1) (no copy)."""
+        return CSR(self.rowptr[r0:r1 + 1], self.colidx, self.values, self.n)
+
+    def _args(self):
+        return (self.rowptr.data_ptr(), self.colidx.data_ptr(), self.values.data_ptr(),
+                _dtype_code(self.values))
+
+
+def accumulate_csr(X, k, kind, seed, F, G=None, **kw):
+    """Algorithm 4 step 2 for a CSR slice X: F += U^T X, G += U^T U."""
+    o = _opts(**kw)
+    _check(load().lspca_accumulate_csr(*X._args(), X.m, X.n, X.nnz, k, KIND[kind], seed,
+                                       ctypes.byref(o), _dev(F, "F").data_ptr(),
+                                       _dev(G, "G").data_ptr() if G is not None else None))
+    return F, G
+
+
+def fit_csr(X, k, kind="gaussian", seed=0, want_sigma_x=False, **kw):
+    """Lazy SPCA (Algorithm 2) of a CSR X: V (n x k), D (k) [, Sigma^s (k)]."""
+    dev = X.values.device
+    V = _f64_out((X.n, k), dev)
+    s = _f64_out((k,), dev)
+    sx = _f64_out((k,), dev) if want_sigma_x else None
+    o = _opts(**kw)
+    _check(load().lspca_fit_csr(*X._args(), X.m, X.n, X.nnz, k, KIND[kind], seed, ctypes.byref(o),
+                                V.data_ptr(), s.data_ptr(), sx.data_ptr() if sx is not None else None))
+    return (V, s, sx) if want_sigma_x else (V, s)
+
+
+def transform_csr(X, V, Z=None, **kw):
+    """Z = X V for a CSR X (Z of the value type)."""
+    torch = _torch()
+    k = V.shape[1]
+    if V.dtype != torch.float64 or not V.is_contiguous() or V.shape[0] != X.n:
+        raise ValueError("V must be a contiguous n x k FP64 device tensor")
+    if Z is None:
+        Z = torch.empty((X.m, k), dtype=X.values.dtype, device=X.values.device)
+    o = _opts(**kw)
+    _check(load().lspca_transform_csr(*X._args(), X.m, X.n, X.nnz, _dev(V, "V").data_ptr(), k,
+                                      Z.data_ptr(), ctypes.byref(o)))
     return Z
 
 

@@ -4,6 +4,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <vector>
 
 #include "common.h"
 
@@ -107,11 +108,12 @@ int PhaseTimer::finish(lspca_timings *out) {
   memset(out, 0, sizeof(*out));
   LSPCA_HIP(hipEventSynchronize(ev[n - 1]));
   double *fields[] = {&out->omega_ms, &out->sketch_ms, &out->factor_ms, &out->reduce_ms,
-                      &out->small_ms, &out->qr_ms, &out->pass2_ms, &out->transform_ms};
+                      &out->small_ms, &out->qr_ms, &out->pass2_ms, &out->transform_ms,
+                      &out->layout_ms};
   for (int i = 1; i < n; ++i) {
     float ms = 0;
     LSPCA_HIP(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
-    if (slot[i] >= 0 && slot[i] < 8) *fields[slot[i]] += ms;
+    if (slot[i] >= 0 && slot[i] < 9) *fields[slot[i]] += ms;
   }
   float tot = 0;
   LSPCA_HIP(hipEventElapsedTime(&tot, ev[0], ev[n - 1]));
@@ -429,6 +431,154 @@ static int lock_device(Locked &L) {
   LSPCA_TRY(current_device(&dev));
   L.st = &device_state(dev);
   L.lk = std::unique_lock<std::mutex>(L.st->mu);
+  return LSPCA_OK;
+}
+
+
+// ------------------------------------------------------ sparse (CSR) X -----
+static int check_csr_args(const int64_t *rowptr, const int32_t *colidx, const void *vals, int vdt,
+                          int64_t m, int64_t n, int64_t nnz, int k, int kind, const Opts &o) {
+  if (!rowptr) { set_error("rowptr is NULL"); return LSPCA_EINVAL; }
+  if (nnz > 0 && (!colidx || !vals)) { set_error("colidx and values must not be NULL"); return LSPCA_EINVAL; }
+  if (vdt != LSPCA_F32 && vdt != LSPCA_F64) {
+    set_error("CSR values must be FP32 or FP64 (dtype %d)", vdt);
+    return valid_dtype(vdt) ? LSPCA_ENOTSUP : LSPCA_EINVAL;
+  }
+  if (m < 1 || n < 1) { set_error("m and n must be >= 1 (m=%lld n=%lld)", (long long)m, (long long)n); return LSPCA_EINVAL; }
+  if (n > (1 << 30)) { set_error("n too large"); return LSPCA_EINVAL; }
+  if (nnz < 0) { set_error("nnz must be >= 0"); return LSPCA_EINVAL; }
+  if (k < 1 || k > n) { set_error("k must satisfy 1 <= k <= n (k=%d n=%lld)", k, (long long)n); return LSPCA_EINVAL; }
+  if (k > 4096) { set_error("k > 4096 is not supported"); return LSPCA_ENOTSUP; }
+  if (!valid_kind(kind)) { set_error("unknown omega kind %d", kind); return LSPCA_EINVAL; }
+  if (kind == LSPCA_OMEGA_VERY_SPARSE && !valid_p(o.p)) { set_error("sparse p must be a power of two in [1, 2^30] (p=%u)", o.p); return LSPCA_EINVAL; }
+  return LSPCA_OK;
+}
+
+// Stripes of the CSR pass: row starts r[s] (r.back() = m) and entry starts
+// e[s] = rowptr[r[s]]. A stripe holds at most `rows_cap` rows (the Y
+// budget) and, where the granularity allows, at most `nnz_cap` entries (the
+// CSC buffers); boundaries fall on multiples of g rows.
+struct CsrPlan {
+  std::vector<int64_t> r, e;
+  int64_t max_rows = 0, max_cnt = 0;
+  int splits_g = 0;
+  size_t bytes = 0;
+};
+
+// Validates the CSR arrays on the device, then plans the stripes. Uses the
+// workspace (reset on return).
+static int plan_csr(const int64_t *rowptr, const int32_t *colidx, lspca_dtype vdt, int64_t m, int64_t n,
+                    int64_t nnz, int k, bool want_g, const Opts &o, Workspace &ws, CsrPlan &pl) {
+  hipStream_t s = o.stream;
+  const size_t esz = dtype_size(vdt);
+  int64_t budget = (int64_t)2 << 30;                 // Y bytes, as the dense pass
+  if (const char *v = getenv("LSPCA_STRIPE_BYTES")) {
+    const long long b = atoll(v);
+    if (b > 0) budget = b;
+  }
+  int64_t nnz_cap = (int64_t)1 << 28;                // entries per CSC build
+  if (const char *v = getenv("LSPCA_CSR_STRIPE_NNZ")) {
+    const long long b = atoll(v);
+    if (b > 0) nnz_cap = b;
+  }
+  int64_t rows_cap = budget / ((int64_t)k * esz);
+  rows_cap = rows_cap < 64 ? 64 : rows_cap;
+  rows_cap = rows_cap > kCsrMaxRows ? kCsrMaxRows : rows_cap;
+  int64_t g = 64;
+  if (o.stripe_rows > 0) {
+    g = o.stripe_rows < kCsrMaxRows ? o.stripe_rows : kCsrMaxRows;
+    rows_cap = g;
+  }
+  const int64_t nb = (m + g - 1) / g + 1;
+  ws.reset();
+  LSPCA_TRY(ws.ensure(ws_bytes<int>(1) + ws_bytes<int64_t>(nb)));
+  int *flag = ws.take<int>(1);
+  int64_t *bd = ws.take<int64_t>(nb);
+  LSPCA_TRY(csr_check(rowptr, colidx, m, n, nnz, flag, s));
+  LSPCA_TRY(launch_row_bounds(rowptr, m, g, nb, bd, s));
+  std::vector<int64_t> hb(nb);
+  LSPCA_HIP(hipMemcpyAsync(hb.data(), bd, nb * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  LSPCA_HIP(hipStreamSynchronize(s));
+  ws.reset();
+  pl = CsrPlan();
+  int64_t b = 0;                                     // block index of the stripe start
+  while (b < nb - 1) {
+    int64_t t = b + 1;
+    while (t < nb - 1 && (t + 1 - b) * g <= rows_cap && hb[t + 1] - hb[b] <= nnz_cap) ++t;
+    const int64_t r0 = b * g, r1 = t * g < m ? t * g : m;
+    pl.r.push_back(r0);
+    pl.e.push_back(hb[b]);
+    pl.max_rows = std::max(pl.max_rows, r1 - r0);
+    pl.max_cnt = std::max(pl.max_cnt, hb[t] - hb[b]);
+    b = t;
+  }
+  pl.r.push_back(m);
+  pl.e.push_back(hb[nb - 1]);
+  if (pl.max_cnt > (int64_t)INT32_MAX) {
+    set_error("CSR: %lld entries in %lld rows exceed the 2^31 - 1 entries of one stripe",
+              (long long)pl.max_cnt, (long long)g);
+    return LSPCA_ENOTSUP;
+  }
+  pl.splits_g = want_g ? tn_pick_splits(pl.max_rows, k, k) : 0;
+  const size_t E = (size_t)pl.max_cnt;
+  const size_t segs = (size_t)csc_segments_max(pl.max_cnt, n, k);
+  pl.bytes = ws_bytes<char>(esz * (size_t)n * k)                // Omega, row-major
+             + ws_bytes<char>(esz * (size_t)pl.max_rows * k)    // Y stripe
+             + (want_g ? ws_bytes<char>(esz * tn_partial_elems(k, k, pl.splits_g)) : 0)
+             + 5 * ws_bytes<int32_t>(E)                         // keys skeys idx sidx rowof
+             + ws_bytes<char>(esz * E) + 3 * ws_bytes<int64_t>((size_t)n + 1)
+             + ws_bytes<int32_t>(segs) + ws_bytes<double>(segs * (size_t)k)
+             + ws_bytes<char>(csc_temp_bytes(pl.max_cnt, n));
+  return LSPCA_OK;
+}
+
+// Algorithm 4 step 2 over a CSR X: per stripe Y = X_s Omega (row SpMM),
+// F += Y^T X_s (column-ordered, from the stripe's CSC form), G += Y^T Y.
+static int csr_pass(const int64_t *rowptr, const int32_t *colidx, const void *vals, lspca_dtype vdt,
+                    int64_t n, int k, int kind, uint64_t seed, const Opts &o, const CsrPlan &pl,
+                    double *F, double *G, Workspace &ws, PhaseTimer &tm) {
+  hipStream_t s = o.stream;
+  const size_t esz = dtype_size(vdt);
+  const size_t E = (size_t)pl.max_cnt;
+  void *Om = ws.take<char>(esz * (size_t)n * k);
+  void *Y = ws.take<char>(esz * (size_t)pl.max_rows * k);
+  void *PG = G ? ws.take<char>(esz * tn_partial_elems(k, k, pl.splits_g)) : nullptr;
+  CscBuffers b;
+  b.keys = ws.take<int32_t>(E);
+  b.skeys = ws.take<int32_t>(E);
+  b.idx = ws.take<uint32_t>(E);
+  b.sidx = ws.take<uint32_t>(E);
+  b.rowof = ws.take<int32_t>(E);
+  b.crow = b.keys;                                   // the unsorted keys are dead after the sort
+  b.cval = ws.take<char>(esz * E);
+  b.colptr = ws.take<int64_t>((size_t)n + 1);
+  b.segcnt = ws.take<int64_t>((size_t)n + 1);
+  b.segoff = ws.take<int64_t>((size_t)n + 1);
+  const size_t segs = (size_t)csc_segments_max(pl.max_cnt, n, k);
+  b.segcol = ws.take<int32_t>(segs);
+  b.P = ws.take<double>(segs * (size_t)k);
+  b.seg = csc_segment(pl.max_cnt, k);                // one segment length for every stripe
+  b.temp_bytes = csc_temp_bytes(pl.max_cnt, n);
+  b.temp = ws.take<char>(b.temp_bytes);
+  LSPCA_TRY(launch_omega(n, k, kind, seed, o.p, vdt, Om, k, 1, s));
+  tm.mark(PH_OMEGA);
+  for (size_t t = 0; t + 1 < pl.r.size(); ++t) {
+    const int64_t r0 = pl.r[t], rows = pl.r[t + 1] - r0;
+    const int64_t e0 = pl.e[t], cnt = pl.e[t + 1] - e0;
+    LSPCA_TRY(launch_csr_spmm(vdt, rowptr, colidx, vals, r0, rows, Om, k, Y, k, s));
+    tm.mark(PH_SKETCH);
+    LSPCA_TRY(build_csc(vdt, rowptr, colidx, vals, r0, rows, e0, cnt, n, k, b, s));
+    tm.mark(PH_LAYOUT);
+    LSPCA_TRY(launch_csc_factor(vdt, b, n, cnt, Y, k, k, F, s));
+    int sg = 0;
+    if (G) {
+      sg = tn_pick_splits(rows, k, k);
+      LSPCA_TRY(launch_tn(vdt, Y, k, Y, k, PG, rows, k, k, sg, s));
+    }
+    tm.mark(PH_FACTOR);
+    if (G) LSPCA_TRY(launch_reduce_add(vdt, PG, sg, (int64_t)k * k, G, 1, s));
+    tm.mark(PH_REDUCE);
+  }
   return LSPCA_OK;
 }
 
@@ -768,6 +918,89 @@ int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, 
   int rank_flag = 0;
   LSPCA_TRY(small_factor(F, nullptr, k, n, V, sigma, nullptr, ws, s, &rank_flag, o.small_route));
   tm.mark(PH_SMALL);
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int lspca_accumulate_csr(const int64_t *rowptr, const int32_t *colidx, const void *values,
+                         lspca_dtype vdt, int64_t m, int64_t n, int64_t nnz, int32_t k,
+                         lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts, double *F,
+                         double *G) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  LSPCA_TRY(check_csr_args(rowptr, colidx, values, vdt, m, n, nnz, k, kind, o));
+  if (!F) { set_error("F is NULL"); return LSPCA_EINVAL; }
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  Workspace &ws = L.st->ws;
+  CsrPlan pl;
+  LSPCA_TRY(plan_csr(rowptr, colidx, vdt, m, n, nnz, k, G != nullptr, o, ws, pl));
+  LSPCA_TRY(ws.ensure(pl.bytes));
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, o.stream);
+  LSPCA_TRY(csr_pass(rowptr, colidx, values, vdt, n, k, kind, seed, o, pl, F, G, ws, tm));
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int lspca_fit_csr(const int64_t *rowptr, const int32_t *colidx, const void *values, lspca_dtype vdt,
+                  int64_t m, int64_t n, int64_t nnz, int32_t k, lspca_omega_kind kind, uint64_t seed,
+                  const lspca_opts *opts, double *V, double *sigma, double *sigma_x) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  LSPCA_TRY(check_csr_args(rowptr, colidx, values, vdt, m, n, nnz, k, kind, o));
+  if (!V || !sigma) { set_error("V and sigma must not be NULL"); return LSPCA_EINVAL; }
+  if (k > m) { set_error("k must satisfy k <= min(m, n) (k=%d m=%lld)", k, (long long)m); return LSPCA_EINVAL; }
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  Workspace &ws = L.st->ws;
+  const bool want_g = sigma_x != nullptr;
+  CsrPlan pl;
+  LSPCA_TRY(plan_csr(rowptr, colidx, vdt, m, n, nnz, k, want_g, o, ws, pl));
+  const size_t fg = ws_bytes<double>((size_t)k * n) + ws_bytes<double>((size_t)k * k);
+  const size_t fb = factor_bytes(n, k);
+  LSPCA_TRY(ws.ensure(fg + (pl.bytes > fb ? pl.bytes : fb)));
+  double *F = ws.take<double>((size_t)k * n);
+  double *G = ws.take<double>((size_t)k * k);
+  const size_t mark = ws.used;
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, o.stream);
+  LSPCA_TRY(zero_f64(F, (int64_t)k * n, o.stream));
+  LSPCA_TRY(zero_f64(G, (int64_t)k * k, o.stream));
+  LSPCA_TRY(csr_pass(rowptr, colidx, values, vdt, n, k, kind, seed, o, pl, F, want_g ? G : nullptr, ws, tm));
+  ws.used = mark;
+  int rank_flag = 0;
+  LSPCA_TRY(small_factor(F, want_g ? G : nullptr, k, n, V, sigma, sigma_x, ws, o.stream, &rank_flag,
+                         o.small_route));
+  tm.mark(PH_SMALL);
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int lspca_transform_csr(const int64_t *rowptr, const int32_t *colidx, const void *values, lspca_dtype vdt,
+                        int64_t r, int64_t n, int64_t nnz, const double *V, int32_t k, void *Z,
+                        const lspca_opts *opts) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  if (r < 0) { set_error("r must be >= 0"); return LSPCA_EINVAL; }
+  if (r == 0) return LSPCA_OK;
+  LSPCA_TRY(check_csr_args(rowptr, colidx, values, vdt, r, n, nnz, k, LSPCA_OMEGA_GAUSSIAN, o));
+  if (!V || !Z) { set_error("V and Z must not be NULL"); return LSPCA_EINVAL; }
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  Workspace &ws = L.st->ws;
+  const bool f32 = vdt == LSPCA_F32;
+  ws.reset();
+  LSPCA_TRY(ws.ensure(ws_bytes<int>(1) + (f32 ? ws_bytes<float>((size_t)n * k) : 0)));
+  int *flag = ws.take<int>(1);
+  float *V32 = f32 ? ws.take<float>((size_t)n * k) : nullptr;
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, o.stream);
+  LSPCA_TRY(csr_check(rowptr, colidx, r, n, nnz, flag, o.stream));
+  if (f32) LSPCA_TRY(launch_f64_to_f32(V, (int64_t)n * k, V32, o.stream));
+  LSPCA_TRY(launch_csr_spmm(vdt, rowptr, colidx, values, 0, r, f32 ? (const void *)V32 : (const void *)V, k,
+                            Z, k, o.stream));
+  tm.mark(PH_TRANSFORM);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;
 }

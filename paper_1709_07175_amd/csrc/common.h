@@ -136,7 +136,7 @@ struct PhaseTimer {
   ~PhaseTimer();
 };
 enum Phase { PH_START = -1, PH_OMEGA = 0, PH_SKETCH, PH_FACTOR, PH_REDUCE, PH_SMALL,
-             PH_QR, PH_PASS2, PH_TRANSFORM };
+             PH_QR, PH_PASS2, PH_TRANSFORM, PH_LAYOUT };
 
 // ---------------------------------------------------------- launchers ------
 // Omega generation (omega.hip). out has the layout out[j*ld_j + c*ld_c].
@@ -189,6 +189,50 @@ int launch_sparse_sketch(lspca_dtype dt, const void *X, int64_t m, int64_t n, in
                          uint64_t seed, uint32_t p, int cap, float *Y, int64_t ldy,
                          unsigned *colmax, void *Yh, void *Yl, int *overflow, hipStream_t s);
 size_t tn_partial_elems(int Mi, int Nj, int splits);
+
+// Sparse X in CSR form (csr.hip). Row i's entries are colidx[e], vals[e] for
+// e in [rowptr[i], rowptr[i + 1]). csr_check validates rowptr (rowptr[0] >= 0,
+// nondecreasing, rowptr[m] = nnz) and colidx over [rowptr[0], nnz) on the
+// device and reports the result (dflag: one device int of scratch).
+int csr_check(const int64_t *rowptr, const int32_t *colidx, int64_t m, int64_t n, int64_t nnz,
+              int *dflag, hipStream_t s);
+constexpr int64_t kCsrMaxRows = (int64_t)1 << 24;   // rows per row-parallel launch
+// Y[i * ldy + c] = sum over row r0 + i of v * B[col * k + c], i < rows; B
+// row-major n x k, all of the value type vdt (FP32 or FP64).
+int launch_csr_spmm(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals,
+                    int64_t r0, int64_t rows, const void *B, int k, void *Y, int64_t ldy, hipStream_t s);
+// rowptr[r0 + g * t] for t = 0 .. nb - 1 (the last clamped to rowptr[r0 +
+// rows]): stripe boundaries of the CSC build.
+int launch_row_bounds(const int64_t *rowptr, int64_t rows, int64_t g, int64_t nb, int64_t *out,
+                      hipStream_t s);
+// The CSC form of a stripe of at most kCsrMaxRows rows (entries [e0, e0 +
+// cnt), cnt < 2^31): column j's entries at [colptr[j], colptr[j + 1]), in
+// row order, with the stripe-local row crow[t] and the value cval[t]; and
+// the split of the column sums into segments of at most `seg` entries
+// (csc_segment of the largest stripe, set by the caller; segcnt, segoff:
+// n + 1 int64; segcol: one int per segment; P: k FP64 per segment,
+// csc_segments_max of them).
+struct CscBuffers {
+  int32_t *keys, *skeys, *rowof, *crow, *segcol;
+  uint32_t *idx, *sidx;
+  void *cval;
+  int64_t *colptr, *segcnt, *segoff;
+  double *P;
+  int64_t seg;
+  void *temp;
+  size_t temp_bytes;
+};
+int64_t csc_segment(int64_t cnt, int k);
+int64_t csc_segments_max(int64_t cnt, int64_t n, int k);
+size_t csc_temp_bytes(int64_t cnt, int64_t n);
+int build_csc(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals, int64_t r0,
+              int64_t rows, int64_t e0, int64_t cnt, int64_t n, int k, CscBuffers &b, hipStream_t s);
+// F[c * n + j] += sum over column j of the stripe of v * Y[row * ldy + c]
+// (FP64 accumulation, Y of the value type).
+int launch_csc_factor(lspca_dtype vdt, const CscBuffers &b, int64_t n, int64_t cnt, const void *Y, int k,
+                      int64_t ldy, double *F, hipStream_t s);
+// B = V (n x k FP64, row-major) rounded to FP32, same layout.
+int launch_f64_to_f32(const double *V, int64_t count, float *out, hipStream_t s);
 
 // Reductions and small FP64 stage (small.hip).
 constexpr int kSmallFlags = 128;   // flag and sweep-counter ints of the small stage

@@ -10,3 +10,6 @@ from .lowrank import (  # noqa: F401
     CONFIGS, config, sigmas, lowrank_np, lowrank_torch, to_storage_np,
     storage_to_f64, request_sizes, random_orthonormal_np,
 )
+from .sparse import (  # noqa: F401
+    CSR_CONFIG, FEATURES, DENSITY, column_density, csr_np, csr_torch,
+)

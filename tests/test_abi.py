@@ -149,3 +149,28 @@ def test_spca_fit_stream_argument_checks(lib):
     assert lib.spca_fit_stream(None, L.F32, 100, 50, 50, 5, L.GAUSSIAN, 1, None, 1 << 20, 1 << 21) == -1
     assert lib.spca_fit_stream(1 << 20, L.F32, 4, 50, 50, 5, L.GAUSSIAN, 1, None, 1 << 21, 1 << 22) == -1  # k > m
     assert lib.spca_fit_stream(1 << 20, L.F32, 100, 50, 50, 5, L.GAUSSIAN, 1, None, None, 1 << 22) == -1
+
+
+def test_csr_argument_checks(lib):
+    # refused before any device work: NULL arrays, unsupported value type,
+    # bad sizes, k above min(m, n)
+    P, F, G = 1 << 20, 1 << 21, 1 << 22
+    acc = lib.lspca_accumulate_csr
+    assert acc(None, P, P, L.F32, 10, 10, 5, 3, L.GAUSSIAN, 1, None, F, None) == -1
+    assert "rowptr" in lib.lspca_last_error().decode()
+    assert acc(P, None, P, L.F32, 10, 10, 5, 3, L.GAUSSIAN, 1, None, F, None) == -1
+    assert acc(P, P, P, L.BF16, 10, 10, 5, 3, L.GAUSSIAN, 1, None, F, None) == -7
+    assert acc(P, P, P, 9, 10, 10, 5, 3, L.GAUSSIAN, 1, None, F, None) == -1
+    assert acc(P, P, P, L.F32, 0, 10, 5, 3, L.GAUSSIAN, 1, None, F, None) == -1
+    assert acc(P, P, P, L.F32, 10, 10, -1, 3, L.GAUSSIAN, 1, None, F, None) == -1
+    assert acc(P, P, P, L.F32, 10, 10, 5, 11, L.GAUSSIAN, 1, None, F, None) == -1
+    assert acc(P, P, P, L.F32, 10, 10, 5, 3, 7, 1, None, F, None) == -1
+    assert acc(P, P, P, L.F32, 10, 10, 5, 3, L.GAUSSIAN, 1, None, None, G) == -1
+    fit = lib.lspca_fit_csr
+    assert fit(P, P, P, L.F64, 4, 10, 5, 5, L.GAUSSIAN, 1, None, F, G, None) == -1      # k > m
+    assert "min(m, n)" in lib.lspca_last_error().decode()
+    assert fit(P, P, P, L.F64, 10, 10, 5, 3, L.GAUSSIAN, 1, None, None, G, None) == -1
+    tr = lib.lspca_transform_csr
+    assert tr(None, None, None, L.F32, 0, 10, 0, None, 3, None, None) == 0               # r = 0: no work
+    assert tr(P, P, P, L.F32, 5, 10, 5, None, 3, F, None) == -1                          # V NULL
+    assert tr(P, P, P, L.F32, -1, 10, 5, F, 3, G, None) == -1

@@ -341,3 +341,76 @@ def test_canonical_order_and_sign():
     # ties in magnitude: the lowest index decides
     Vt, _ = O.canonicalize(np.array([[-0.5], [0.5]]), np.array([1.0]))
     assert Vt[0, 0] == 0.5
+
+
+# ------------------------------------------------------------ sparse X (CSR) --
+
+def test_csr_dense_hand_example():
+    """A 4 x 5 matrix written out by hand: an empty row, unsorted columns and
+    a repeated column (whose values add)."""
+    rowptr = [0, 2, 2, 5, 6]
+    colidx = [3, 0, 4, 1, 4, 2]
+    values = [2.0, -1.0, 0.5, 3.0, 0.25, 7.0]
+    want = np.array([[-1, 0, 0, 2, 0],
+                     [0, 0, 0, 0, 0],
+                     [0, 3, 0, 0, 0.75],
+                     [0, 0, 7, 0, 0]], dtype=np.float64)
+    assert np.array_equal(O.csr_dense(rowptr, colidx, values, 5), want)
+
+
+def test_csr_dense_matches_scipy_and_row_slices():
+    """Against scipy.sparse (an independent CSR implementation), including a
+    row slice given by an offset rowptr."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(4)
+    m, n = 57, 41
+    counts = rng.integers(0, 9, m)
+    counts[[3, 17, 40]] = 0
+    rowptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    colidx = rng.integers(0, n, rowptr[-1]).astype(np.int32)       # repeats allowed
+    values = rng.standard_normal(rowptr[-1])
+    want = sp.csr_matrix((values, colidx, rowptr), shape=(m, n)).toarray()
+    assert np.allclose(O.csr_dense(rowptr, colidx, values, n), want, rtol=0, atol=1e-15)
+    r0, r1 = 11, 44
+    got = O.csr_dense(rowptr[r0:r1 + 1], colidx, values, n)
+    assert np.allclose(got, want[r0:r1], rtol=0, atol=1e-15)
+
+
+def test_csr_generator_density():
+    """The synthetic feature matrix has the requested mean density and sorted,
+    unique columns in every row."""
+    from synth import csr_np
+    rowptr, colidx, values = csr_np(300, 5000, density=0.0244, seed=9)
+    assert abs(rowptr[-1] / (300 * 5000) - 0.0244) < 0.002
+    for i in range(0, 300, 37):
+        c = colidx[rowptr[i]:rowptr[i + 1]]
+        assert np.all(np.diff(c) > 0)
+    assert np.all((values > 0) & (values <= 1))
+
+
+def test_csr_factor_rows_brute_force():
+    """U_C = X Omega_C and F_C = U_C^T X by explicit loops over the stored
+    entries of a tiny CSR matrix (brute force)."""
+    rng = np.random.default_rng(12)
+    m, n, c = 9, 7, 3
+    counts = rng.integers(0, 5, m)
+    rowptr = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    colidx = rng.integers(0, n, rowptr[-1]).astype(np.int32)
+    values = rng.standard_normal(rowptr[-1])
+    om = rng.standard_normal((n, c))
+    U = np.zeros((m, c))
+    for i in range(m):
+        for e in range(rowptr[i], rowptr[i + 1]):
+            for a in range(c):
+                U[i, a] += values[e] * om[colidx[e], a]
+    F = np.zeros((c, n))
+    for i in range(m):
+        for e in range(rowptr[i], rowptr[i + 1]):
+            for a in range(c):
+                F[a, colidx[e]] += U[i, a] * values[e]
+    gotU, gotF = O.csr_factor_rows(rowptr, colidx, values, n, om)
+    assert np.allclose(gotU, U, rtol=1e-14, atol=1e-14)
+    assert np.allclose(gotF, F, rtol=1e-14, atol=1e-14)
+    # the same on a row slice (offset rowptr)
+    gotU2, _ = O.csr_factor_rows(rowptr[2:7], colidx, values, n, om)
+    assert np.allclose(gotU2, U[2:6], rtol=1e-14, atol=1e-14)
