@@ -458,17 +458,26 @@ static int check_csr_args(const int64_t *rowptr, const int32_t *colidx, const vo
 // e[s] = rowptr[r[s]]. A stripe holds at most `rows_cap` rows (the Y
 // budget) and, where the granularity allows, at most `nnz_cap` entries (the
 // CSC buffers); boundaries fall on multiples of g rows.
+// The very sparse Omega goes through row lists (int32 positions: n k < 2^31).
+static bool csr_lists(int kind, int64_t n, int k) {
+  return kind == LSPCA_OMEGA_VERY_SPARSE && n * (int64_t)k < ((int64_t)1 << 31);
+}
+
 struct CsrPlan {
   std::vector<int64_t> r, e;
   int64_t max_rows = 0, max_cnt = 0;
   int splits_g = 0;
+  int64_t ldy = 0;                                   // row pitch of Y (128-byte rows)
+  CscShape shape;                                    // of the largest stripe
   size_t bytes = 0;
 };
+
+
 
 // Validates the CSR arrays on the device, then plans the stripes. Uses the
 // workspace (reset on return).
 static int plan_csr(const int64_t *rowptr, const int32_t *colidx, lspca_dtype vdt, int64_t m, int64_t n,
-                    int64_t nnz, int k, bool want_g, const Opts &o, Workspace &ws, CsrPlan &pl) {
+                    int64_t nnz, int k, int kind, bool want_g, const Opts &o, Workspace &ws, CsrPlan &pl) {
   hipStream_t s = o.stream;
   const size_t esz = dtype_size(vdt);
   int64_t budget = (int64_t)2 << 30;                 // Y bytes, as the dense pass
@@ -520,15 +529,21 @@ static int plan_csr(const int64_t *rowptr, const int32_t *colidx, lspca_dtype vd
     return LSPCA_ENOTSUP;
   }
   pl.splits_g = want_g ? tn_pick_splits(pl.max_rows, k, k) : 0;
+  pl.ldy = csr_ld(k, esz);
+  pl.shape = csc_shape(pl.max_rows, n, pl.max_cnt, k, esz);
   const size_t E = (size_t)pl.max_cnt;
-  const size_t segs = (size_t)csc_segments_max(pl.max_cnt, n, k);
-  pl.bytes = ws_bytes<char>(esz * (size_t)n * k)                // Omega, row-major
-             + ws_bytes<char>(esz * (size_t)pl.max_rows * k)    // Y stripe
+  const size_t L1 = (size_t)pl.shape.lists + 1;
+  pl.bytes = ws_bytes<char>(esz * (size_t)n * pl.ldy)           // Omega, row-major
+             + ws_bytes<char>(esz * (size_t)pl.max_rows * pl.ldy)  // Y stripe
+             + ws_bytes<double>((size_t)n * k)                  // this call's F, transposed
              + (want_g ? ws_bytes<char>(esz * tn_partial_elems(k, k, pl.splits_g)) : 0)
              + 5 * ws_bytes<int32_t>(E)                         // keys skeys idx sidx rowof
-             + ws_bytes<char>(esz * E) + 3 * ws_bytes<int64_t>((size_t)n + 1)
-             + ws_bytes<int32_t>(segs) + ws_bytes<double>(segs * (size_t)k)
-             + ws_bytes<char>(csc_temp_bytes(pl.max_cnt, n));
+             + ws_bytes<char>(esz * E) + 4 * ws_bytes<int64_t>(L1)
+             + ws_bytes<int32_t>((size_t)pl.shape.segs_max)
+             + ws_bytes<double>((size_t)pl.shape.partial_rows * k)
+             + ws_bytes<char>(std::max(csc_temp_bytes(pl.max_cnt, pl.shape.lists), om_scan_bytes(n)));
+  if (csr_lists(kind, n, k))                                      // Omega row lists
+    pl.bytes += 2 * ws_bytes<int32_t>((size_t)n + 1) + ws_bytes<int32_t>((size_t)n * k);
   return LSPCA_OK;
 }
 
@@ -540,8 +555,11 @@ static int csr_pass(const int64_t *rowptr, const int32_t *colidx, const void *va
   hipStream_t s = o.stream;
   const size_t esz = dtype_size(vdt);
   const size_t E = (size_t)pl.max_cnt;
-  void *Om = ws.take<char>(esz * (size_t)n * k);
-  void *Y = ws.take<char>(esz * (size_t)pl.max_rows * k);
+  const size_t L1 = (size_t)pl.shape.lists + 1;
+  const int64_t ldy = pl.ldy;
+  void *Om = ws.take<char>(esz * (size_t)n * ldy);
+  void *Y = ws.take<char>(esz * (size_t)pl.max_rows * ldy);
+  double *Ft = ws.take<double>((size_t)n * k);
   void *PG = G ? ws.take<char>(esz * tn_partial_elems(k, k, pl.splits_g)) : nullptr;
   CscBuffers b;
   b.keys = ws.take<int32_t>(E);
@@ -551,34 +569,49 @@ static int csr_pass(const int64_t *rowptr, const int32_t *colidx, const void *va
   b.rowof = ws.take<int32_t>(E);
   b.crow = b.keys;                                   // the unsorted keys are dead after the sort
   b.cval = ws.take<char>(esz * E);
-  b.colptr = ws.take<int64_t>((size_t)n + 1);
-  b.segcnt = ws.take<int64_t>((size_t)n + 1);
-  b.segoff = ws.take<int64_t>((size_t)n + 1);
-  const size_t segs = (size_t)csc_segments_max(pl.max_cnt, n, k);
-  b.segcol = ws.take<int32_t>(segs);
-  b.P = ws.take<double>(segs * (size_t)k);
-  b.seg = csc_segment(pl.max_cnt, k);                // one segment length for every stripe
-  b.temp_bytes = csc_temp_bytes(pl.max_cnt, n);
+  b.colptr = ws.take<int64_t>(L1);
+  b.cnt = ws.take<int64_t>(L1);
+  b.segoff = ws.take<int64_t>(L1);
+  b.moff = ws.take<int64_t>(L1);
+  b.segcol = ws.take<int32_t>((size_t)pl.shape.segs_max);
+  b.P = ws.take<double>((size_t)pl.shape.partial_rows * k);
+  b.temp_bytes = std::max(csc_temp_bytes(pl.max_cnt, pl.shape.lists), om_scan_bytes(n));
   b.temp = ws.take<char>(b.temp_bytes);
-  LSPCA_TRY(launch_omega(n, k, kind, seed, o.p, vdt, Om, k, 1, s));
+  const bool lists = csr_lists(kind, n, k);
+  int32_t *optr = nullptr, *oc = nullptr;
+  LSPCA_TRY(zero_f64(Ft, (int64_t)n * k, s));
+  LSPCA_TRY(launch_omega(n, k, kind, seed, o.p, vdt, Om, ldy, 1, s));
+  if (lists) {
+    int32_t *ocnt = ws.take<int32_t>((size_t)n + 1);
+    optr = ws.take<int32_t>((size_t)n + 1);
+    oc = ws.take<int32_t>((size_t)n * k);
+    LSPCA_TRY(build_omega_lists(vdt, Om, ldy, n, k, ocnt, optr, oc, b.temp, b.temp_bytes, s));
+  }
   tm.mark(PH_OMEGA);
   for (size_t t = 0; t + 1 < pl.r.size(); ++t) {
     const int64_t r0 = pl.r[t], rows = pl.r[t + 1] - r0;
     const int64_t e0 = pl.e[t], cnt = pl.e[t + 1] - e0;
-    LSPCA_TRY(launch_csr_spmm(vdt, rowptr, colidx, vals, r0, rows, Om, k, Y, k, s));
+    if (lists)
+      LSPCA_TRY(launch_csr_sketch_lists(vdt, rowptr, colidx, vals, r0, rows, optr, oc, k, Y, ldy, s));
+    else
+      LSPCA_TRY(launch_csr_spmm(vdt, rowptr, colidx, vals, r0, rows, Om, ldy, k, Y, ldy, s));
     tm.mark(PH_SKETCH);
-    LSPCA_TRY(build_csc(vdt, rowptr, colidx, vals, r0, rows, e0, cnt, n, k, b, s));
+    // this stripe's row blocks; the segment length of the largest stripe
+    CscShape sh = csc_shape(rows, n, pl.max_cnt, k, esz);
+    LSPCA_TRY(build_csc(vdt, rowptr, colidx, vals, r0, rows, e0, cnt, n, sh, b, s));
     tm.mark(PH_LAYOUT);
-    LSPCA_TRY(launch_csc_factor(vdt, b, n, cnt, Y, k, k, F, s));
+    LSPCA_TRY(launch_csc_factor(vdt, b, sh, n, cnt, Y, k, ldy, Ft, s));
     int sg = 0;
     if (G) {
       sg = tn_pick_splits(rows, k, k);
-      LSPCA_TRY(launch_tn(vdt, Y, k, Y, k, PG, rows, k, k, sg, s));
+      LSPCA_TRY(launch_tn(vdt, Y, ldy, Y, ldy, PG, rows, k, k, sg, s));
     }
     tm.mark(PH_FACTOR);
     if (G) LSPCA_TRY(launch_reduce_add(vdt, PG, sg, (int64_t)k * k, G, 1, s));
     tm.mark(PH_REDUCE);
   }
+  LSPCA_TRY(launch_add_transposed(Ft, n, k, F, s));
+  tm.mark(PH_REDUCE);
   return LSPCA_OK;
 }
 
@@ -934,7 +967,7 @@ int lspca_accumulate_csr(const int64_t *rowptr, const int32_t *colidx, const voi
   LSPCA_TRY(lock_device(L));
   Workspace &ws = L.st->ws;
   CsrPlan pl;
-  LSPCA_TRY(plan_csr(rowptr, colidx, vdt, m, n, nnz, k, G != nullptr, o, ws, pl));
+  LSPCA_TRY(plan_csr(rowptr, colidx, vdt, m, n, nnz, k, kind, G != nullptr, o, ws, pl));
   LSPCA_TRY(ws.ensure(pl.bytes));
   PhaseTimer tm;
   tm.begin(o.timing != 0, o.stream);
@@ -956,7 +989,7 @@ int lspca_fit_csr(const int64_t *rowptr, const int32_t *colidx, const void *valu
   Workspace &ws = L.st->ws;
   const bool want_g = sigma_x != nullptr;
   CsrPlan pl;
-  LSPCA_TRY(plan_csr(rowptr, colidx, vdt, m, n, nnz, k, want_g, o, ws, pl));
+  LSPCA_TRY(plan_csr(rowptr, colidx, vdt, m, n, nnz, k, kind, want_g, o, ws, pl));
   const size_t fg = ws_bytes<double>((size_t)k * n) + ws_bytes<double>((size_t)k * k);
   const size_t fb = factor_bytes(n, k);
   LSPCA_TRY(ws.ensure(fg + (pl.bytes > fb ? pl.bytes : fb)));
@@ -989,17 +1022,28 @@ int lspca_transform_csr(const int64_t *rowptr, const int32_t *colidx, const void
   Locked L;
   LSPCA_TRY(lock_device(L));
   Workspace &ws = L.st->ws;
-  const bool f32 = vdt == LSPCA_F32;
+  const size_t esz = dtype_size(vdt);
+  const int64_t ldv = csr_ld(k, esz);
+  int64_t nbc = 0;
+  const int nblk = csr_blocks(n, esz, &nbc);
+  const bool try_blocks = r <= kCsrMaxRows;         // one launch per block over all rows
   ws.reset();
-  LSPCA_TRY(ws.ensure(ws_bytes<int>(1) + (f32 ? ws_bytes<float>((size_t)n * k) : 0)));
+  LSPCA_TRY(ws.ensure(ws_bytes<int>(1) + ws_bytes<char>(esz * (size_t)n * ldv) +
+                      (try_blocks ? ws_bytes<int32_t>((size_t)r * (nblk + 1)) : 0)));
   int *flag = ws.take<int>(1);
-  float *V32 = f32 ? ws.take<float>((size_t)n * k) : nullptr;
+  void *Vp = ws.take<char>(esz * (size_t)n * ldv);  // V in the value type, 128-byte rows
+  int32_t *pos = try_blocks ? ws.take<int32_t>((size_t)r * (nblk + 1)) : nullptr;
   PhaseTimer tm;
   tm.begin(o.timing != 0, o.stream);
-  LSPCA_TRY(csr_check(rowptr, colidx, r, n, nnz, flag, o.stream));
-  if (f32) LSPCA_TRY(launch_f64_to_f32(V, (int64_t)n * k, V32, o.stream));
-  LSPCA_TRY(launch_csr_spmm(vdt, rowptr, colidx, values, 0, r, f32 ? (const void *)V32 : (const void *)V, k,
-                            Z, k, o.stream));
+  bool unsorted = true;
+  LSPCA_TRY(csr_check_launch(rowptr, colidx, r, n, nnz, flag, o.stream));
+  if (try_blocks) LSPCA_TRY(launch_row_block_pos(rowptr, colidx, r, nnz, nbc, nblk, pos, flag, o.stream));
+  LSPCA_TRY(csr_check_result(flag, n, nnz, &unsorted, o.stream));
+  LSPCA_TRY(launch_v_padded(V, n, k, vdt, Vp, ldv, o.stream));
+  if (try_blocks && !unsorted)                       // rows with nondecreasing columns: by column blocks
+    LSPCA_TRY(launch_csr_blocked(vdt, rowptr, colidx, values, pos, nblk, r, Vp, ldv, k, Z, k, o.stream));
+  else
+    LSPCA_TRY(launch_csr_spmm(vdt, rowptr, colidx, values, 0, r, Vp, ldv, k, Z, k, o.stream));
   tm.mark(PH_TRANSFORM);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;

@@ -196,43 +196,82 @@ size_t tn_partial_elems(int Mi, int Nj, int splits);
 // device and reports the result (dflag: one device int of scratch).
 int csr_check(const int64_t *rowptr, const int32_t *colidx, int64_t m, int64_t n, int64_t nnz,
               int *dflag, hipStream_t s);
+// The same in two halves (other kernels may be queued between them):
+// launch, then wait and report; *unsorted: some row's columns decrease
+// (set by launch_row_block_pos).
+int csr_check_launch(const int64_t *rowptr, const int32_t *colidx, int64_t m, int64_t n, int64_t nnz,
+                     int *dflag, hipStream_t s);
+int csr_check_result(const int *dflag, int64_t n, int64_t nnz, bool *unsorted, hipStream_t s);
+// Z = X V by column blocks of nbc features (csr_blocks gives nbc and the
+// block count): pos (rows x (nblk + 1) int32) holds each row's block
+// offsets, for rows with nondecreasing columns.
+int csr_blocks(int64_t n, size_t esz, int64_t *nbc);
+int launch_row_block_pos(const int64_t *rowptr, const int32_t *colidx, int64_t rows, int64_t nnz, int64_t nbc,
+                         int nblk, int32_t *pos, int *dflag, hipStream_t s);
+int launch_csr_blocked(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals,
+                       const int32_t *pos, int nblk, int64_t rows, const void *V, int64_t ldv, int k, void *Z,
+                       int64_t ldz, hipStream_t s);
 constexpr int64_t kCsrMaxRows = (int64_t)1 << 24;   // rows per row-parallel launch
-// Y[i * ldy + c] = sum over row r0 + i of v * B[col * k + c], i < rows; B
-// row-major n x k, all of the value type vdt (FP32 or FP64).
+// Y[i * ldy + c] = sum over row r0 + i of v * B[col * ldb + c], i < rows,
+// c < k; B row-major n x k, all of the value type vdt (FP32 or FP64).
 int launch_csr_spmm(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals,
-                    int64_t r0, int64_t rows, const void *B, int k, void *Y, int64_t ldy, hipStream_t s);
+                    int64_t r0, int64_t rows, const void *B, int64_t ldb, int k, void *Y, int64_t ldy,
+                    hipStream_t s);
+// The very sparse Omega (entries -1, 0, +1; materialised n x k row-major,
+// row pitch ldo) as row lists: row j's nonzeros oc[t], t in [optr[j],
+// optr[j + 1]), in column order, each the column with the sign in bit 31
+// (cnt, optr: n + 1 int32, n k < 2^31; oc: room for n k codes; temp of
+// om_scan_bytes). Y = X Omega from those lists (row r0 + i of X to row i
+// of Y).
+size_t om_scan_bytes(int64_t n);
+int build_omega_lists(lspca_dtype vdt, const void *Om, int64_t ldo, int64_t n, int k, int32_t *cnt,
+                      int32_t *optr, int32_t *oc, void *temp, size_t temp_bytes, hipStream_t s);
+int launch_csr_sketch_lists(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals,
+                            int64_t r0, int64_t rows, const int32_t *optr, const int32_t *oc, int k, void *Y,
+                            int64_t ldy, hipStream_t s);
 // rowptr[r0 + g * t] for t = 0 .. nb - 1 (the last clamped to rowptr[r0 +
 // rows]): stripe boundaries of the CSC build.
 int launch_row_bounds(const int64_t *rowptr, int64_t rows, int64_t g, int64_t nb, int64_t *out,
                       hipStream_t s);
-// The CSC form of a stripe of at most kCsrMaxRows rows (entries [e0, e0 +
-// cnt), cnt < 2^31): column j's entries at [colptr[j], colptr[j + 1]), in
-// row order, with the stripe-local row crow[t] and the value cval[t]; and
-// the split of the column sums into segments of at most `seg` entries
-// (csc_segment of the largest stripe, set by the caller; segcnt, segoff:
-// n + 1 int64; segcol: one int per segment; P: k FP64 per segment,
-// csc_segments_max of them).
+// The column-ordered (CSC) form of a stripe of at most kCsrMaxRows rows
+// (entries [e0, e0 + cnt), cnt < 2^31), in row blocks of rb rows: list
+// l = b n + j holds the entries of column j in block b at [colptr[l],
+// colptr[l + 1]), in row order, with the stripe-local row crow[t] and the
+// value cval[t]. The column sums are cut into segments of at most `seg`
+// entries (segoff: L + 1; segcol: one int per segment); lists of two or more
+// segments keep partial rows in P (k FP64 each, from row moff[l] on).
+struct CscShape {
+  int64_t rb = 1, nblocks = 1, lists = 1, seg = 1024, segs_max = 1, partial_rows = 1;
+};
+CscShape csc_shape(int64_t rows, int64_t n, int64_t cnt, int k, size_t esz);
 struct CscBuffers {
   int32_t *keys, *skeys, *rowof, *crow, *segcol;
   uint32_t *idx, *sidx;
   void *cval;
-  int64_t *colptr, *segcnt, *segoff;
+  int64_t *colptr, *cnt, *segoff, *moff;
   double *P;
-  int64_t seg;
   void *temp;
   size_t temp_bytes;
 };
-int64_t csc_segment(int64_t cnt, int k);
-int64_t csc_segments_max(int64_t cnt, int64_t n, int k);
-size_t csc_temp_bytes(int64_t cnt, int64_t n);
+size_t csc_temp_bytes(int64_t cnt, int64_t lists);
 int build_csc(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals, int64_t r0,
-              int64_t rows, int64_t e0, int64_t cnt, int64_t n, int k, CscBuffers &b, hipStream_t s);
-// F[c * n + j] += sum over column j of the stripe of v * Y[row * ldy + c]
-// (FP64 accumulation, Y of the value type).
-int launch_csc_factor(lspca_dtype vdt, const CscBuffers &b, int64_t n, int64_t cnt, const void *Y, int k,
-                      int64_t ldy, double *F, hipStream_t s);
-// B = V (n x k FP64, row-major) rounded to FP32, same layout.
-int launch_f64_to_f32(const double *V, int64_t count, float *out, hipStream_t s);
+              int64_t rows, int64_t e0, int64_t cnt, int64_t n, const CscShape &sh, CscBuffers &b,
+              hipStream_t s);
+// Ft[j * k + c] += sum over column j of the stripe of v * Y[row * ldy + c]
+// (FP64 accumulation, Y of the value type; Ft is n x k).
+int launch_csc_factor(lspca_dtype vdt, const CscBuffers &b, const CscShape &sh, int64_t n, int64_t cnt,
+                      const void *Y, int k, int64_t ldy, double *Ft, hipStream_t s);
+// F[c * n + j] += Ft[j * k + c].
+int launch_add_transposed(const double *Ft, int64_t n, int k, double *F, hipStream_t s);
+// out[j * ldo + c] = V[j][c] (n x k FP64, row-major) in the value type (FP32:
+// rounded to nearest).
+int launch_v_padded(const double *V, int64_t n, int k, lspca_dtype vdt, void *out, int64_t ldo, hipStream_t s);
+// Row pitch (elements) of the library's n x k or m x k row-major buffers for
+// the sparse path: rows start on 128-byte boundaries.
+inline int64_t csr_ld(int k, size_t esz) {
+  const int64_t q = 128 / (int64_t)esz;
+  return (k + q - 1) / q * q;
+}
 
 // Reductions and small FP64 stage (small.hip).
 constexpr int kSmallFlags = 128;   // flag and sweep-counter ints of the small stage

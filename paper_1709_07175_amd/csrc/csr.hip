@@ -49,13 +49,17 @@ __global__ void k_csr_check(const int64_t *__restrict__ rowptr, const int32_t *_
   if (bad) atomicOr(flag, bad);
 }
 
-int csr_check(const int64_t *rowptr, const int32_t *colidx, int64_t m, int64_t n, int64_t nnz,
-              int *dflag, hipStream_t s) {
+int csr_check_launch(const int64_t *rowptr, const int32_t *colidx, int64_t m, int64_t n, int64_t nnz,
+                     int *dflag, hipStream_t s) {
   LSPCA_TRY(zero_i32(dflag, 1, s));
   const int64_t work = (m + 1 > nnz ? m + 1 : nnz);
   const unsigned grid = (unsigned)std::min<int64_t>((work + 255) / 256, 4096);
   hipLaunchKernelGGL(k_csr_check, grid > 0 ? grid : 1, 256, 0, s, rowptr, colidx, m, n, nnz, dflag);
   LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+int csr_check_result(const int *dflag, int64_t n, int64_t nnz, bool *unsorted, hipStream_t s) {
   int h = 0;
   LSPCA_HIP(hipMemcpyAsync(&h, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
   LSPCA_HIP(hipStreamSynchronize(s));
@@ -67,64 +71,144 @@ int csr_check(const int64_t *rowptr, const int32_t *colidx, int64_t m, int64_t n
     set_error("CSR colidx out of [0, n) (n = %lld)", (long long)n);
     return LSPCA_EINVAL;
   }
+  if (unsorted) *unsorted = (h & 4) != 0;
   return LSPCA_OK;
 }
 
-// acc[q] += v[t] * B[idx[t] * ldb + cb + lane + 64 q] for t in [t0, t1), in
-// order of t (ACC: the accumulator type); four entries' loads in flight.
-template <typename T, typename ACC, int KQ>
-__device__ __forceinline__ void gather_acc(const int32_t *__restrict__ idx, const T *__restrict__ v,
-                                           int64_t t0, int64_t t1, const T *__restrict__ B, int64_t ldb,
-                                           int cb, int k, int lane, ACC (&acc)[KQ]) {
-  bool on[KQ];
-#pragma unroll
-  for (int q = 0; q < KQ; ++q) on[q] = cb + lane + 64 * q < k;
-  const T *Bc = B + cb + lane;
-  int64_t t = t0;
-  for (; t + 4 <= t1; t += 4) {
-    int64_t r[4];
-    ACC w[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      r[u] = (int64_t)idx[t + u] * ldb;
-      w[u] = (ACC)v[t + u];
-    }
-    T b[4][KQ];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int q = 0; q < KQ; ++q) b[u][q] = on[q] ? Bc[r[u] + 64 * q] : T(0);
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int q = 0; q < KQ; ++q) acc[q] = fma(w[u], (ACC)b[u][q], acc[q]);
-  }
-  for (; t < t1; ++t) {
-    const int64_t r = (int64_t)idx[t] * ldb;
-    const ACC w = (ACC)v[t];
-#pragma unroll
-    for (int q = 0; q < KQ; ++q)
-      if (on[q]) acc[q] = fma(w, (ACC)Bc[r + 64 * q], acc[q]);
-  }
+int csr_check(const int64_t *rowptr, const int32_t *colidx, int64_t m, int64_t n, int64_t nnz,
+              int *dflag, hipStream_t s) {
+  LSPCA_TRY(csr_check_launch(rowptr, colidx, m, n, nnz, dflag, s));
+  return csr_check_result(dflag, n, nnz, nullptr, s);
 }
 
-// ---- Y[i][c] = sum_e v_e B[col_e][c] for rows r0 + i, i < rows (one wave
-// per row; 64 KQ columns per pass over the row's entries)
-template <typename T, int KQ>
+// sum over t in [t0, t1), in order, of v[t] * B[idx[t] * ldb + c] (coff:
+// this lane's byte offset c * sizeof(T) within a row of B; idx and v are
+// wave-uniform and read through the scalar cache). Groups of sixteen gathers
+// in two buffers: the next group's indices and gathers are issued before the
+// current group's products, so sixteen to thirty-two gathers stay in flight.
+template <typename T, typename ACC>
+__device__ __forceinline__ ACC gather_dot(const int32_t *__restrict__ idx, const T *__restrict__ v,
+                                          int64_t t0, int64_t t1, const T *__restrict__ B, int64_t ldb,
+                                          uint32_t coff) {
+  ACC acc = ACC(0);
+  int64_t t = t0;
+  if (t + 16 <= t1) {
+    T va[16], ya[16], vb[16], yb[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      va[u] = v[t + u];
+      ya[u] = *(const T *)((const char *)(B + (int64_t)idx[t + u] * ldb) + coff);
+    }
+    for (;;) {
+      const bool more = t + 32 <= t1;
+      if (more) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          vb[u] = v[t + 16 + u];
+          yb[u] = *(const T *)((const char *)(B + (int64_t)idx[t + 16 + u] * ldb) + coff);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc = fma((ACC)va[u], (ACC)ya[u], acc);
+      t += 16;
+      if (!more) break;
+      const bool more2 = t + 32 <= t1;
+      if (more2) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          va[u] = v[t + 16 + u];
+          ya[u] = *(const T *)((const char *)(B + (int64_t)idx[t + 16 + u] * ldb) + coff);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc = fma((ACC)vb[u], (ACC)yb[u], acc);
+      t += 16;
+      if (!more2) break;
+    }
+  }
+  for (; t < t1; ++t)
+    acc = fma((ACC)v[t], (ACC) * (const T *)((const char *)(B + (int64_t)idx[t] * ldb) + coff), acc);
+  return acc;
+}
+
+// ---- Y[i][c] = sum_e v_e B[col_e][c] for rows r0 + i, i < rows: one wave
+// per row, lanes over 64 KQ columns per pass over the row's entries (taken
+// in storage order). The entries' columns and values are wave-uniform
+// (scalar loads); groups of GE entries (KQ gathers each) go in two buffers,
+// the next group issued before the current group's products. Lanes past k
+// gather column 0 and drop the result.
+template <typename T, int KQ, int GE>
 __global__ __launch_bounds__(256) void k_csr_spmm(const int64_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ colidx,
                                                   const T *__restrict__ vals, int64_t r0, int64_t rows,
-                                                  const T *__restrict__ B, int k, T *__restrict__ Y,
-                                                  int64_t ldy) {
+                                                  const T *__restrict__ B, int64_t ldb, int k,
+                                                  T *__restrict__ Y, int64_t ldy) {
   const int lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t i = (int64_t)blockIdx.x * 4 + wv;
   if (i >= rows) return;
   const int64_t e0 = rowptr[r0 + i], e1 = rowptr[r0 + i + 1];
   for (int cb = 0; cb < k; cb += 64 * KQ) {
+    uint32_t off[KQ];                               // byte offsets (the base is wave-uniform)
+#pragma unroll
+    for (int q = 0; q < KQ; ++q) {
+      const int c = cb + lane + 64 * q;
+      off[q] = (c < k ? (uint32_t)c : 0u) * (uint32_t)sizeof(T);
+    }
     T acc[KQ];
 #pragma unroll
     for (int q = 0; q < KQ; ++q) acc[q] = T(0);
-    gather_acc<T, T, KQ>(colidx, vals, e0, e1, B, k, cb, k, lane, acc);
+    int64_t e = e0;
+    if (e + GE <= e1) {
+      T va[GE], vb[GE], ya[GE][KQ], yb[GE][KQ];
+#pragma unroll
+      for (int u = 0; u < GE; ++u) {
+        const T *Bj = B + (int64_t)colidx[e + u] * ldb;
+        va[u] = vals[e + u];
+#pragma unroll
+        for (int q = 0; q < KQ; ++q) ya[u][q] = *(const T *)((const char *)Bj + off[q]);
+      }
+      for (;;) {
+        const bool more = e + 2 * GE <= e1;
+        if (more) {
+#pragma unroll
+          for (int u = 0; u < GE; ++u) {
+            const T *Bj = B + (int64_t)colidx[e + GE + u] * ldb;
+            vb[u] = vals[e + GE + u];
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) yb[u][q] = *(const T *)((const char *)Bj + off[q]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < GE; ++u)
+#pragma unroll
+          for (int q = 0; q < KQ; ++q) acc[q] = fma(va[u], ya[u][q], acc[q]);
+        e += GE;
+        if (!more) break;
+        const bool more2 = e + 2 * GE <= e1;
+        if (more2) {
+#pragma unroll
+          for (int u = 0; u < GE; ++u) {
+            const T *Bj = B + (int64_t)colidx[e + GE + u] * ldb;
+            va[u] = vals[e + GE + u];
+#pragma unroll
+            for (int q = 0; q < KQ; ++q) ya[u][q] = *(const T *)((const char *)Bj + off[q]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < GE; ++u)
+#pragma unroll
+          for (int q = 0; q < KQ; ++q) acc[q] = fma(vb[u], yb[u][q], acc[q]);
+        e += GE;
+        if (!more2) break;
+      }
+    }
+    for (; e < e1; ++e) {
+      const T *Bj = B + (int64_t)colidx[e] * ldb;
+      const T v = vals[e];
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) acc[q] = fma(v, *(const T *)((const char *)Bj + off[q]), acc[q]);
+    }
 #pragma unroll
     for (int q = 0; q < KQ; ++q) {
       const int c = cb + lane + 64 * q;
@@ -133,8 +217,23 @@ __global__ __launch_bounds__(256) void k_csr_spmm(const int64_t *__restrict__ ro
   }
 }
 
+template <typename T>
+static void spmm_kq(const int64_t *rowptr, const int32_t *colidx, const T *vals, int64_t r0, int64_t rows,
+                    const T *B, int64_t ldb, int k, T *Y, int64_t ldy, unsigned grid, hipStream_t s) {
+  constexpr int G8 = sizeof(T) == 8 ? 2 : 4;
+  if (k <= 64)
+    hipLaunchKernelGGL((k_csr_spmm<T, 1, 8>), grid, 256, 0, s, rowptr, colidx, vals, r0, rows, B, ldb, k, Y, ldy);
+  else if (k <= 128)
+    hipLaunchKernelGGL((k_csr_spmm<T, 2, 8>), grid, 256, 0, s, rowptr, colidx, vals, r0, rows, B, ldb, k, Y, ldy);
+  else if (k <= 256)
+    hipLaunchKernelGGL((k_csr_spmm<T, 4, 4>), grid, 256, 0, s, rowptr, colidx, vals, r0, rows, B, ldb, k, Y, ldy);
+  else
+    hipLaunchKernelGGL((k_csr_spmm<T, 8, G8>), grid, 256, 0, s, rowptr, colidx, vals, r0, rows, B, ldb, k, Y, ldy);
+}
+
 int launch_csr_spmm(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals,
-                    int64_t r0, int64_t rows, const void *B, int k, void *Y, int64_t ldy, hipStream_t s) {
+                    int64_t r0, int64_t rows, const void *B, int64_t ldb, int k, void *Y, int64_t ldy,
+                    hipStream_t s) {
   if (vdt != LSPCA_F32 && vdt != LSPCA_F64) {
     set_error("CSR values must be FP32 or FP64 (dtype %d)", (int)vdt);
     return LSPCA_ENOTSUP;
@@ -144,43 +243,153 @@ int launch_csr_spmm(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colid
     const int64_t cr = rows - c0 < kCsrMaxRows ? rows - c0 : kCsrMaxRows;
     const unsigned grid = (unsigned)((cr + 3) / 4);
     void *Yc = (char *)Y + (size_t)c0 * ldy * es;
-    if (vdt == LSPCA_F32) {
-      if (k <= 64)
-        hipLaunchKernelGGL((k_csr_spmm<float, 1>), grid, 256, 0, s, rowptr, colidx, (const float *)vals,
-                           r0 + c0, cr, (const float *)B, k, (float *)Yc, ldy);
-      else if (k <= 128)
-        hipLaunchKernelGGL((k_csr_spmm<float, 2>), grid, 256, 0, s, rowptr, colidx, (const float *)vals,
-                           r0 + c0, cr, (const float *)B, k, (float *)Yc, ldy);
-      else
-        hipLaunchKernelGGL((k_csr_spmm<float, 4>), grid, 256, 0, s, rowptr, colidx, (const float *)vals,
-                           r0 + c0, cr, (const float *)B, k, (float *)Yc, ldy);
-    } else {
-      if (k <= 64)
-        hipLaunchKernelGGL((k_csr_spmm<double, 1>), grid, 256, 0, s, rowptr, colidx, (const double *)vals,
-                           r0 + c0, cr, (const double *)B, k, (double *)Yc, ldy);
-      else if (k <= 128)
-        hipLaunchKernelGGL((k_csr_spmm<double, 2>), grid, 256, 0, s, rowptr, colidx, (const double *)vals,
-                           r0 + c0, cr, (const double *)B, k, (double *)Yc, ldy);
-      else
-        hipLaunchKernelGGL((k_csr_spmm<double, 4>), grid, 256, 0, s, rowptr, colidx, (const double *)vals,
-                           r0 + c0, cr, (const double *)B, k, (double *)Yc, ldy);
-    }
+    if (vdt == LSPCA_F32)
+      spmm_kq<float>(rowptr, colidx, (const float *)vals, r0 + c0, cr, (const float *)B, ldb, k, (float *)Yc,
+                     ldy, grid, s);
+    else
+      spmm_kq<double>(rowptr, colidx, (const double *)vals, r0 + c0, cr, (const double *)B, ldb, k,
+                      (double *)Yc, ldy, grid, s);
     LSPCA_HIP(hipGetLastError());
   }
   return LSPCA_OK;
 }
 
-// ---- CSC of the stripe of rows [r0, r0 + rows), entries [e0, e1)
-// one wave per row, lanes over its entries
+// ---- the very sparse Omega (entries -1, 0, +1) as row lists: row j's
+// nonzeros are oc[t] for t in [optr[j], optr[j + 1]), in column order, each
+// the column with the entry's sign in bit 31. Built from the materialised
+// Omega (n x k, row-major, row pitch ldo); one wave per row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_om_count(const T *__restrict__ Om, int64_t ldo, int64_t n, int k,
+                                                  int32_t *__restrict__ cnt) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j > n) return;
+  int c_nz = 0;
+  if (j < n)
+    for (int cb = 0; cb < k; cb += 64) {
+      const int c = cb + lane;
+      c_nz += __popcll(__ballot(c < k && Om[j * ldo + c] != T(0)));
+    }
+  if (lane == 0) cnt[j] = c_nz;                   // cnt[n] = 0 closes the scan
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_om_fill(const T *__restrict__ Om, int64_t ldo, int64_t n, int k,
+                                                 const int32_t *__restrict__ optr, int32_t *__restrict__ oc) {
+  const int lane = threadIdx.x & 63;
+  const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  int32_t base = optr[j];
+  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int cb = 0; cb < k; cb += 64) {
+    const int c = cb + lane;
+    const T v = c < k ? Om[j * ldo + c] : T(0);
+    const uint64_t mask = __ballot(v != T(0));
+    if (v != T(0)) oc[base + __popcll(mask & below)] = v < T(0) ? (int32_t)((uint32_t)c | 0x80000000u) : c;
+    base += __popcll(mask);
+  }
+}
+
+size_t om_scan_bytes(int64_t n) {
+  size_t scan = 0;
+  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (const int32_t *)nullptr, (int32_t *)nullptr,
+                                         (int)(n + 1));
+  return scan;
+}
+
+int build_omega_lists(lspca_dtype vdt, const void *Om, int64_t ldo, int64_t n, int k, int32_t *cnt,
+                      int32_t *optr, int32_t *oc, void *temp, size_t temp_bytes, hipStream_t s) {
+  const unsigned g = (unsigned)((n + 1 + 3) / 4);
+  if (vdt == LSPCA_F32)
+    hipLaunchKernelGGL(k_om_count<float>, g, 256, 0, s, (const float *)Om, ldo, n, k, cnt);
+  else
+    hipLaunchKernelGGL(k_om_count<double>, g, 256, 0, s, (const double *)Om, ldo, n, k, cnt);
+  LSPCA_HIP(hipGetLastError());
+  size_t tb = temp_bytes;
+  LSPCA_HIP(hipcub::DeviceScan::ExclusiveSum(temp, tb, cnt, optr, (int)(n + 1), s));
+  if (vdt == LSPCA_F32)
+    hipLaunchKernelGGL(k_om_fill<float>, g, 256, 0, s, (const float *)Om, ldo, n, k, optr, oc);
+  else
+    hipLaunchKernelGGL(k_om_fill<double>, g, 256, 0, s, (const double *)Om, ldo, n, k, optr, oc);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+// ---- Y = X Omega with Omega as row lists (very sparse kind): one wave per
+// row, the row of Y accumulated in LDS. Lanes take 64 entries of the row at
+// a time and add +-v for each listed column of their entry with LDS
+// atomics, four list codes loaded at once; one wave owns the row, so the
+// order of the adds is fixed by the instruction stream and the result is
+// reproducible.
+template <typename T>
+__global__ void k_csr_sketch_lists(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
+                                   const T *__restrict__ vals, int64_t r0, int64_t rows,
+                                   const int32_t *__restrict__ optr, const int32_t *__restrict__ oc, int k,
+                                   T *__restrict__ Y, int64_t ldy) {
+  extern __shared__ unsigned char smem[];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  T *yl = (T *)smem + (size_t)wv * k;
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  if (i >= rows) return;
+  for (int c = lane; c < k; c += 64) yl[c] = T(0);
+  const int64_t e0 = rowptr[r0 + i], e1 = rowptr[r0 + i + 1];
+  for (int64_t eb = e0; eb < e1; eb += 64) {
+    const int64_t e = eb + lane;
+    if (e < e1) {
+      const int64_t j = colidx[e];
+      const T v = vals[e];
+      const int32_t a = optr[j], b = optr[j + 1];
+      for (int32_t t = a; t < b; t += 4) {
+        int32_t cd[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cd[u] = oc[t + u < b ? t + u : b - 1];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (t + u < b) atomicAdd(&yl[cd[u] & 0x7fffffff], cd[u] < 0 ? -v : v);
+      }
+    }
+  }
+  for (int c = lane; c < k; c += 64) Y[i * ldy + c] = yl[c];
+}
+
+int launch_csr_sketch_lists(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals,
+                            int64_t r0, int64_t rows, const int32_t *optr, const int32_t *oc, int k, void *Y,
+                            int64_t ldy, hipStream_t s) {
+  const size_t es = dtype_size(vdt);
+  int waves = (int)std::min<int64_t>(4, 65536 / ((int64_t)k * es));
+  waves = waves < 1 ? 1 : waves;
+  const size_t lds = (size_t)waves * k * es;
+  for (int64_t c0 = 0; c0 < rows; c0 += kCsrMaxRows) {
+    const int64_t cr = rows - c0 < kCsrMaxRows ? rows - c0 : kCsrMaxRows;
+    const unsigned grid = (unsigned)((cr + waves - 1) / waves);
+    void *Yc = (char *)Y + (size_t)c0 * ldy * es;
+    if (vdt == LSPCA_F32)
+      hipLaunchKernelGGL(k_csr_sketch_lists<float>, grid, 64 * waves, lds, s, rowptr, colidx,
+                         (const float *)vals, r0 + c0, cr, optr, oc, k, (float *)Yc, ldy);
+    else
+      hipLaunchKernelGGL(k_csr_sketch_lists<double>, grid, 64 * waves, lds, s, rowptr, colidx,
+                         (const double *)vals, r0 + c0, cr, optr, oc, k, (double *)Yc, ldy);
+    LSPCA_HIP(hipGetLastError());
+  }
+  return LSPCA_OK;
+}
+
+// ---- column-ordered form of a stripe of rows [r0, r0 + rows), entries
+// [e0, e0 + cnt), in row blocks: list l = b * n + j holds the entries of
+// column j in rows [b * rb, (b + 1) * rb) of the stripe, in row order. One
+// wave per row, lanes over its entries.
 __global__ __launch_bounds__(256) void k_csr_expand(const int64_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ colidx, int64_t r0,
-                                                    int64_t rows, int64_t e0, int32_t *__restrict__ keys,
-                                                    uint32_t *__restrict__ idx, int32_t *__restrict__ rowof) {
+                                                    int64_t rows, int64_t e0, int64_t n, int64_t rb,
+                                                    int32_t *__restrict__ keys, uint32_t *__restrict__ idx,
+                                                    int32_t *__restrict__ rowof) {
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   if (i >= rows) return;
   const int64_t a = rowptr[r0 + i], b = rowptr[r0 + i + 1];
+  const int64_t kb = (i / rb) * n;
   for (int64_t e = a + (threadIdx.x & 63); e < b; e += 64) {
-    keys[e - e0] = colidx[e];
+    keys[e - e0] = (int32_t)(kb + colidx[e]);
     idx[e - e0] = (uint32_t)(e - e0);
     rowof[e - e0] = (int32_t)i;
   }
@@ -201,16 +410,21 @@ int launch_row_bounds(const int64_t *rowptr, int64_t rows, int64_t g, int64_t nb
   return LSPCA_OK;
 }
 
-__global__ void k_f64_to_f32(const double *__restrict__ v, int64_t count, float *__restrict__ out) {
+// out[j * ldo + c] = V[j * k + c] in the value type (n x k FP64 in)
+template <typename T>
+__global__ void k_v_padded(const double *__restrict__ V, int64_t n, int k, T *__restrict__ out, int64_t ldo) {
+  const int64_t count = n * k;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < count; t += stride)
-    out[t] = (float)v[t];
+    out[(t / k) * ldo + t % k] = (T)V[t];
 }
 
-int launch_f64_to_f32(const double *V, int64_t count, float *out, hipStream_t s) {
-  if (count <= 0) return LSPCA_OK;
-  const unsigned grid = (unsigned)std::min<int64_t>((count + 255) / 256, 65536);
-  hipLaunchKernelGGL(k_f64_to_f32, grid, 256, 0, s, V, count, out);
+int launch_v_padded(const double *V, int64_t n, int k, lspca_dtype vdt, void *out, int64_t ldo, hipStream_t s) {
+  const unsigned grid = (unsigned)std::min<int64_t>((n * k + 255) / 256, 65536);
+  if (vdt == LSPCA_F32)
+    hipLaunchKernelGGL(k_v_padded<float>, grid, 256, 0, s, V, n, k, (float *)out, ldo);
+  else
+    hipLaunchKernelGGL(k_v_padded<double>, grid, 256, 0, s, V, n, k, (double *)out, ldo);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }
@@ -226,17 +440,17 @@ __global__ void k_csc_gather(const uint32_t *__restrict__ idx, const int32_t *__
   cval[t] = vals[e0 + e];
 }
 
-// colptr[j] = first position of a key >= j in the sorted keys (j <= n)
-__global__ void k_colptr(const int32_t *__restrict__ skeys, int64_t cnt, int64_t n, int64_t *__restrict__ colptr) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j > n) return;
+// colptr[l] = first position of a key >= l in the sorted keys (l <= L)
+__global__ void k_colptr(const int32_t *__restrict__ skeys, int64_t cnt, int64_t L, int64_t *__restrict__ colptr) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l > L) return;
   int64_t lo = 0, hi = cnt;
   while (lo < hi) {
     const int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)skeys[mid] < j) lo = mid + 1;
+    if ((int64_t)skeys[mid] < l) lo = mid + 1;
     else hi = mid;
   }
-  colptr[j] = lo;
+  colptr[l] = lo;
 }
 
 static int key_bits(int64_t n) {
@@ -245,50 +459,75 @@ static int key_bits(int64_t n) {
   return b;
 }
 
-// Work split of the column sums: segments of at most S entries; column j
-// owns the segments [segoff[j], segoff[j + 1]), segcol maps a segment to its
-// column.
-__global__ void k_seg_count(const int64_t *__restrict__ colptr, int64_t n, int64_t S,
+// Work split of the column sums: list l is cut into segments of at most S
+// entries, [segoff[l], segoff[l + 1]) (segcol maps a segment to its list).
+// Lists of two or more segments leave one partial row per segment in P,
+// from slot moff[l] on.
+__global__ void k_seg_count(const int64_t *__restrict__ colptr, int64_t L, int64_t S,
                             int64_t *__restrict__ segcnt) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < n) segcnt[j] = (colptr[j + 1] - colptr[j] + S - 1) / S;
-  else if (j == n) segcnt[n] = 0;
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < L) segcnt[l] = (colptr[l + 1] - colptr[l] + S - 1) / S;
+  else if (l == L) segcnt[L] = 0;
 }
 
-__global__ void k_seg_fill(const int64_t *__restrict__ segoff, int64_t n, int32_t *__restrict__ segcol) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
-  for (int64_t w = segoff[j]; w < segoff[j + 1]; ++w) segcol[w] = (int32_t)j;
+__global__ void k_multi_count(const int64_t *__restrict__ segoff, int64_t L, int64_t *__restrict__ mcnt) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l < L) {
+    const int64_t ns = segoff[l + 1] - segoff[l];
+    mcnt[l] = ns > 1 ? ns : 0;
+  } else if (l == L) {
+    mcnt[L] = 0;
+  }
 }
 
-int64_t csc_segment(int64_t cnt, int k) {
-  int64_t S = (cnt * (int64_t)k * 8 + ((int64_t)1 << 31) - 1) >> 31;  // partials <= 2 GiB + n k
-  return S < 256 ? 256 : S;
+__global__ void k_seg_fill(const int64_t *__restrict__ segoff, int64_t L, int32_t *__restrict__ segcol) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= L) return;
+  for (int64_t w = segoff[l]; w < segoff[l + 1]; ++w) segcol[w] = (int32_t)l;
 }
 
-int64_t csc_segments_max(int64_t cnt, int64_t n, int k) {
-  return n + (cnt + csc_segment(cnt, k) - 1) / csc_segment(cnt, k);
+CscShape csc_shape(int64_t rows, int64_t n, int64_t cnt, int k, size_t esz) {
+  CscShape c;
+  // rows per block: one 64-column slice of the block's sketch rows in 2 MiB
+  // (half an XCD's L2); the lists (blocks x n) stay below 2^26
+  const int64_t rb_l2 = (int64_t)(2 << 20) / (64 * (int64_t)esz);
+  int64_t nb = (rows + rb_l2 - 1) / rb_l2;
+  const int64_t nb_max = std::max<int64_t>(1, ((int64_t)1 << 26) / n);
+  nb = std::max<int64_t>(1, std::min(nb, nb_max));
+  c.rb = (rows + nb - 1) / nb;
+  c.rb = c.rb < 1 ? 1 : c.rb;
+  c.nblocks = (rows + c.rb - 1) / c.rb;
+  c.lists = c.nblocks * n;
+  // segment length: partial rows of multi-segment lists (<= 2 cnt / S of
+  // them) within 2 GiB
+  int64_t S = (cnt * (int64_t)k * 16 + ((int64_t)1 << 31) - 1) >> 31;
+  c.seg = S < 1024 ? 1024 : S;
+  c.segs_max = c.lists + (cnt + c.seg - 1) / c.seg;
+  c.partial_rows = 2 * ((cnt + c.seg - 1) / c.seg) + 1;
+  return c;
 }
 
-size_t csc_temp_bytes(int64_t cnt, int64_t n) {
+size_t csc_temp_bytes(int64_t cnt, int64_t lists) {
   size_t sort = 0, scan = 0;
   (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort, (const int32_t *)nullptr, (int32_t *)nullptr,
                                            (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)cnt, 0,
-                                           key_bits(n));
+                                           key_bits(lists));
   (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (const int64_t *)nullptr, (int64_t *)nullptr,
-                                         (int)(n + 1));
+                                         (int)(lists + 1));
   return sort > scan ? sort : scan;
 }
 
 int build_csc(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals, int64_t r0,
-              int64_t rows, int64_t e0, int64_t cnt, int64_t n, int k, CscBuffers &b, hipStream_t s) {
+              int64_t rows, int64_t e0, int64_t cnt, int64_t n, const CscShape &sh, CscBuffers &b,
+              hipStream_t s) {
+  const int64_t L = sh.lists;
   if (cnt > 0) {
-    hipLaunchKernelGGL(k_csr_expand, (unsigned)((rows + 3) / 4), 256, 0, s, rowptr, colidx, r0, rows, e0,
-                       b.keys, b.idx, b.rowof);
+    hipLaunchKernelGGL(k_csr_expand, (unsigned)((rows + 3) / 4), 256, 0, s, rowptr, colidx, r0, rows, e0, n,
+                       sh.rb, b.keys, b.idx, b.rowof);
     LSPCA_HIP(hipGetLastError());
     size_t tb = b.temp_bytes;
     LSPCA_HIP(hipcub::DeviceRadixSort::SortPairs(b.temp, tb, b.keys, b.skeys, b.idx, b.sidx, (int)cnt, 0,
-                                                 key_bits(n), s));
+                                                 key_bits(L), s));
     const unsigned g = (unsigned)((cnt + 255) / 256);
     if (vdt == LSPCA_F32)
       hipLaunchKernelGGL(k_csc_gather<float>, g, 256, 0, s, b.sidx, b.rowof, (const float *)vals, e0, cnt,
@@ -298,92 +537,217 @@ int build_csc(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, con
                          b.crow, (double *)b.cval);
     LSPCA_HIP(hipGetLastError());
   }
-  const unsigned gn = (unsigned)((n + 1 + 255) / 256);
-  hipLaunchKernelGGL(k_colptr, gn, 256, 0, s, b.skeys, cnt, n, b.colptr);
+  const unsigned gl = (unsigned)((L + 1 + 255) / 256);
+  hipLaunchKernelGGL(k_colptr, gl, 256, 0, s, b.skeys, cnt, L, b.colptr);
   LSPCA_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_seg_count, gn, 256, 0, s, b.colptr, n, b.seg, b.segcnt);
+  hipLaunchKernelGGL(k_seg_count, gl, 256, 0, s, b.colptr, L, sh.seg, b.cnt);
   LSPCA_HIP(hipGetLastError());
   size_t tb = b.temp_bytes;
-  LSPCA_HIP(hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.segcnt, b.segoff, (int)(n + 1), s));
-  hipLaunchKernelGGL(k_seg_fill, (unsigned)((n + 255) / 256), 256, 0, s, b.segoff, n, b.segcol);
+  LSPCA_HIP(hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.cnt, b.segoff, (int)(L + 1), s));
+  hipLaunchKernelGGL(k_multi_count, gl, 256, 0, s, b.segoff, L, b.cnt);
+  LSPCA_HIP(hipGetLastError());
+  tb = b.temp_bytes;
+  LSPCA_HIP(hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.cnt, b.moff, (int)(L + 1), s));
+  hipLaunchKernelGGL(k_seg_fill, (unsigned)((L + 255) / 256), 256, 0, s, b.segoff, L, b.segcol);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }
 
-// ---- column sums F[c][j] += sum over column j of cval[t] * Y[crow[t]][c]
-// (FP64). One wave per segment (grid-stride; the segment count is read on
-// the device), lanes over c. A column of one segment adds into F directly;
-// longer columns leave one partial row per segment in P, summed in segment
-// order by k_seg_reduce.
-template <typename T, int KQ>
-__global__ __launch_bounds__(256) void k_csc_factor(const int64_t *__restrict__ colptr,
-                                                    const int64_t *__restrict__ segoff,
-                                                    const int32_t *__restrict__ segcol,
-                                                    const int32_t *__restrict__ crow,
-                                                    const T *__restrict__ cval, int64_t n, int64_t S,
-                                                    const T *__restrict__ Y, int k, int64_t ldy,
-                                                    double *__restrict__ F, double *__restrict__ P) {
+// ---- column sums of one row block b: Ft[j][c] += sum over list b n + j of
+// cval[t] * Y[crow[t]][c] (FP64). Workgroup g takes the 64-column slice
+// g mod nslices (with 8 slices, consecutive workgroups land on the 8 XCDs
+// in turn, so each XCD's L2 holds one slice of the block's sketch rows);
+// its waves take the block's segments in turn (their range is read on the
+// device), lanes over the slice's columns. Lists of one segment add into
+// Ft directly; the others write partial rows, added by k_block_reduce in
+// segment order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_csc_block(const int64_t *__restrict__ colptr,
+                                                   const int64_t *__restrict__ segoff,
+                                                   const int32_t *__restrict__ segcol,
+                                                   const int64_t *__restrict__ moff,
+                                                   const int32_t *__restrict__ crow,
+                                                   const T *__restrict__ cval, int64_t lbase, int64_t n,
+                                                   int64_t S, int nslices, const T *__restrict__ Y, int k,
+                                                   int64_t ldy, double *__restrict__ Ft,
+                                                   double *__restrict__ P) {
   const int lane = threadIdx.x & 63;
-  const int64_t nseg_all = segoff[n];
-  for (int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < nseg_all; w += (int64_t)gridDim.x * 4) {
-    const int64_t j = segcol[w];
-    const int64_t first = segoff[j], nseg = segoff[j + 1] - first;
-    const int64_t t0 = colptr[j] + (w - first) * S;
-    const int64_t t1 = t0 + S < colptr[j + 1] ? t0 + S : colptr[j + 1];
-    for (int cb = 0; cb < k; cb += 64 * KQ) {
-      double acc[KQ];
-#pragma unroll
-      for (int q = 0; q < KQ; ++q) acc[q] = 0.0;
-      gather_acc<T, double, KQ>(crow, cval, t0, t1, Y, ldy, cb, k, lane, acc);
-#pragma unroll
-      for (int q = 0; q < KQ; ++q) {
-        const int c = cb + lane + 64 * q;
-        if (c >= k) continue;
-        if (nseg == 1) F[(int64_t)c * n + j] += acc[q];
-        else P[w * k + c] = acc[q];
-      }
+  // the wave index in a scalar register: every list quantity below is
+  // wave-uniform and read through the scalar cache
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int slice = (int)(blockIdx.x % (unsigned)nslices);
+  const int c = slice * 64 + lane;
+  const bool on = c < k;
+  const uint32_t coff = (on ? (uint32_t)c : 0u) * (uint32_t)sizeof(T);  // byte offset from a row start
+  const int64_t wbeg = segoff[lbase], wend = segoff[lbase + n];
+  const int64_t groups = gridDim.x / (unsigned)nslices;
+  for (int64_t w = wbeg + (int64_t)(blockIdx.x / (unsigned)nslices) * 4 + wv; w < wend; w += groups * 4) {
+    const int64_t l = segcol[w];
+    const int64_t first = segoff[l], nseg = segoff[l + 1] - first;
+    const int64_t t0 = colptr[l] + (w - first) * S;
+    const int64_t t1 = t0 + S < colptr[l + 1] ? t0 + S : colptr[l + 1];
+    const double acc = gather_dot<T, double>(crow, cval, t0, t1, Y, ldy, coff);
+    if (on) {
+      const int64_t j = l - lbase;
+      if (nseg == 1) Ft[j * k + c] += acc;
+      else P[(moff[l] + (w - first)) * k + c] = acc;
     }
   }
 }
 
-__global__ __launch_bounds__(256) void k_seg_reduce(const int64_t *__restrict__ segoff, int64_t n,
-                                                    const double *__restrict__ P, int k,
-                                                    double *__restrict__ F) {
+__global__ __launch_bounds__(256) void k_block_reduce(const int64_t *__restrict__ segoff,
+                                                      const int64_t *__restrict__ moff, int64_t lbase,
+                                                      int64_t n, const double *__restrict__ P, int k,
+                                                      double *__restrict__ Ft) {
   const int lane = threadIdx.x & 63;
   for (int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); j < n; j += (int64_t)gridDim.x * 4) {
-    const int64_t w0 = segoff[j], w1 = segoff[j + 1];
-    if (w1 - w0 < 2) continue;
+    const int64_t l = lbase + j;
+    const int64_t nseg = segoff[l + 1] - segoff[l];
+    if (nseg < 2) continue;
+    const double *Pl = P + moff[l] * k;
     for (int c = lane; c < k; c += 64) {
-      double sum = P[w0 * k + c];
-      for (int64_t w = w0 + 1; w < w1; ++w) sum += P[w * k + c];
-      F[(int64_t)c * n + j] += sum;
+      double sum = Pl[c];
+      for (int64_t q = 1; q < nseg; ++q) sum += Pl[q * k + c];
+      Ft[j * k + c] += sum;
     }
   }
 }
 
-template <typename T>
-static void factor_kq(const CscBuffers &b, int64_t n, const T *Y, int k, int64_t ldy, double *F,
-                      unsigned grid, hipStream_t s) {
-  if (k <= 64)
-    hipLaunchKernelGGL((k_csc_factor<T, 1>), grid, 256, 0, s, b.colptr, b.segoff, b.segcol, b.crow,
-                       (const T *)b.cval, n, b.seg, Y, k, ldy, F, b.P);
-  else if (k <= 128)
-    hipLaunchKernelGGL((k_csc_factor<T, 2>), grid, 256, 0, s, b.colptr, b.segoff, b.segcol, b.crow,
-                       (const T *)b.cval, n, b.seg, Y, k, ldy, F, b.P);
-  else
-    hipLaunchKernelGGL((k_csc_factor<T, 4>), grid, 256, 0, s, b.colptr, b.segoff, b.segcol, b.crow,
-                       (const T *)b.cval, n, b.seg, Y, k, ldy, F, b.P);
+int launch_csc_factor(lspca_dtype vdt, const CscBuffers &b, const CscShape &sh, int64_t n, int64_t cnt,
+                      const void *Y, int k, int64_t ldy, double *Ft, hipStream_t s) {
+  const int nslices = (k + 63) / 64;
+  const int64_t per_block = n + (cnt + sh.seg - 1) / sh.seg;            // segments of one block, at most
+  const int64_t groups = std::max<int64_t>(1, std::min<int64_t>((per_block + 3) / 4, 65536 / nslices));
+  const unsigned grid = (unsigned)(groups * nslices);
+  const unsigned gr = (unsigned)std::min<int64_t>((n + 3) / 4, 1 << 16);
+  for (int64_t bk = 0; bk < sh.nblocks; ++bk) {
+    const int64_t lbase = bk * n;
+    if (vdt == LSPCA_F32)
+      hipLaunchKernelGGL(k_csc_block<float>, grid, 256, 0, s, b.colptr, b.segoff, b.segcol, b.moff, b.crow,
+                         (const float *)b.cval, lbase, n, sh.seg, nslices, (const float *)Y, k, ldy, Ft, b.P);
+    else
+      hipLaunchKernelGGL(k_csc_block<double>, grid, 256, 0, s, b.colptr, b.segoff, b.segcol, b.moff, b.crow,
+                         (const double *)b.cval, lbase, n, sh.seg, nslices, (const double *)Y, k, ldy, Ft, b.P);
+    LSPCA_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_block_reduce, gr, 256, 0, s, b.segoff, b.moff, lbase, n, b.P, k, Ft);
+    LSPCA_HIP(hipGetLastError());
+  }
+  return LSPCA_OK;
 }
 
-int launch_csc_factor(lspca_dtype vdt, const CscBuffers &b, int64_t n, int64_t cnt, const void *Y, int k,
-                      int64_t ldy, double *F, hipStream_t s) {
-  const int64_t segs = n + (cnt + b.seg - 1) / b.seg;
-  const unsigned grid = (unsigned)std::min<int64_t>((segs + 3) / 4, 1 << 20);
-  if (vdt == LSPCA_F32) factor_kq<float>(b, n, (const float *)Y, k, ldy, F, grid, s);
-  else factor_kq<double>(b, n, (const double *)Y, k, ldy, F, grid, s);
+// ---- Z = X V by column blocks (rows with nondecreasing columns): block b
+// holds the features [b nbc, (b + 1) nbc); pos[i][b] is the offset in row i
+// of its first entry in block b. One wave per row: lanes take the block
+// boundaries (lower bounds in the row's columns); the wave also flags a row
+// whose columns decrease (bit 2 of flag). Reads stay in [0, nnz) whatever
+// rowptr holds, so this may run before the check's result is known.
+__global__ __launch_bounds__(256) void k_row_block_pos(const int64_t *__restrict__ rowptr,
+                                                       const int32_t *__restrict__ colidx, int64_t rows,
+                                                       int64_t nnz, int64_t nbc, int nblk,
+                                                       int32_t *__restrict__ pos, int *flag) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= rows) return;
+  int64_t a = rowptr[i], b = rowptr[i + 1];
+  a = a < 0 ? 0 : (a > nnz ? nnz : a);
+  b = b < a ? a : (b > nnz ? nnz : b);
+  bool bad = false;
+  for (int64_t e = a + lane; e + 1 < b; e += 64) bad |= colidx[e] > colidx[e + 1];
+  if (__ballot(bad) != 0ull && lane == 0) atomicOr(flag, 4);
+  for (int bk = lane; bk <= nblk; bk += 64) {
+    const int64_t key = (int64_t)bk * nbc;
+    int64_t lo = a, hi = b;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)colidx[mid] < key) lo = mid + 1;
+      else hi = mid;
+    }
+    pos[i * (nblk + 1) + bk] = (int32_t)(lo - a);
+  }
+}
+
+// Block b of Z = X V: workgroup g takes the 64-column slice g mod nslices
+// (the XCD's L2 holds that slice of the block's rows of V), its waves take
+// rows in turn, lanes over the slice's columns; Z (+)= the block's sum.
+template <typename T>
+__global__ __launch_bounds__(256) void k_csr_block(const int64_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ colidx,
+                                                   const T *__restrict__ vals, const int32_t *__restrict__ pos,
+                                                   int nblk, int bk, int64_t rows, const T *__restrict__ V,
+                                                   int64_t ldv, int k, int nslices, T *__restrict__ Z,
+                                                   int64_t ldz) {
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int slice = (int)(blockIdx.x % (unsigned)nslices);
+  const int c = slice * 64 + lane;
+  const bool on = c < k;
+  const uint32_t coff = (on ? (uint32_t)c : 0u) * (uint32_t)sizeof(T);
+  const int64_t groups = gridDim.x / (unsigned)nslices;
+  for (int64_t i = (int64_t)(blockIdx.x / (unsigned)nslices) * 4 + wv; i < rows; i += groups * 4) {
+    const int64_t base = rowptr[i];
+    const int64_t t0 = base + pos[i * (nblk + 1) + bk], t1 = base + pos[i * (nblk + 1) + bk + 1];
+    const T acc = gather_dot<T, T>(colidx, vals, t0, t1, V, ldv, coff);
+    if (on) {
+      if (bk == 0) Z[i * ldz + c] = acc;
+      else Z[i * ldz + c] += acc;
+    }
+  }
+}
+
+int csr_blocks(int64_t n, size_t esz, int64_t *nbc) {
+  *nbc = (int64_t)(2 << 20) / (64 * (int64_t)esz);       // a 64-column slice of a block in 2 MiB
+  return (int)((n + *nbc - 1) / *nbc);
+}
+
+int launch_row_block_pos(const int64_t *rowptr, const int32_t *colidx, int64_t rows, int64_t nnz, int64_t nbc,
+                         int nblk, int32_t *pos, int *dflag, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_block_pos, (unsigned)((rows + 3) / 4), 256, 0, s, rowptr, colidx, rows, nnz, nbc,
+                     nblk, pos, dflag);
   LSPCA_HIP(hipGetLastError());
-  const unsigned gr = (unsigned)std::min<int64_t>((n + 3) / 4, 1 << 20);
-  hipLaunchKernelGGL(k_seg_reduce, gr, 256, 0, s, b.segoff, n, b.P, k, F);
+  return LSPCA_OK;
+}
+
+int launch_csr_blocked(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals,
+                       const int32_t *pos, int nblk, int64_t rows, const void *V, int64_t ldv, int k, void *Z,
+                       int64_t ldz, hipStream_t s) {
+  const int nslices = (k + 63) / 64;
+  const int64_t groups = std::max<int64_t>(1, std::min<int64_t>((rows + 3) / 4, 65536 / nslices));
+  const unsigned grid = (unsigned)(groups * nslices);
+  for (int bk = 0; bk < nblk; ++bk) {
+    if (vdt == LSPCA_F32)
+      hipLaunchKernelGGL(k_csr_block<float>, grid, 256, 0, s, rowptr, colidx, (const float *)vals, pos, nblk, bk,
+                         rows, (const float *)V, ldv, k, nslices, (float *)Z, ldz);
+    else
+      hipLaunchKernelGGL(k_csr_block<double>, grid, 256, 0, s, rowptr, colidx, (const double *)vals, pos, nblk,
+                         bk, rows, (const double *)V, ldv, k, nslices, (double *)Z, ldz);
+    LSPCA_HIP(hipGetLastError());
+  }
+  return LSPCA_OK;
+}
+
+// ---- F[c][j] += Ft[j][c] (k x n FP64 from n x k), through 64 x 64 LDS tiles
+__global__ __launch_bounds__(256) void k_add_transposed(const double *__restrict__ Ft, int64_t n, int k,
+                                                        double *__restrict__ F) {
+  __shared__ double tile[64][65];
+  const int64_t j0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t j = j0 + r;
+    const int c = c0 + tx;
+    tile[r][tx] = (j < n && c < k) ? Ft[j * k + c] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int c = c0 + r;
+    const int64_t j = j0 + tx;
+    if (c < k && j < n) F[(int64_t)c * n + j] += tile[tx][r];
+  }
+}
+
+int launch_add_transposed(const double *Ft, int64_t n, int k, double *F, hipStream_t s) {
+  const dim3 grid((unsigned)((n + 63) / 64), (unsigned)((k + 63) / 64));
+  hipLaunchKernelGGL(k_add_transposed, grid, 256, 0, s, Ft, n, k, F);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }

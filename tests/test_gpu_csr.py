@@ -170,6 +170,15 @@ def test_transform_csr_matches_oracle(gpu_lib, dtype, k):
     nz = int(np.diff(rowptr).max())
     bound = gamma(nz, UNIT[dtype]) * (np.abs(X64) @ np.abs(Vq))
     assert np.all(np.abs(Z - ref) <= bound + 1e-300)
+    # rows whose columns are not in order take the row-parallel path
+    rng2 = np.random.default_rng(5)
+    ci2, v2 = colidx.copy(), values.copy()
+    for i in range(0, m, 3):
+        p = rowptr[i] + rng2.permutation(rowptr[i + 1] - rowptr[i])
+        ci2[rowptr[i]:rowptr[i + 1]], v2[rowptr[i]:rowptr[i + 1]] = colidx[p], values[p]
+    Zu = gpu_lib.transform_csr(_dev_csr(gpu_lib, rowptr, ci2, v2, n),
+                               torch.from_numpy(V64).cuda()).double().cpu().numpy()
+    assert np.all(np.abs(Zu - ref) <= bound + 1e-300)
     # a row's result does not depend on the others (row slice)
     Z2 = gpu_lib.transform_csr(X.rows(500, 900), torch.from_numpy(V64).cuda()).double().cpu().numpy()
     assert np.array_equal(Z2, Z[500:900])
