@@ -357,7 +357,7 @@ static size_t factor_bytes(int64_t n, int k) {
   return 4 * ws_bytes<double>((size_t)n * k) + ws_bytes<double>(tn_partial_elems(k, k, splits)) +
          6 * ws_bytes<double>(kk) + 2 * ws_bytes<double>(k) + ws_bytes<int>(kSmallFlags) +
          ws_bytes<double>(4 * kk) +
-         ws_bytes<double>(3 * 128 * 128);
+         ws_bytes<double>(3 * 128 * 128) + sign_fix_bytes(n, k);
 }
 
 // Algorithm 4 over X in host memory: stripes of `stripe` rows go through two

@@ -280,6 +280,8 @@ int launch_reduce_add(lspca_dtype pdt, const void *P, int splits, int64_t count,
                       double *out, int accumulate, hipStream_t s,
                       const double *rowscale = nullptr, int ncols = 1);
 int zero_i32(int *p, int count, hipStream_t s);
+// Workspace of the sign step of small_factor (part of its need).
+size_t sign_fix_bytes(int64_t n, int k);
 int small_factor(const double *F, const double *G, int k, int64_t n,
                  double *V, double *sigma, double *sigma_x, Workspace &ws,
                  hipStream_t s, int *rank_flag, int route = 0);

@@ -83,47 +83,52 @@ int csr_check(const int64_t *rowptr, const int32_t *colidx, int64_t m, int64_t n
 
 // sum over t in [t0, t1), in order, of v[t] * B[idx[t] * ldb + c] (coff:
 // this lane's byte offset c * sizeof(T) within a row of B; idx and v are
-// wave-uniform and read through the scalar cache). Groups of sixteen gathers
-// in two buffers: the next group's indices and gathers are issued before the
-// current group's products, so sixteen to thirty-two gathers stay in flight.
+// wave-uniform and read through the scalar cache). Groups of kGatherGroup
+// gathers are issued together; the next group's indices (scalar loads) are
+// fetched while the current group's gathers are outstanding.
+#ifndef LSPCA_GATHER_GROUP
+#define LSPCA_GATHER_GROUP 32
+#endif
+constexpr int kGatherGroup = LSPCA_GATHER_GROUP;
+
 template <typename T, typename ACC>
 __device__ __forceinline__ ACC gather_dot(const int32_t *__restrict__ idx, const T *__restrict__ v,
                                           int64_t t0, int64_t t1, const T *__restrict__ B, int64_t ldb,
                                           uint32_t coff) {
+  constexpr int G = kGatherGroup;
   ACC acc = ACC(0);
   int64_t t = t0;
-  if (t + 16 <= t1) {
-    T va[16], ya[16], vb[16], yb[16];
+  if (t + G <= t1) {
+    int32_t r[G];
+    T w[G];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      va[u] = v[t + u];
-      ya[u] = *(const T *)((const char *)(B + (int64_t)idx[t + u] * ldb) + coff);
+    for (int u = 0; u < G; ++u) {
+      r[u] = idx[t + u];
+      w[u] = v[t + u];
     }
     for (;;) {
-      const bool more = t + 32 <= t1;
+      T y[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) y[u] = *(const T *)((const char *)(B + (int64_t)r[u] * ldb) + coff);
+      const bool more = t + 2 * G <= t1;
+      int32_t rn[G];
+      T wn[G];
       if (more) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          vb[u] = v[t + 16 + u];
-          yb[u] = *(const T *)((const char *)(B + (int64_t)idx[t + 16 + u] * ldb) + coff);
+        for (int u = 0; u < G; ++u) {
+          rn[u] = idx[t + G + u];
+          wn[u] = v[t + G + u];
         }
       }
 #pragma unroll
-      for (int u = 0; u < 16; ++u) acc = fma((ACC)va[u], (ACC)ya[u], acc);
-      t += 16;
+      for (int u = 0; u < G; ++u) acc = fma((ACC)w[u], (ACC)y[u], acc);
+      t += G;
       if (!more) break;
-      const bool more2 = t + 32 <= t1;
-      if (more2) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-          va[u] = v[t + 16 + u];
-          ya[u] = *(const T *)((const char *)(B + (int64_t)idx[t + 16 + u] * ldb) + coff);
-        }
+      for (int u = 0; u < G; ++u) {
+        r[u] = rn[u];
+        w[u] = wn[u];
       }
-#pragma unroll
-      for (int u = 0; u < 16; ++u) acc = fma((ACC)vb[u], (ACC)yb[u], acc);
-      t += 16;
-      if (!more2) break;
     }
   }
   for (; t < t1; ++t)

@@ -600,37 +600,67 @@ __global__ void k_scale_cols_inv(double *V, int64_t n, int k, const double *d) {
   if (e < n * k) V[e] /= d[e % k];
 }
 
-__global__ __launch_bounds__(256) void k_sign_fix(double *V, int64_t n, int k) {
-  __shared__ double bv[256];
-  __shared__ int64_t bi[256];
-  const int c = blockIdx.x;
-  double best = -1.0;
-  int64_t bidx = 0;
-  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-    const double a = fabs(V[i * k + c]);
-    if (a > best) {
-      best = a;
-      bidx = i;
-    }
-  }
-  bv[threadIdx.x] = best;
-  bi[threadIdx.x] = bidx;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) {
-      const double a = bv[threadIdx.x + o];
-      const int64_t ai = bi[threadIdx.x + o];
-      if (a > bv[threadIdx.x] || (a == bv[threadIdx.x] && ai < bi[threadIdx.x])) {
-        bv[threadIdx.x] = a;
-        bi[threadIdx.x] = ai;
+// Sign of each column of V (n x k): its entry of largest magnitude made
+// positive, the first row on ties. Column maxima per chunk of kSignRows rows
+// (threads over columns, coalesced), then across chunks in order, then the
+// flip.
+constexpr int kSignRows = 256;
+__global__ __launch_bounds__(256) void k_colmax_part(const double *__restrict__ V, int64_t n, int k,
+                                                     double *__restrict__ pv, int64_t *__restrict__ pi) {
+  const int64_t r0 = (int64_t)blockIdx.x * kSignRows;
+  const int64_t r1 = r0 + kSignRows < n ? r0 + kSignRows : n;
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    double best = -1.0;
+    int64_t bi = r0;
+    for (int64_t i = r0; i < r1; ++i) {
+      const double a = fabs(V[i * k + c]);
+      if (a > best) {
+        best = a;
+        bi = i;
       }
     }
-    __syncthreads();
+    pv[(int64_t)blockIdx.x * k + c] = best;
+    pi[(int64_t)blockIdx.x * k + c] = bi;
   }
-  const bool flip = V[bi[0] * k + c] < 0.0;
-  __syncthreads();
-  if (flip)
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) V[i * k + c] = -V[i * k + c];
+}
+
+__global__ void k_colmax_sign(const double *__restrict__ V, const double *__restrict__ pv,
+                              const int64_t *__restrict__ pi, int64_t chunks, int k, double *__restrict__ sgn) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t b = 0; b < chunks; ++b)
+    if (pv[b * k + c] > best) {
+      best = pv[b * k + c];
+      bi = pi[b * k + c];
+    }
+  sgn[c] = V[bi * k + c] < 0.0 ? -1.0 : 1.0;
+}
+
+__global__ void k_flip(double *__restrict__ V, int64_t n, int k, const double *__restrict__ sgn) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * k; e += stride)
+    if (sgn[e % k] < 0.0) V[e] = -V[e];
+}
+
+size_t sign_fix_bytes(int64_t n, int k) {
+  const int64_t chunks = (n + kSignRows - 1) / kSignRows;
+  return ws_bytes<double>((size_t)chunks * k) + ws_bytes<int64_t>((size_t)chunks * k) + ws_bytes<double>(k);
+}
+
+static int sign_fix(double *V, int64_t n, int k, Workspace &ws, hipStream_t s) {
+  const int64_t chunks = (n + kSignRows - 1) / kSignRows;
+  double *pv = ws.take<double>((size_t)chunks * k);
+  int64_t *pi = ws.take<int64_t>((size_t)chunks * k);
+  double *sgn = ws.take<double>(k);
+  hipLaunchKernelGGL(k_colmax_part, (unsigned)chunks, 256, 0, s, V, n, k, pv, pi);
+  LSPCA_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_colmax_sign, (unsigned)((k + 255) / 256), 256, 0, s, V, pv, pi, chunks, k, sgn);
+  LSPCA_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_flip, (unsigned)std::min<int64_t>((n * k + 255) / 256, 65536), 256, 0, s, V, n, k, sgn);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
 }
 
 // ------------------------------------------------------------- driver ------
@@ -972,8 +1002,7 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
     LSPCA_TRY(trinv_t(M, k, XT, scr, s));
     LSPCA_TRY(launch_nt(LSPCA_F64, Qa, k, XT, k, Vw, k, n, k, k, s));
   }
-  hipLaunchKernelGGL(k_sign_fix, k, 256, 0, s, Vw, n, k);
-  LSPCA_HIP(hipGetLastError());
+  LSPCA_TRY(sign_fix(Vw, n, k, ws, s));
 
   if (sigma_x) {
     // Sigma^s = singular values of R R_G^-1, G = R_G^T R_G.
