@@ -46,19 +46,28 @@ MEASURED_TRAFFIC = {
         "sha256": "f196c74cc83612f933f55b7979b1c32282398a8b4ada7e84c569f52f700b4f00",
         "bytes": 9.2162e9,
     },
+    ("csr", 131_072, 98_450, 500, "sparse"): {   # k_csc_block, per row-block launch
+        "sources": ["paper_1709_07175_amd/csrc/csr.hip", "paper_1709_07175_amd/csrc/common.h"],
+        "sha256": "3a641c29d8c3b69b6ae10cc5413d2bab26539193db2c7e39419c7b829a71d0f3",
+        "bytes": 3.3356e+09,
+    },
 }
 
 
-def measured_traffic(cfg, m):
+def measured_traffic_rec(rec):
     import hashlib
-    rec = MEASURED_TRAFFIC.get((cfg["dtype"], m, cfg["n"], cfg["k"], cfg["kind"]))
-    if rec is None:
-        return None
     h = hashlib.sha256()
     for f in rec["sources"]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    return rec["bytes"] if h.hexdigest() == rec["sha256"] else None
+    return h.hexdigest() == rec["sha256"]
+
+
+def measured_traffic(cfg, m):
+    rec = MEASURED_TRAFFIC.get((cfg["dtype"], m, cfg["n"], cfg["k"], cfg["kind"]))
+    if rec is None:
+        return None
+    return rec["bytes"] if measured_traffic_rec(rec) else None
 
 
 def roofline(cfg, m, n, k, xbytes, esz, sketch_ms):
@@ -227,19 +236,56 @@ def serving(lib, V, Xsrc, levels, counts, modes, seed=7175 + 5, log_every=500):
     return out
 
 
-def csr_roofline(c, cnt, rows, esz, factor_ms_per_launch):
-    """The column sums F += Y^T X of one stripe (k_csc_factor): algorithmic
-    bytes = the stripe's column-ordered entries (row index + value) once, its
+# Gather bound of the sparse column sums: each XCD's L2 serves 16 channels x
+# 128 B per clock (the CDNA3 L2 design), 8 XCDs at 2.4 GHz.
+L2_GBs = 8 * 16 * 128 * 2.4
+
+
+def calibrate(torch, dev, gib):
+    """y = 2 x over `gib` GiB of FP32: a reference op of known HBM traffic
+    (reads and writes gib GiB once) for the byte counters."""
+    cnt = int(gib * 2 ** 30) // 4
+    a = torch.ones(cnt, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def csr_block_launches(rows, n, esz):
+    """Row blocks of one stripe (the library's csc_shape): one k_csc_block
+    launch each."""
+    rb_l2 = (2 << 20) // (64 * esz)
+    nb = -(-rows // rb_l2)
+    nb = max(1, min(nb, max(1, (1 << 26) // n)))
+    rb = -(-rows // nb)
+    return -(-rows // rb)
+
+
+def csr_roofline(c, nnz, m, esz, launches, factor_ms):
+    """The column sums F += Y^T X (k_csc_block, one launch per row block of a
+    stripe). Per launch (the pass's totals over its launches): gathered bytes
+    = entries x k x value size (one sketch-row segment per entry and 64-column
+    slice); algorithmic HBM bytes = the entries (row index + value) once, the
     sketch rows once, F read and written once."""
     n, k = c["n"], c["k"]
-    alg = cnt * (4 + esz) + rows * k * esz + 2 * k * n * 8
-    achieved = alg / (factor_ms_per_launch * 1e-3) / 1e9
-    return {"kernel": "k_csc_factor (F += Y^T X, column order)", "bound": "hbm",
-            "achieved": round(achieved, 3), "peak": PEAKS["hbm_GBs"], "unit": "GB/s",
-            "frac": round(achieved / PEAKS["hbm_GBs"], 4), "traffic": None,
-            "algorithmic": f"entries (4 + {esz} B) + Y rows once + F in and out = {alg:.4g} bytes per launch",
-            "algorithmic_bytes": alg,
-            "gathered_GBs": round(cnt * k * esz / (factor_ms_per_launch * 1e-3) / 1e9, 3)}
+    gathered = nnz * k * esz / launches
+    alg = (nnz * (4 + esz) + m * k * esz + 2 * k * n * 8) / launches
+    t = factor_ms / launches * 1e-3
+    achieved = gathered / t / 1e9
+    rec = MEASURED_TRAFFIC.get(("csr", m, n, k, c["kind"]))
+    traffic = None
+    if rec is not None and measured_traffic_rec(rec):
+        traffic = rec["bytes"]
+    return {"kernel": "k_csc_block (F += Y^T X, one row block)", "bound": "l2",
+            "achieved": round(achieved, 3), "peak": L2_GBs, "unit": "GB/s",
+            "frac": round(achieved / L2_GBs, 4), "traffic": traffic,
+            "algorithmic": f"gathered: entries x k x {esz} B = {gathered:.4g} bytes per launch "
+                           f"({launches} launches per fit)",
+            "algorithmic_bytes": gathered,
+            "hbm_algorithmic_bytes": alg,
+            "hbm_GBs": round(alg / t / 1e9, 3)}
 
 
 def csr_cpu_baseline(c, rph, cih, vvh, budget_s=20.0):
@@ -266,8 +312,9 @@ def csr_cpu_baseline(c, rph, cih, vvh, budget_s=20.0):
 
     rows = k
     dt = one(rows)
-    while rows < len(rph) - 1 and dt * 2.2 <= budget_s:
-        rows = min(len(rph) - 1, rows * 2)
+    cap = min(len(rph) - 1, 8192)                   # dense rows of the sample: <= 8192 x n FP64
+    while rows < cap and dt * 2.2 <= budget_s:
+        rows = min(cap, rows * 2)
         dt = one(rows)
     times = [dt]
     while sum(times) < 10.0 and len(times) < 200:
@@ -300,6 +347,8 @@ def csr_main(args, lib, torch):
     log(f"generated in {time.time() - t0:.1f}s: nnz {X.nnz}")
     xbytes = rp.numel() * 8 + X.nnz * (4 + vv.element_size())
     stream = torch.cuda.current_stream()
+    if args.calib_gib > 0:
+        calibrate(torch, dev, args.calib_gib)
 
     def step(timing):
         V, s = lib.fit_csr(X, k, c["kind"], c["omega_seed"], timing=timing, sparse_p=c["p"])
@@ -330,8 +379,9 @@ def csr_main(args, lib, torch):
     # stripes of the pass (the library's plan: entries per stripe <= 2^28 on
     # 64-row boundaries, rows <= the 2 GiB sketch budget)
     rph = rp.cpu().numpy()
+    esz = vv.element_size()
     starts, r0 = [0], 0
-    rows_cap = min((2 << 30) // (k * vv.element_size()), 1 << 24)
+    rows_cap = min((2 << 30) // (k * esz), 1 << 24)
     while r0 < m:
         r1 = r0 + 64
         while r1 < m and r1 + 64 - r0 <= rows_cap and rph[min(r1 + 64, m)] - rph[r0] <= (1 << 28):
@@ -339,8 +389,7 @@ def csr_main(args, lib, torch):
         r0 = min(r1, m)
         starts.append(r0)
     nstripes = len(starts) - 1
-    big = max(range(nstripes), key=lambda t: rph[starts[t + 1]] - rph[starts[t]])
-    cnt = int(rph[starts[big + 1]] - rph[starts[big]])
+    launches = sum(csr_block_launches(starts[t + 1] - starts[t], n, esz) for t in range(nstripes))
     fit_ms, tr_ms = avg("total_ms", 0), avg("transform_ms", 1)
     value = 2 * xbytes / (ms_step * 1e-3) / 1e9
     out = {
@@ -353,11 +402,10 @@ def csr_main(args, lib, torch):
                    "m": m, "n": n, "k": k, "nnz": X.nnz, "x_bytes": xbytes, "stripes": nstripes,
                    "parallelism": "single-gpu"},
         "phases_ms": {"fit_total": round(fit_ms, 4), "omega": round(avg("omega_ms"), 4),
-                      "sketch_spmm": round(avg("sketch_ms"), 4), "csc_build": round(avg("layout_ms"), 4),
-                      "factor_F": round(avg("factor_ms"), 4), "reduce_G": round(avg("reduce_ms"), 4),
+                      "sketch": round(avg("sketch_ms"), 4), "csc_build": round(avg("layout_ms"), 4),
+                      "factor_F": round(avg("factor_ms"), 4), "reduce": round(avg("reduce_ms"), 4),
                       "small_fp64": round(avg("small_ms"), 4), "transform": round(tr_ms, 4)},
-        "roofline": csr_roofline(c, cnt, starts[big + 1] - starts[big], vv.element_size(),
-                                 avg("factor_ms") / nstripes),
+        "roofline": csr_roofline(c, X.nnz, m, esz, launches, avg("factor_ms")),
     }
     if not args.no_cpu:
         log("cpu baseline (oracle on a row sample)")
@@ -415,13 +463,7 @@ def main():
     xbytes = X.numel() * X.element_size()
     stream = torch.cuda.current_stream()
     if args.calib_gib > 0:
-        cnt = int(args.calib_gib * 2 ** 30) // 4
-        a = torch.ones(cnt, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        torch.mul(a, 2.0, out=b)           # reads and writes calib_gib GiB once
-        torch.cuda.synchronize()
-        del a, b
+        calibrate(torch, dev, args.calib_gib)
 
     def step(timing):
         V, s = lib.fit(X, k, cfg["kind"], cfg["omega_seed"], timing=timing, sparse_p=cfg.get("p", 64))
