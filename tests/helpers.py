@@ -47,8 +47,9 @@ def pass_bound(X64, Om64, dtype, refine=True):
     m, n = X64.shape
     aX, aO = np.abs(X64), np.abs(Om64)
     Y = X64 @ Om64
-    aY = np.abs(Y) + gamma(n, u) * (aX @ aO)
-    bF = gamma(n, u) * (aO.T @ (aX.T @ aX)) + gamma(m, u) * (aY.T @ aX)
+    aXO = aX @ aO                                   # |X| |Omega| (m x k), reused below
+    aY = np.abs(Y) + gamma(n, u) * aXO
+    bF = gamma(n, u) * (aXO.T @ aX) + gamma(m, u) * (aY.T @ aX)
     if dtype in U16:
         rho = U16[dtype] ** 2 if refine else U16[dtype]
         # split error, plus FP16's subnormal floor (columns scaled so the
@@ -56,7 +57,7 @@ def pass_bound(X64, Om64, dtype, refine=True):
         bF = bF + (rho * 1.01) * (aY.T @ aX) + 2.0 ** -37 * aY.max(axis=0)[:, None] * aX.sum(axis=0)[None, :]
         bG = bF @ aO + 1e-12 * np.abs(Y.T @ Y)
         return bF, bG
-    bG = 2 * gamma(n, u) * ((aX @ aO).T @ aY) + gamma(m, u) * (aY.T @ aY)
+    bG = 2 * gamma(n, u) * (aXO.T @ aY) + gamma(m, u) * (aY.T @ aY)
     return bF, bG
 
 
