@@ -335,6 +335,8 @@ def csr_main(args, lib, torch):
     c = dict(CSR_CONFIG)
     if args.m:
         c["m"] = args.m
+    if args.k:
+        c["k"] = args.k
     m, n, k = c["m"], c["n"], c["k"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -407,6 +409,20 @@ def csr_main(args, lib, torch):
                       "small_fp64": round(avg("small_ms"), 4), "transform": round(tr_ms, 4)},
         "roofline": csr_roofline(c, X.nnz, m, esz, launches, avg("factor_ms")),
     }
+    if not args.no_spca and k <= 256:
+        # Algorithm 1 on the same CSR X (the GPU tall-skinny QR holds k <= 256)
+        lib.spca_fit_csr(X, k, c["kind"], c["omega_seed"], sparse_p=c["p"])
+        torch.cuda.synchronize()
+        sp = []
+        for _ in range(2):
+            lib.spca_fit_csr(X, k, c["kind"], c["omega_seed"], timing=True, sparse_p=c["p"])
+            sp.append(lib.last_timings())
+        sp_ms = sum(t["total_ms"] for t in sp) / len(sp)
+        out["spca"] = {"fit_ms": round(sp_ms, 3),
+                       "phases_ms": {key: round(sum(t[key + "_ms"] for t in sp) / len(sp), 4)
+                                     for key in ("omega", "sketch", "qr", "layout", "pass2", "reduce", "small")},
+                       "lazy_fit_speedup": round(sp_ms / fit_ms, 3)}
+        log(f"spca_fit_csr {sp_ms:.2f} ms vs lazy {fit_ms:.2f} ms")
     if not args.no_cpu:
         log("cpu baseline (oracle on a row sample)")
         out["cpu_baseline"] = csr_cpu_baseline(c, rph, ci.cpu().numpy(), vv.cpu().numpy())
@@ -424,6 +440,8 @@ def main():
     ap.add_argument("--no-spca", action="store_true")
     ap.add_argument("--spca-steps", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the fit of an FP32 copy of 16-bit X (the plain FP32 path)")
     ap.add_argument("--no-host", action="store_true",
                     help="skip the fit of the same X from pinned host memory (Algorithm 4 streamed)")
     ap.add_argument("--serve-counts", type=str, default="200,600,2000",
@@ -432,6 +450,7 @@ def main():
     ap.add_argument("--csr", action="store_true",
                     help="the sparse-X workload instead: CSR X 131,072 x 98,450 at density 0.0244 "
                          "(Experiment 1's feature matrix shape), very sparse Omega, k = 500")
+    ap.add_argument("--k", type=int, default=0, help="override k (sparse-X workload)")
     ap.add_argument("--calib-gib", type=float, default=0.0,
                     help="run y = 2 x over this many GiB (FP32) before timing: a reference of "
                          "known traffic for HBM byte counters")
@@ -563,6 +582,25 @@ def main():
             log(f"spca_fit_stream {ss_ms:.3f} ms")
         except lib.LspcaError as e:
             out["spca"] = {"error": str(e)}
+    if not args.no_plain and cfg["dtype"] in ("bf16", "f16"):
+        # the same values as FP32 through the plain FP32 path (exact copy)
+        log("fit of an FP32 copy of X (plain FP32 path)")
+        X32 = X.float()
+        lib.fit(X32, k, cfg["kind"], cfg["omega_seed"], sparse_p=cfg.get("p", 64))
+        torch.cuda.synchronize()
+        pts = []
+        for _ in range(2):
+            lib.fit(X32, k, cfg["kind"], cfg["omega_seed"], timing=True, sparse_p=cfg.get("p", 64))
+            pts.append(lib.last_timings())
+        p_ms = sum(t["total_ms"] for t in pts) / len(pts)
+        out["fp32_plain"] = {"fit_ms": round(p_ms, 3),
+                             "x_bytes": X32.numel() * 4,
+                             "phases_ms": {key: round(sum(t[key + "_ms"] for t in pts) / len(pts), 4)
+                                           for key in ("omega", "sketch", "factor", "reduce", "small")},
+                             "lazy_16bit_speedup": round(p_ms / fit_ms, 3)}
+        log(f"FP32 copy: fit {p_ms:.2f} ms vs {fit_ms:.2f} ms")
+        del X32
+        torch.cuda.empty_cache()
     if not args.no_host:
         # Algorithm 4 with X in pinned host memory (the out-of-core regime):
         # host-to-device copies of stripes overlapped with the pass

@@ -307,6 +307,18 @@ LSPCA_API int lspca_fit_csr(const int64_t *rowptr, const int32_t *colidx, const 
                             double *sigma, double *sigma_x);
 
 /*
+ * spca_fit_csr -- SPCA (Algorithm 1), the non-lazy baseline, for a CSR X:
+ * U = X Omega for all rows (kept, m x k), tall-skinny Householder QR U = Q R
+ * with explicit thin Q, F = Q^T X (a second pass over X), truncated SVD of
+ * F. Outputs as spca_fit (V^s, Sigma^s); limits as spca_fit (k <= 256, FP64
+ * values: k <= 128). Synchronous. Errors as lspca_fit_csr, ENOTSUP.
+ */
+LSPCA_API int spca_fit_csr(const int64_t *rowptr, const int32_t *colidx, const void *values,
+                           lspca_dtype vdt, int64_t m, int64_t n, int64_t nnz, int32_t k,
+                           lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts, double *V,
+                           double *sigma);
+
+/*
  * lspca_transform_csr -- Z = X V (eq. (dim_reduction_maps)) for the r rows
  * of a CSR X. V: n x k FP64 (device; rounded to FP32 for FP32 values).
  * Z: r x k of the value type. Each row of Z is the sum of its row's

@@ -33,7 +33,7 @@ STATUS = {0: "LSPCA_OK", -1: "LSPCA_EINVAL", -2: "LSPCA_ENOMEM", -3: "LSPCA_EHIP
 EXPORTS = ["lspca_version", "lspca_strerror", "lspca_last_error", "lspca_last_timings",
            "lspca_omega", "lspca_accumulate", "lspca_factor", "lspca_fit", "spca_fit",
            "lspca_transform", "lspca_accumulate_host", "lspca_fit_host", "spca_fit_stream",
-           "lspca_accumulate_csr", "lspca_fit_csr", "lspca_transform_csr",
+           "lspca_accumulate_csr", "lspca_fit_csr", "lspca_transform_csr", "spca_fit_csr",
            "lspca_server_create", "lspca_server_submit", "lspca_server_wait",
            "lspca_server_pause", "lspca_server_get_stats", "lspca_server_destroy"]
 
@@ -97,6 +97,8 @@ _SIGS = {
                        ctypes.POINTER(lspca_opts), _P, _P, _P], ctypes.c_int),
     "lspca_transform_csr": ([_P, _P, _P, ctypes.c_int, _I64, _I64, _I64, _P, _I32, _P,
                              ctypes.POINTER(lspca_opts)], ctypes.c_int),
+    "spca_fit_csr": ([_P, _P, _P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
+                      ctypes.POINTER(lspca_opts), _P, _P], ctypes.c_int),
     "lspca_server_create": ([_P, _I64, _I32, ctypes.c_int, ctypes.c_size_t, _I32,
                              ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "lspca_server_submit": ([_P, _P, _I64, _P, ctypes.POINTER(_U64)], ctypes.c_int),
@@ -334,6 +336,17 @@ def fit_csr(X, k, kind="gaussian", seed=0, want_sigma_x=False, **kw):
     _check(load().lspca_fit_csr(*X._args(), X.m, X.n, X.nnz, k, KIND[kind], seed, ctypes.byref(o),
                                 V.data_ptr(), s.data_ptr(), sx.data_ptr() if sx is not None else None))
     return (V, s, sx) if want_sigma_x else (V, s)
+
+
+def spca_fit_csr(X, k, kind="gaussian", seed=0, **kw):
+    """SPCA (Algorithm 1) of a CSR X with the GPU tall-skinny QR: V^s, Sigma^s."""
+    dev = X.values.device
+    V = _f64_out((X.n, k), dev)
+    s = _f64_out((k,), dev)
+    o = _opts(**kw)
+    _check(load().spca_fit_csr(*X._args(), X.m, X.n, X.nnz, k, KIND[kind], seed, ctypes.byref(o),
+                               V.data_ptr(), s.data_ptr()))
+    return V, s
 
 
 def transform_csr(X, V, Z=None, **kw):

@@ -468,6 +468,8 @@ struct CsrPlan {
   int64_t max_rows = 0, max_cnt = 0;
   int splits_g = 0;
   int64_t ldy = 0;                                   // row pitch of Y (128-byte rows)
+  int nblk = 0;                                      // Gaussian sketch by column blocks of nbc
+  int64_t nbc = 0;
   CscShape shape;                                    // of the largest stripe
   size_t bytes = 0;
 };
@@ -503,13 +505,20 @@ static int plan_csr(const int64_t *rowptr, const int32_t *colidx, lspca_dtype vd
   LSPCA_TRY(ws.ensure(ws_bytes<int>(1) + ws_bytes<int64_t>(nb)));
   int *flag = ws.take<int>(1);
   int64_t *bd = ws.take<int64_t>(nb);
-  LSPCA_TRY(csr_check(rowptr, colidx, m, n, nnz, flag, s));
+  // a Gaussian Omega is applied by column blocks when every row's columns
+  // are in order (the dense rows of Omega then stay in L2)
+  const bool blocks = !csr_lists(kind, n, k);
+  LSPCA_TRY(csr_check_launch(rowptr, colidx, m, n, nnz, flag, s));
+  if (blocks) LSPCA_TRY(launch_rows_sorted(rowptr, colidx, m, nnz, flag, s));
   LSPCA_TRY(launch_row_bounds(rowptr, m, g, nb, bd, s));
+  bool unsorted = true;
+  LSPCA_TRY(csr_check_result(flag, n, nnz, &unsorted, s));
   std::vector<int64_t> hb(nb);
   LSPCA_HIP(hipMemcpyAsync(hb.data(), bd, nb * sizeof(int64_t), hipMemcpyDeviceToHost, s));
   LSPCA_HIP(hipStreamSynchronize(s));
   ws.reset();
   pl = CsrPlan();
+  pl.nblk = blocks && !unsorted ? csr_blocks(n, esz, &pl.nbc) : 0;
   int64_t b = 0;                                     // block index of the stripe start
   while (b < nb - 1) {
     int64_t t = b + 1;
@@ -544,14 +553,25 @@ static int plan_csr(const int64_t *rowptr, const int32_t *colidx, lspca_dtype vd
              + ws_bytes<char>(std::max(csc_temp_bytes(pl.max_cnt, pl.shape.lists), om_scan_bytes(n)));
   if (csr_lists(kind, n, k))                                      // Omega row lists
     pl.bytes += 2 * ws_bytes<int32_t>((size_t)n + 1) + ws_bytes<int32_t>((size_t)n * k);
+  if (pl.nblk)                                                     // the stripe's block offsets
+    pl.bytes += ws_bytes<int32_t>((size_t)pl.max_rows * (pl.nblk + 1)) + ws_bytes<int>(1);
   return LSPCA_OK;
 }
 
 // Algorithm 4 step 2 over a CSR X: per stripe Y = X_s Omega (row SpMM),
 // F += Y^T X_s (column-ordered, from the stripe's CSC form), G += Y^T Y.
+// SPCA (Algorithm 1) over a CSR X: the whole sketch U^T (column c at
+// Ut + c * ldt), overwritten by the QR, and its thin Q (m x k, row pitch ldq).
+struct CsrSpca {
+  void *Ut;
+  int64_t ldt;
+  void *Q;
+  int64_t ldq;
+};
+
 static int csr_pass(const int64_t *rowptr, const int32_t *colidx, const void *vals, lspca_dtype vdt,
                     int64_t n, int k, int kind, uint64_t seed, const Opts &o, const CsrPlan &pl,
-                    double *F, double *G, Workspace &ws, PhaseTimer &tm) {
+                    double *F, double *G, Workspace &ws, PhaseTimer &tm, const CsrSpca *sp = nullptr) {
   hipStream_t s = o.stream;
   const size_t esz = dtype_size(vdt);
   const size_t E = (size_t)pl.max_cnt;
@@ -587,14 +607,52 @@ static int csr_pass(const int64_t *rowptr, const int32_t *colidx, const void *va
     oc = ws.take<int32_t>((size_t)n * k);
     LSPCA_TRY(build_omega_lists(vdt, Om, ldy, n, k, ocnt, optr, oc, b.temp, b.temp_bytes, s));
   }
+  int32_t *pos = nullptr;
+  int *pflag = nullptr;
+  if (pl.nblk) {
+    pos = ws.take<int32_t>((size_t)pl.max_rows * (pl.nblk + 1));
+    pflag = ws.take<int>(1);
+  }
   tm.mark(PH_OMEGA);
+  // Y (rows x k, row pitch ldy) = rows [r0, r0 + rows) of X times Omega
+  auto sketch = [&](int64_t r0, int64_t rows) -> int {
+    if (lists)
+      return launch_csr_sketch_lists(vdt, rowptr, colidx, vals, r0, rows, optr, oc, k, Y, ldy, s);
+    if (pl.nblk) {
+      LSPCA_TRY(launch_row_block_pos(rowptr + r0, colidx, rows, pl.e.back(), pl.nbc, pl.nblk, pos, pflag, s));
+      return launch_csr_blocked(vdt, rowptr + r0, colidx, vals, pos, pl.nblk, rows, Om, ldy, k, Y, ldy, s);
+    }
+    return launch_csr_spmm(vdt, rowptr, colidx, vals, r0, rows, Om, ldy, k, Y, ldy, s);
+  };
+  if (sp) {
+    // Algorithm 1: U = X Omega (all rows, transposed), Q R = U, F = Q^T X
+    const size_t esz_ = dtype_size(vdt);
+    for (size_t t = 0; t + 1 < pl.r.size(); ++t) {
+      const int64_t r0 = pl.r[t], rows = pl.r[t + 1] - r0;
+      LSPCA_TRY(sketch(r0, rows));
+      LSPCA_TRY(launch_rows_to_cols(vdt, Y, rows, k, ldy, (char *)sp->Ut + esz_ * (size_t)r0, sp->ldt, s));
+    }
+    tm.mark(PH_SKETCH);
+    LSPCA_TRY(tsqr(sp->Ut, vdt, pl.r.back(), sp->ldt, k, ws, 0, vdt, sp->Q, nullptr, nullptr, sp->ldq, s));
+    tm.mark(PH_QR);
+    for (size_t t = 0; t + 1 < pl.r.size(); ++t) {
+      const int64_t r0 = pl.r[t], rows = pl.r[t + 1] - r0;
+      const int64_t e0 = pl.e[t], cnt = pl.e[t + 1] - e0;
+      CscShape sh = csc_shape(rows, n, pl.max_cnt, k, esz);
+      LSPCA_TRY(build_csc(vdt, rowptr, colidx, vals, r0, rows, e0, cnt, n, sh, b, s));
+      tm.mark(PH_LAYOUT);
+      LSPCA_TRY(launch_csc_factor(vdt, b, sh, n, cnt, (const char *)sp->Q + esz_ * (size_t)r0 * sp->ldq, k,
+                                  sp->ldq, Ft, s));
+      tm.mark(PH_PASS2);
+    }
+    LSPCA_TRY(launch_add_transposed(Ft, n, k, F, s));
+    tm.mark(PH_REDUCE);
+    return LSPCA_OK;
+  }
   for (size_t t = 0; t + 1 < pl.r.size(); ++t) {
     const int64_t r0 = pl.r[t], rows = pl.r[t + 1] - r0;
     const int64_t e0 = pl.e[t], cnt = pl.e[t + 1] - e0;
-    if (lists)
-      LSPCA_TRY(launch_csr_sketch_lists(vdt, rowptr, colidx, vals, r0, rows, optr, oc, k, Y, ldy, s));
-    else
-      LSPCA_TRY(launch_csr_spmm(vdt, rowptr, colidx, vals, r0, rows, Om, ldy, k, Y, ldy, s));
+    LSPCA_TRY(sketch(r0, rows));
     tm.mark(PH_SKETCH);
     // this stripe's row blocks; the segment length of the largest stripe
     CscShape sh = csc_shape(rows, n, pl.max_cnt, k, esz);
@@ -1045,6 +1103,44 @@ int lspca_transform_csr(const int64_t *rowptr, const int32_t *colidx, const void
   else
     LSPCA_TRY(launch_csr_spmm(vdt, rowptr, colidx, values, 0, r, Vp, ldv, k, Z, k, o.stream));
   tm.mark(PH_TRANSFORM);
+  if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int spca_fit_csr(const int64_t *rowptr, const int32_t *colidx, const void *values, lspca_dtype vdt, int64_t m,
+                 int64_t n, int64_t nnz, int32_t k, lspca_omega_kind kind, uint64_t seed, const lspca_opts *opts,
+                 double *V, double *sigma) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  LSPCA_TRY(check_csr_args(rowptr, colidx, values, vdt, m, n, nnz, k, kind, o));
+  if (!V || !sigma) { set_error("V and sigma must not be NULL"); return LSPCA_EINVAL; }
+  if (k > m) { set_error("k must satisfy k <= min(m, n) (k=%d m=%lld)", k, (long long)m); return LSPCA_EINVAL; }
+  if (k > (vdt == LSPCA_F64 ? 128 : 256)) {
+    set_error("spca_fit_csr: k = %d above the QR block height (%d)", k, vdt == LSPCA_F64 ? 128 : 256);
+    return LSPCA_ENOTSUP;
+  }
+  Locked L;
+  LSPCA_TRY(lock_device(L));
+  Workspace &ws = L.st->ws;
+  CsrPlan pl;
+  LSPCA_TRY(plan_csr(rowptr, colidx, vdt, m, n, nnz, k, kind, false, o, ws, pl));
+  const size_t esz = dtype_size(vdt);
+  const int64_t ldt = tsqr_ld(m, vdt), ldq = csr_ld(k, esz);
+  const size_t fixed = ws_bytes<double>((size_t)k * n) + ws_bytes<char>(esz * (size_t)ldt * k) +
+                       ws_bytes<char>(esz * (size_t)m * ldq);
+  const size_t pass = pl.bytes + tsqr_workspace_bytes(m, k, vdt), fb = factor_bytes(n, k);
+  LSPCA_TRY(ws.ensure(fixed + (pass > fb ? pass : fb)));
+  double *F = ws.take<double>((size_t)k * n);
+  CsrSpca sp{ws.take<char>(esz * (size_t)ldt * k), ldt, ws.take<char>(esz * (size_t)m * ldq), ldq};
+  const size_t mark = ws.used;
+  PhaseTimer tm;
+  tm.begin(o.timing != 0, o.stream);
+  LSPCA_TRY(zero_f64(F, (int64_t)k * n, o.stream));
+  LSPCA_TRY(csr_pass(rowptr, colidx, values, vdt, n, k, kind, seed, o, pl, F, nullptr, ws, tm, &sp));
+  ws.used = mark;
+  int rank_flag = 0;
+  LSPCA_TRY(small_factor(F, nullptr, k, n, V, sigma, nullptr, ws, o.stream, &rank_flag, o.small_route));
+  tm.mark(PH_SMALL);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;
 }

@@ -206,6 +206,9 @@ int csr_check_result(const int *dflag, int64_t n, int64_t nnz, bool *unsorted, h
 // block count): pos (rows x (nblk + 1) int32) holds each row's block
 // offsets, for rows with nondecreasing columns.
 int csr_blocks(int64_t n, size_t esz, int64_t *nbc);
+// Sets bit 2 of *dflag when some row's columns decrease.
+int launch_rows_sorted(const int64_t *rowptr, const int32_t *colidx, int64_t rows, int64_t nnz, int *dflag,
+                       hipStream_t s);
 int launch_row_block_pos(const int64_t *rowptr, const int32_t *colidx, int64_t rows, int64_t nnz, int64_t nbc,
                          int nblk, int32_t *pos, int *dflag, hipStream_t s);
 int launch_csr_blocked(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals,
@@ -261,6 +264,9 @@ int build_csc(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, con
 // (FP64 accumulation, Y of the value type; Ft is n x k).
 int launch_csc_factor(lspca_dtype vdt, const CscBuffers &b, const CscShape &sh, int64_t n, int64_t cnt,
                       const void *Y, int k, int64_t ldy, double *Ft, hipStream_t s);
+// Ut[c * ldt + i] = Y[i * ldy + c] for i < rows, c < k (value type vdt).
+int launch_rows_to_cols(lspca_dtype vdt, const void *Y, int64_t rows, int k, int64_t ldy, void *Ut, int64_t ldt,
+                        hipStream_t s);
 // F[c * n + j] += Ft[j * k + c].
 int launch_add_transposed(const double *Ft, int64_t n, int k, double *F, hipStream_t s);
 // out[j * ldo + c] = V[j][c] (n x k FP64, row-major) in the value type (FP32:

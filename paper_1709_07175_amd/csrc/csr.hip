@@ -699,6 +699,32 @@ __global__ __launch_bounds__(256) void k_csr_block(const int64_t *__restrict__ r
   }
 }
 
+// Bit 2 of flag when some row's columns decrease (one wave per row; reads
+// stay in [0, nnz) whatever rowptr holds).
+__global__ __launch_bounds__(256) void k_rows_sorted(const int64_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ colidx, int64_t rows,
+                                                     int64_t nnz, int *flag) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= rows) return;
+  int64_t a = rowptr[i], b = rowptr[i + 1];
+  a = a < 0 ? 0 : (a > nnz ? nnz : a);
+  b = b < a ? a : (b > nnz ? nnz : b);
+  bool bad = false;
+  for (int64_t e = a + lane; e + 1 < b; e += 64) bad |= colidx[e] > colidx[e + 1];
+  if (__ballot(bad) != 0ull && lane == 0) atomicOr(flag, 4);
+}
+
+int launch_rows_sorted(const int64_t *rowptr, const int32_t *colidx, int64_t rows, int64_t nnz, int *dflag,
+                       hipStream_t s) {
+  for (int64_t r0 = 0; r0 < rows; r0 += kCsrMaxRows) {
+    const int64_t cr = rows - r0 < kCsrMaxRows ? rows - r0 : kCsrMaxRows;
+    hipLaunchKernelGGL(k_rows_sorted, (unsigned)((cr + 3) / 4), 256, 0, s, rowptr + r0, colidx, cr, nnz, dflag);
+    LSPCA_HIP(hipGetLastError());
+  }
+  return LSPCA_OK;
+}
+
 int csr_blocks(int64_t n, size_t esz, int64_t *nbc) {
   *nbc = (int64_t)(2 << 20) / (64 * (int64_t)esz);       // a 64-column slice of a block in 2 MiB
   return (int)((n + *nbc - 1) / *nbc);
@@ -727,6 +753,41 @@ int launch_csr_blocked(lspca_dtype vdt, const int64_t *rowptr, const int32_t *co
                          bk, rows, (const double *)V, ldv, k, nslices, (double *)Z, ldz);
     LSPCA_HIP(hipGetLastError());
   }
+  return LSPCA_OK;
+}
+
+// ---- Ut[c * ldt + i] = Y[i * ldy + c] (rows x k in, k x rows out; the
+// SPCA sketch transposed for the tall-skinny QR), through 64 x 64 LDS tiles
+template <typename T>
+__global__ __launch_bounds__(256) void k_rows_to_cols(const T *__restrict__ Y, int64_t rows, int k,
+                                                      int64_t ldy, T *__restrict__ Ut, int64_t ldt) {
+  __shared__ T tile[64][65];
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += 4) {
+    const int64_t i = i0 + r;
+    const int c = c0 + tx;
+    tile[r][tx] = (i < rows && c < k) ? Y[i * ldy + c] : T(0);
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int c = c0 + r;
+    const int64_t i = i0 + tx;
+    if (c < k && i < rows) Ut[(int64_t)c * ldt + i] = tile[tx][r];
+  }
+}
+
+int launch_rows_to_cols(lspca_dtype vdt, const void *Y, int64_t rows, int k, int64_t ldy, void *Ut, int64_t ldt,
+                        hipStream_t s) {
+  if (rows <= 0) return LSPCA_OK;
+  const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)((k + 63) / 64));
+  if (vdt == LSPCA_F32)
+    hipLaunchKernelGGL(k_rows_to_cols<float>, grid, 256, 0, s, (const float *)Y, rows, k, ldy, (float *)Ut, ldt);
+  else
+    hipLaunchKernelGGL(k_rows_to_cols<double>, grid, 256, 0, s, (const double *)Y, rows, k, ldy, (double *)Ut,
+                       ldt);
+  LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }
 

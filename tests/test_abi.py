@@ -170,6 +170,11 @@ def test_csr_argument_checks(lib):
     assert fit(P, P, P, L.F64, 4, 10, 5, 5, L.GAUSSIAN, 1, None, F, G, None) == -1      # k > m
     assert "min(m, n)" in lib.lspca_last_error().decode()
     assert fit(P, P, P, L.F64, 10, 10, 5, 3, L.GAUSSIAN, 1, None, None, G, None) == -1
+    sp = lib.spca_fit_csr
+    assert sp(P, P, P, L.F32, 1000, 1000, 5, 257, L.GAUSSIAN, 1, None, F, G) == -7           # QR block height
+    assert sp(P, P, P, L.F64, 1000, 1000, 5, 129, L.GAUSSIAN, 1, None, F, G) == -7
+    assert sp(P, P, P, L.F32, 10, 100, 5, 11, L.GAUSSIAN, 1, None, F, G) == -1              # k > m
+    assert sp(P, P, P, L.F32, 100, 100, 5, 10, L.GAUSSIAN, 1, None, None, G) == -1
     tr = lib.lspca_transform_csr
     assert tr(None, None, None, L.F32, 0, 10, 0, None, 3, None, None) == 0               # r = 0: no work
     assert tr(P, P, P, L.F32, 5, 10, 5, None, 3, F, None) == -1                          # V NULL

@@ -292,3 +292,74 @@ def test_full_size_sparse_workload_sampled(gpu_lib):
         bz = gamma(nz, U32) * (np.abs(Xi) @ np.abs(Vq))[0]
         assert np.all(np.abs(Zh[t] - zr) <= bz + 1e-300)
     _log("done")
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "sparse"])
+def test_unordered_rows(gpu_lib, kind):
+    """Rows whose columns are not in order: the Gaussian sketch takes the
+    row-parallel kernel instead of the column blocks; same bound."""
+    import torch
+    m, n, k, dtype = 1500, 9000, 40, "f32"                   # two column blocks of 8,192 features
+    rowptr, colidx, values, X64 = _case(m, n, dtype, 0.01, seed=12)
+    rng = np.random.default_rng(2)
+    ci2, v2 = colidx.copy(), values.copy()
+    for i in range(0, m, 2):
+        p = rowptr[i] + rng.permutation(rowptr[i + 1] - rowptr[i])
+        ci2[rowptr[i]:rowptr[i + 1]], v2[rowptr[i]:rowptr[i + 1]] = colidx[p], values[p]
+    om = P.omega(n, k, kind, 31, p=64, dtype=dtype)
+    ref = O.streaming_lazy_fit(X64, om, k)
+    bF, bG = pass_bound(X64, om, dtype)
+    for ci, vv in ((colidx, values), (ci2, v2)):
+        F = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+        G = torch.zeros((k, k), dtype=torch.float64, device="cuda")
+        gpu_lib.accumulate_csr(_dev_csr(gpu_lib, rowptr, ci, vv, n), k, kind, 31, F, G)
+        torch.cuda.synchronize()
+        assert np.all(np.abs(F.cpu().numpy() - ref["F"]) <= bF)
+        assert np.all(np.abs(G.cpu().numpy() - ref["G"]) <= bG)
+
+
+# ------------------------------------------------------------- SPCA (Alg. 1) --
+
+@pytest.mark.parametrize("m,n,k,kind", [(1037, 203, 17, "gaussian"), (129, 60, 7, "sparse"),
+                                        (3 * 128 + 5, 400, 20, "sparse")])
+def test_spca_fit_csr_f64_matches_oracle(gpu_lib, m, n, k, kind):
+    rowptr, colidx, values, X64 = _case(m, n, "f64", 0.2, seed=13)
+    V, s = gpu_lib.spca_fit_csr(_dev_csr(gpu_lib, rowptr, colidx, values, n), k, kind, 3)
+    ref = O.spca_fit(X64, P.omega(n, k, kind, 3, p=64), k)
+    assert O.principal_sines(ref["V"], V.cpu().numpy()).max() < 1e-10
+    assert np.max(np.abs(s.cpu().numpy() - ref["sigma"]) / ref["sigma"]) < 1e-10
+
+
+@pytest.mark.parametrize("m,n,k,kind,cap", [(2600, 512, 64, "sparse", 0), (1500, 9000, 40, "gaussian", 0),
+                                            (2999, 260, 24, "sparse", 3000)])
+def test_spca_fit_csr_f32_within_bound(gpu_lib, monkeypatch, m, n, k, kind, cap):
+    """FP32 values; a Gaussian Omega over two column blocks; several stripes."""
+    from tests.test_gpu_spca import _f_bound
+    if cap:
+        monkeypatch.setenv("LSPCA_CSR_STRIPE_NNZ", str(cap))
+    rowptr, colidx, values, X64 = _case(m, n, "f32", 0.05 if n < 5000 else 0.01, seed=14)
+    V, s = gpu_lib.spca_fit_csr(_dev_csr(gpu_lib, rowptr, colidx, values, n), k, kind, 11)
+    ref = O.spca_fit(X64, P.omega(n, k, kind, 11, p=64, dtype="f32"), k)
+    err = np.linalg.norm(_f_bound(X64, ref["Q"], k, "f32"))
+    s = s.cpu().numpy()
+    assert np.max(np.abs(s - ref["sigma"]) / ref["sigma"]) <= err / ref["sigma"][-1] + 1e-12
+    assert O.principal_sines(ref["V"], V.cpu().numpy()).max() <= subspace_tol(ref["sigma"][-1], err) + 1e-12
+
+
+def test_proposition_2_across_csr_fits(gpu_lib):
+    """Prop. 2 on sparse X: the GPU SPCA and Lazy SPCA bases span the same
+    subspace; Prop. 3: identical pairwise distances after projection."""
+    m, n, k = 3000, 350, 24
+    rowptr, colidx, values, _ = _case(m, n, "f64", 0.1, seed=15)
+    X = _dev_csr(gpu_lib, rowptr, colidx, values, n)
+    # Gaussian Omega: with n = 350 a very sparse Omega (p = 64) has an empty
+    # column with a few per cent probability, and the Lazy fit then reports
+    # ERANK (F has a zero row), as it should
+    Vs, _ = gpu_lib.spca_fit_csr(X, k, "gaussian", 8)
+    Vl, _ = gpu_lib.fit_csr(X, k, "gaussian", 8)
+    assert O.principal_sines(Vs.cpu().numpy(), Vl.cpu().numpy()).max() < 1e-10
+    Zs = gpu_lib.transform_csr(X, Vs).cpu().numpy()
+    Zl = gpu_lib.transform_csr(X, Vl).cpu().numpy()
+    pairs = np.random.default_rng(0).integers(0, m, size=(3000, 2))
+    ds, dl = O.pairwise_distances(Zs, pairs), O.pairwise_distances(Zl, pairs)
+    assert np.max(np.abs(ds - dl)) <= 1e-10 * np.max(ds)
