@@ -48,8 +48,8 @@ MEASURED_TRAFFIC = {
     },
     ("csr", 131_072, 98_450, 500, "sparse"): {   # k_csc_block, per row-block launch
         "sources": ["paper_1709_07175_amd/csrc/csr.hip", "paper_1709_07175_amd/csrc/common.h"],
-        "sha256": "b1a934a80fd6fa25b39c4a09b093766848ade507a358696164d0af8c3c59760a",
-        "bytes": 3.3356e+09,
+        "sha256": "749d646a9c8f55e873c13c510dbd99905b7f19a315bcc5024f7c93cb64c23249",
+        "bytes": 6.3313e+09,
     },
 }
 
@@ -256,7 +256,8 @@ def calibrate(torch, dev, gib):
 def csr_block_launches(rows, n, esz):
     """Row blocks of one stripe (the library's csc_shape): one k_csc_block
     launch each."""
-    rb_l2 = (2 << 20) // (64 * esz)
+    slice_cols = 128 if esz == 4 else 64                 # columns per XCD slice
+    rb_l2 = (4 << 20) // (slice_cols * esz)
     nb = -(-rows // rb_l2)
     nb = max(1, min(nb, max(1, (1 << 26) // n)))
     rb = -(-rows // nb)
@@ -266,7 +267,7 @@ def csr_block_launches(rows, n, esz):
 def csr_roofline(c, nnz, m, esz, launches, factor_ms):
     """The column sums F += Y^T X (k_csc_block, one launch per row block of a
     stripe). Per launch (the pass's totals over its launches): gathered bytes
-    = entries x k x value size (one sketch-row segment per entry and 64-column
+    = entries x k x value size (one sketch-row segment per entry and column
     slice); algorithmic HBM bytes = the entries (row index + value) once, the
     sketch rows once, F read and written once."""
     n, k = c["n"], c["k"]
