@@ -60,6 +60,23 @@ enum { OUT_ROWS = 0, OUT_T32 = 1, OUT_TSPLIT = 2 };
 #ifndef LSPCA_NT16_BK
 #define LSPCA_NT16_BK 64
 #endif
+// Row tile of the products whose B side is one column tile: the split-B
+// product with N > 128 (projection with k > 128) and with N <= 128, and the
+// unsplit product with N <= 128 (sketch). Larger row tiles cut the L2 reads
+// of the B side per byte of A.
+#ifndef LSPCA_NT16_PROJ_BM
+#define LSPCA_NT16_PROJ_BM 256
+#endif
+#ifndef LSPCA_NT16_PROJ_BM_NARROW
+#define LSPCA_NT16_PROJ_BM_NARROW 256
+#endif
+#ifndef LSPCA_NT16_SKETCH_BM
+#define LSPCA_NT16_SKETCH_BM 128
+#endif
+// Streaming (nontemporal) loads of A when A is read once.
+#ifndef LSPCA_NT16_NTA
+#define LSPCA_NT16_NTA 0
+#endif
 
 // One BM x BN tile of C at (m0, n0); the LDS it stages through is free
 // again on return, so a workgroup may call it for several tiles in turn.
@@ -109,7 +126,8 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
       const int64_t gr = m0 + r;
       if constexpr (VEC) {
         const int kk = k0 + kc < K ? k0 + kc : K - 8;
-        ra[sl][v] = *(const u16x8 *)(A + (gr < M ? gr : mlast) * lda + kk);
+        const u16x8 *src = (const u16x8 *)(A + (gr < M ? gr : mlast) * lda + kk);
+        ra[sl][v] = LSPCA_NT16_NTA ? __builtin_nontemporal_load(src) : *src;
       } else {
         ra[sl][v] = ld8(A + gr * lda + k0 + kc, gr < M && k0 + kc < K, K - k0 - kc);
       }
@@ -280,9 +298,15 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
         if (lane < 32) red[(wave >> 1) * BN + wn0 + j * 32 + lane] = mj;
       }
       __syncthreads();
+      // one row per 128 rows of A (nt16_row_tiles), the same maximum in each
+      // row this tile covers
       for (int t = tid; t < BN; t += 256)
-        if (n0 + t < N)
-          colmax[(m0 / BM) * (int64_t)N + n0 + t] = __float_as_uint(fmaxf(red[t], red[BN + t]));
+        if (n0 + t < N) {
+          const unsigned mv = __float_as_uint(fmaxf(red[t], red[BN + t]));
+#pragma unroll
+          for (int h = 0; h < BM / 128; ++h)
+            if (m0 + 128 * h < M) colmax[(m0 / 128 + h) * (int64_t)N + n0 + t] = mv;
+        }
     }
   }
 }
@@ -300,18 +324,36 @@ __global__ __launch_bounds__(256) void k_nt16(const uint16_t *__restrict__ A, in
 
 // FP16 split of the transposed FP32 sketch: column c (row of Yt) is scaled
 // by scale[c] (a power of two) and split, Yh = rn(s y), Yl = rn(s y - Yh).
-template <int DT>
+// VEC (ld a multiple of 8, 16-byte aligned rows): 8 elements of one column
+// per thread, two 16-byte loads and one 16-byte store per part.
+template <int DT, bool VEC>
 __global__ void k_split16(const float *__restrict__ Yt, int64_t count, int64_t ld,
                           const float *__restrict__ scale, uint16_t *__restrict__ Yh,
                           uint16_t *__restrict__ Yl) {
-  const int64_t e4 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
-  if (e4 >= count) return;
-  for (int e = 0; e < 4 && e4 + e < count; ++e) {
-    const int64_t idx = e4 + e;
-    const float y = Yt[idx] * (scale ? scale[idx / ld] : 1.f);
-    const uint16_t h = H16<DT>::from_f32(y);
-    Yh[idx] = h;
-    if (Yl) Yl[idx] = H16<DT>::from_f32(y - H16<DT>::to_f32(h));
+  if constexpr (VEC) {
+    const int64_t e8 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+    if (e8 >= count) return;
+    const float sc = scale ? scale[e8 / ld] : 1.f;
+    const f32x4 a = *(const f32x4 *)(Yt + e8), b = *(const f32x4 *)(Yt + e8 + 4);
+    u16x8 h, l;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const float y = (e < 4 ? a[e & 3] : b[e & 3]) * sc;
+      h[e] = H16<DT>::from_f32(y);
+      l[e] = H16<DT>::from_f32(y - H16<DT>::to_f32(h[e]));
+    }
+    *(u16x8 *)(Yh + e8) = h;
+    if (Yl) *(u16x8 *)(Yl + e8) = l;
+  } else {
+    const int64_t e4 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (e4 >= count) return;
+    for (int e = 0; e < 4 && e4 + e < count; ++e) {
+      const int64_t idx = e4 + e;
+      const float y = Yt[idx] * (scale ? scale[idx / ld] : 1.f);
+      const uint16_t h = H16<DT>::from_f32(y);
+      Yh[idx] = h;
+      if (Yl) Yl[idx] = H16<DT>::from_f32(y - H16<DT>::to_f32(h));
+    }
   }
 }
 
@@ -335,6 +377,10 @@ __global__ void k_split16(const float *__restrict__ Yt, int64_t count, int64_t l
 #endif
 #ifndef LSPCA_TN16_BK
 #define LSPCA_TN16_BK 64
+#endif
+// Streaming (nontemporal) loads of X
+#ifndef LSPCA_TN16_NTX
+#define LSPCA_TN16_NTX 0
 #endif
 
 template <int DT, int BM, int BN, bool REFINE, bool VEC>
@@ -401,7 +447,8 @@ __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
         if constexpr (VEC) {
           const int64_t rr = gr < rows ? gr : rows - 1;
           const int cc = c < Nj ? c : Nj - 8;
-          rb[sl][p][h] = *(const u16x8 *)(X + rr * ldx + cc);
+          const u16x8 *src = (const u16x8 *)(X + rr * ldx + cc);
+          rb[sl][p][h] = LSPCA_TN16_NTX ? __builtin_nontemporal_load(src) : *src;
         } else {
           u16x8 x = {};
           if (gr < rend) {
@@ -538,8 +585,10 @@ template <int DT, bool SPLITB, int OUT>
 static int nt16_n(const uint16_t *A, int64_t lda, const uint16_t *Bh, const uint16_t *Bl,
                   int64_t ldb, float *C, int64_t ldc, int64_t M, int N, int K, unsigned *colmax,
                   uint16_t *Ch, uint16_t *Cl, hipStream_t s) {
-  if (N > 128) return nt16_typed<DT, 128, 256, SPLITB, OUT>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
-  return nt16_typed<DT, 128, 128, SPLITB, OUT>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
+  constexpr int BMW = SPLITB ? LSPCA_NT16_PROJ_BM : 128;
+  constexpr int BMN = SPLITB ? LSPCA_NT16_PROJ_BM_NARROW : LSPCA_NT16_SKETCH_BM;
+  if (N > 128) return nt16_typed<DT, BMW, 256, SPLITB, OUT>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
+  return nt16_typed<DT, BMN, 128, SPLITB, OUT>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
 }
 
 template <int DT>
@@ -556,7 +605,7 @@ int launch_nt16(lspca_dtype dt, const void *A, int64_t lda, const void *Bh, cons
                 int64_t ldb, float *C, int64_t ldc, int64_t M, int N, int K, unsigned *colmax,
                 void *Ch, void *Cl, int mode, hipStream_t s) {
   if (M <= 0 || N <= 0) return LSPCA_OK;
-  if ((M + 127) / 128 > 0x7fffffff) {
+  if ((M + 127) / 128 > 0x7fffffff / 2) {
     set_error("nt16 product: too many row tiles");
     return LSPCA_EINVAL;
   }
@@ -624,11 +673,16 @@ int launch_proj_batch16(lspca_dtype dt, const ProjTable *tab, const void *VTh, c
 int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld, const float *scale,
                    void *Yh, void *Yl, hipStream_t s) {
   const int64_t count = rows_k * ld;
-  const unsigned grid = (unsigned)((count / 4 + 256) / 256);
-  if (dt == LSPCA_BF16)
-    hipLaunchKernelGGL(k_split16<LSPCA_BF16>, grid, 256, 0, s, Yt, count, ld, scale, (uint16_t *)Yh, (uint16_t *)Yl);
-  else
-    hipLaunchKernelGGL(k_split16<LSPCA_F16>, grid, 256, 0, s, Yt, count, ld, scale, (uint16_t *)Yh, (uint16_t *)Yl);
+  const bool vec = ld % 8 == 0 && (uintptr_t)Yt % 16 == 0 && (uintptr_t)Yh % 16 == 0 &&
+                   (uintptr_t)Yl % 16 == 0;
+  const unsigned grid = vec ? (unsigned)((count / 8 + 255) / 256) : (unsigned)((count / 4 + 256) / 256);
+  if (dt == LSPCA_BF16) {
+    if (vec) hipLaunchKernelGGL((k_split16<LSPCA_BF16, true>), grid, 256, 0, s, Yt, count, ld, scale, (uint16_t *)Yh, (uint16_t *)Yl);
+    else hipLaunchKernelGGL((k_split16<LSPCA_BF16, false>), grid, 256, 0, s, Yt, count, ld, scale, (uint16_t *)Yh, (uint16_t *)Yl);
+  } else {
+    if (vec) hipLaunchKernelGGL((k_split16<LSPCA_F16, true>), grid, 256, 0, s, Yt, count, ld, scale, (uint16_t *)Yh, (uint16_t *)Yl);
+    else hipLaunchKernelGGL((k_split16<LSPCA_F16, false>), grid, 256, 0, s, Yt, count, ld, scale, (uint16_t *)Yh, (uint16_t *)Yl);
+  }
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }
@@ -636,17 +690,21 @@ int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld, 
 // X-column tile: 256 when the Y side is one 128-column tile (halves the
 // re-reads of Y per X column), else 128.
 #ifndef LSPCA_TN16_WIDE_BN
-#define LSPCA_TN16_WIDE_BN 256
+#define LSPCA_TN16_WIDE_BN 512
 #endif
 #ifndef LSPCA_TN16_WIDE_ALL
 #define LSPCA_TN16_WIDE_ALL 0
+#endif
+// X-column tile when the Y side is one 256-column tile
+#ifndef LSPCA_TN16_BN256
+#define LSPCA_TN16_BN256 256
 #endif
 
 template <int DT, int BM, bool REFINE>
 static int tn16_typed(const uint16_t *Yh, const uint16_t *Yl, int64_t ysb, int64_t ysc, int64_t ylim,
                       const uint16_t *X, int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
                       hipStream_t s) {
-  constexpr int BN = (BM <= 128 || LSPCA_TN16_WIDE_ALL) ? LSPCA_TN16_WIDE_BN : 128;
+  constexpr int BN = (BM <= 128 || LSPCA_TN16_WIDE_ALL) ? LSPCA_TN16_WIDE_BN : LSPCA_TN16_BN256;
   int64_t chunk = (rows + splits - 1) / splits;
   chunk = (chunk + 63) / 64 * 64;                 // a multiple of every K-tile depth
   dim3 grid((unsigned)((Nj + BN - 1) / BN), (unsigned)((Mi + BM - 1) / BM), (unsigned)splits);

@@ -750,6 +750,40 @@ int trinv_t(const double *R, int k, double *XT, double *scratch, hipStream_t s) 
   return LSPCA_OK;
 }
 
+// The preconditioner of the small SVD (Cholesky QR of R^T) is applied when
+// R is graded: max |R_ii| >= kPrecondRatio min |R_ii|. The ratio of R's
+// extreme diagonal entries follows the spread of F's singular values; on
+// flat or slowly decaying spectra (ratio below 4) one-sided Jacobi on R
+// takes the same number of sweeps, or one more, without it, so its two
+// Cholesky QR passes would only cost time; on graded ones it saves 3 to 15
+// sweeps (measured on k = 128 with spectra from flat to 1e6).
+constexpr double kPrecondRatio = 4.0;
+
+// flag[0] = 1 when max_i |R_ii| >= ratio * min_i |R_ii| (R row-major k x k);
+// one workgroup of 256 threads.
+__global__ __launch_bounds__(256) void k_diag_graded(const double *__restrict__ R, int k, double ratio,
+                                                     int *__restrict__ flag) {
+  __shared__ double smax[256], smin[256];
+  const int t = threadIdx.x;
+  double mx = 0.0, mn = INFINITY;
+  for (int i = t; i < k; i += 256) {
+    const double d = fabs(R[(int64_t)i * k + i]);
+    mx = fmax(mx, d);
+    mn = fmin(mn, d);
+  }
+  smax[t] = mx;
+  smin[t] = mn;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) {
+      smax[t] = fmax(smax[t], smax[t + w]);
+      smin[t] = fmin(smin[t], smin[t + w]);
+    }
+    __syncthreads();
+  }
+  if (t == 0) flag[0] = smax[0] >= ratio * smin[0] ? 1 : 0;
+}
+
 static bool debug_on() {
   static int v = -1;
   if (v < 0) {
@@ -944,8 +978,17 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
     // R^T = Q2 R2 (Cholesky QR twice on the k x k matrix R^T), R2^T has the
     // same left singular vectors U_R and singular values as R, and one-sided
     // Jacobi on the columns of R2^T (= the rows of R2) needs far fewer sweeps
-    // than on R (Drmac and Veselic, SIAM J. Matrix Anal. Appl. 29, 2008).
+    // than on R when R is graded (Drmac and Veselic, SIAM J. Matrix Anal.
+    // Appl. 29, 2008); applied only then (kPrecondRatio).
     bool pre = !shifted;
+    if (pre) {
+      hipLaunchKernelGGL(k_diag_graded, 1, 256, 0, s, Rall, k, kPrecondRatio, dflag + 2);
+      LSPCA_HIP(hipGetLastError());
+      LSPCA_HIP(hipMemcpyAsync(hflag + 2, dflag + 2, sizeof(int), hipMemcpyDeviceToHost, s));
+      LSPCA_HIP(hipStreamSynchronize(s));
+      pre = hflag[2] != 0;
+      if (debug_on()) fprintf(stderr, "[lspca] small SVD preconditioner %s\n", pre ? "on" : "off");
+    }
     if (pre) {
       double *T = prebuf;                              // 4 k x k scratch matrices
       double *S1 = T + kk, *P = T + 2 * kk, *R2 = T + 3 * kk;

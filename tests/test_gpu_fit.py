@@ -188,16 +188,23 @@ def test_rank_deficient_X_gives_erank(gpu_lib):
 
 # ------------------------------------------------------------ small stage --
 
-@pytest.mark.parametrize("k,n", [(1, 9), (7, 40), (50, 1000), (128, 1500), (130, 700), (256, 4096),
-                                 (300, 700), (520, 1100)])
-def test_factor_matches_oracle_svd(gpu_lib, k, n):
+@pytest.mark.parametrize("k,n,spectrum", [(1, 9, "graded"), (7, 40, "graded"), (50, 1000, "graded"),
+                                          (128, 1500, "graded"), (130, 700, "graded"),
+                                          (256, 4096, "graded"), (300, 700, "graded"),
+                                          (520, 1100, "graded"), (50, 1000, "flat"), (128, 1500, "flat"),
+                                          (256, 4096, "flat"), (520, 1100, "flat")])
+def test_factor_matches_oracle_svd(gpu_lib, k, n, spectrum):
     """Truncated SVD of a generated F = U diag(d) W^T with known, separated
-    singular values (condition 1e3): V columns and D to 1e-10."""
+    singular values, graded (condition 1e3: the preconditioned Jacobi) or
+    flat (1.65 down to 1: Jacobi on R directly): V columns and D to 1e-10."""
     import torch
     rng = np.random.default_rng(k)
     Uf = random_orthonormal_np(k, k, rng)
     W = random_orthonormal_np(n, k, rng)
-    d = np.geomspace(1e3, 1.0, k) if k > 1 else np.array([3.0])
+    if k == 1:
+        d = np.array([3.0])
+    else:
+        d = np.geomspace(1e3, 1.0, k) if spectrum == "graded" else np.linspace(1.65, 1.0, k)
     F = (Uf * d) @ W.T
     V, s = gpu_lib.factor(torch.from_numpy(F).cuda())
     V, s = V.cpu().numpy(), s.cpu().numpy()
