@@ -380,11 +380,11 @@ def csr_main(args, lib, torch):
         return sum(p[which][key] for p in phases) / len(phases)
 
     # stripes of the pass (the library's plan: entries per stripe <= 2^28 on
-    # 64-row boundaries, rows <= the 2 GiB sketch budget)
+    # 64-row boundaries, rows <= the 4 GiB sketch budget)
     rph = rp.cpu().numpy()
     esz = vv.element_size()
     starts, r0 = [0], 0
-    rows_cap = min((2 << 30) // (k * esz), 1 << 24)
+    rows_cap = min((4 << 30) // (k * esz), 1 << 24)
     while r0 < m:
         r1 = r0 + 64
         while r1 < m and r1 + 64 - r0 <= rows_cap and rph[min(r1 + 64, m)] - rph[r0] <= (1 << 28):
@@ -538,7 +538,8 @@ def main():
                                f"{cfg['kind']} Omega, k={k}",
                    "m": m, "n": n, "k": k, "x_bytes": xbytes, "parallelism": "single-gpu"},
         "phases_ms": {"fit_total": round(fit_ms, 4), "omega": round(avg("omega_ms"), 4),
-                      "sketch": round(sketch_ms, 4), "factor_F_G": round(factor_ms, 4),
+                      "sketch": round(sketch_ms, 4), "layout": round(avg("layout_ms"), 4),
+                      "factor_F_G": round(factor_ms, 4),
                       "reduce": round(avg("reduce_ms"), 4), "small_fp64": round(small_ms, 4),
                       "transform": round(tr_ms, 4)},
         "fit_x_stream_GBs": round(xbytes / (fit_ms * 1e-3) / 1e9, 3),

@@ -112,7 +112,7 @@ typedef struct lspca_opts {
                            only down to about sqrt(u) D_1) */
   int32_t reserved;     /* 0 */
   int64_t stripe_rows;  /* rows per stripe of the pass (Algorithm 4's slices);
-                           0 = auto (a 2 GiB sketch stripe) */
+                           0 = auto (a 4 GiB sketch stripe) */
 } lspca_opts;
 
 /* Per-phase device times (ms) of the last call on this thread that had
@@ -127,7 +127,8 @@ typedef struct lspca_timings {
   double pass2_ms;      /* spca_fit: F = Q^T X */
   double transform_ms;  /* Z = X V */
   double total_ms;      /* whole call */
-  double layout_ms;     /* sparse X: column-order (CSC) build of each stripe */
+  double layout_ms;     /* sparse X: column-order (CSC) build of each stripe;
+                           FP16 X: the sketch scaled and split into 16-bit parts */
 } lspca_timings;
 
 /* Version string, e.g. "lspca 0.1 gfx950". */

@@ -217,9 +217,10 @@ static PassPlan plan_pass(lspca_dtype xdt, int64_t m, int64_t n, int k, bool wan
   p.cap = 0;
   p.gather = kind == LSPCA_OMEGA_VERY_SPARSE && sparse_sketch_ok(xdt, n, k, sp, &p.cap);
   p.esz = xdt == LSPCA_F64 ? 8 : 4;
-  // Y stripe bytes: 2 GiB, or LSPCA_STRIPE_BYTES (a tuning and test knob:
-  // small values exercise the multi-stripe paths on small inputs)
-  int64_t budget = (int64_t)2 << 30;
+  // Y stripe bytes: 4 GiB (under 2% of the device memory), or
+  // LSPCA_STRIPE_BYTES (a tuning and test knob: small values exercise the
+  // multi-stripe paths on small inputs)
+  int64_t budget = (int64_t)4 << 30;
   if (const char *e = getenv("LSPCA_STRIPE_BYTES")) {
     const long long v = atoll(e);
     if (v > 0) budget = v;
@@ -326,15 +327,24 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
       } else {
         LSPCA_TRY(launch_nt16(xdt, Xs, ldx, OmT, nullptr, n, y32 ? (float *)Y : nullptr, rows, rows,
                               k, (int)n, fp16 ? colpart : nullptr, Yh, Ylo, y32 ? 1 : 2, s));
-        if (fp16) LSPCA_TRY(launch_colmax_reduce(colpart, nt16_row_tiles(rows), k, colmax, s));
       }
-      if (fp16) LSPCA_TRY(launch_col_scales(colmax, k, scale, inv, s));
-      if (y32) LSPCA_TRY(launch_split16(xdt, (const float *)Y, k, rows, fp16 ? scale : nullptr, Yh, Ylo, s));
       tm.mark(PH_SKETCH);
+      // FP32 sketch -> column scales (FP16) and 16-bit parts (timed as the
+      // layout phase); without a hook the FP16 split happens inside the F
+      // product, as its tiles are loaded
+      const bool fused = fp16 && !hook;
+      if (fp16 && !pl.gather) LSPCA_TRY(launch_colmax_reduce(colpart, nt16_row_tiles(rows), k, colmax, s));
+      if (fp16) LSPCA_TRY(launch_col_scales(colmax, k, scale, inv, s));
+      if (y32 && !fused)
+        LSPCA_TRY(launch_split16(xdt, (const float *)Y, k, rows, fp16 ? scale : nullptr, Yh, Ylo, s));
+      if (y32) tm.mark(PH_LAYOUT);
       if (hook) LSPCA_TRY((*hook)(Y, rows, rows, true));
-      // the gather kernel writes its split sketch in 8-row blocks
-      LSPCA_TRY(launch_tn16(xdt, Yh, Ylo, rows, Xs, ldx, (float *)PF, rows, k, (int)n, sf, s,
-                            pl.gather && !y32));
+      if (fused)
+        LSPCA_TRY(launch_tn16_f32y(xdt, (const float *)Y, scale, rows, refine, Xs, ldx, (float *)PF, rows, k,
+                                   (int)n, sf, s));
+      else  // the gather kernel writes its split sketch in 8-row blocks
+        LSPCA_TRY(launch_tn16(xdt, Yh, Ylo, rows, Xs, ldx, (float *)PF, rows, k, (int)n, sf, s,
+                              pl.gather && !y32));
       tm.mark(PH_FACTOR);
       const int accum = (r0 > 0) ? 1 : acc;
       LSPCA_TRY(launch_reduce_add(LSPCA_F32, PF, sf, (int64_t)k * n, Fdst, accum, s,
@@ -482,7 +492,7 @@ static int plan_csr(const int64_t *rowptr, const int32_t *colidx, lspca_dtype vd
                     int64_t nnz, int k, int kind, bool want_g, const Opts &o, Workspace &ws, CsrPlan &pl) {
   hipStream_t s = o.stream;
   const size_t esz = dtype_size(vdt);
-  int64_t budget = (int64_t)2 << 30;                 // Y bytes, as the dense pass
+  int64_t budget = (int64_t)4 << 30;                 // Y bytes, as the dense pass
   if (const char *v = getenv("LSPCA_STRIPE_BYTES")) {
     const long long b = atoll(v);
     if (b > 0) budget = b;

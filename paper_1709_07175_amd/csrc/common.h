@@ -171,6 +171,12 @@ int launch_nt16(lspca_dtype dt, const void *A, int64_t lda, const void *Bh,
 int launch_tn16(lspca_dtype dt, const void *Yh, const void *Yl, int64_t ldyt,
                 const void *X, int64_t ldx, float *P, int64_t rows, int Mi, int Nj,
                 int splits, hipStream_t s, bool yblocked = false);
+// The same partials from the transposed FP32 sketch Yt[i*ldyt + r] (FP16 X
+// only): column i scaled by scale[i] (NULL: 1) and split into 16-bit parts
+// as launch_split16 does, on the way into the product (refine: both parts).
+int launch_tn16_f32y(lspca_dtype dt, const float *Yt, const float *scale, int64_t ldyt, bool refine,
+                     const void *X, int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
+                     hipStream_t s);
 // Scale row c of Yt (rows_k x ld) by scale[c] and split into 16-bit parts.
 int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld,
                    const float *scale, void *Yh, void *Yl, hipStream_t s);

@@ -383,13 +383,14 @@ __global__ void k_split16(const float *__restrict__ Yt, int64_t count, int64_t l
 #define LSPCA_TN16_NTX 0
 #endif
 
-template <int DT, int BM, int BN, bool REFINE, bool VEC>
+template <int DT, int BM, int BN, bool REFINE, bool VEC, bool YF>
 __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
                                               const uint16_t *__restrict__ Yl, int64_t ysb, int64_t ysc,
                                               int64_t ylim,
                                               const uint16_t *__restrict__ X, int64_t ldx,
                                               float *__restrict__ P, int64_t rows, int Mi, int Nj,
-                                              int64_t chunk) {
+                                              int64_t chunk, const float *__restrict__ Yf,
+                                              const float *__restrict__ yscale) {
   constexpr int NPART = REFINE ? 2 : 1;
   constexpr int BKW = LSPCA_TN16_BK;
   constexpr int BK = (NPART * BM + BN) * (BKW + 8) * 2 * 2 <= 160 * 1024 ? BKW : 32;
@@ -397,9 +398,10 @@ __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
   constexpr int WM = BM / 2, WN = BN / 2, TM = WM / 32, TN = WN / 32;
   constexpr int AV = BM * BK / 8 / 256;               // u16x8 loads per part per thread
   constexpr int XP = BN * BK / 16 / 256;              // 2 x 8 pieces of X per thread
-  // register stages: one fewer for the wide refined tile (its ring would not
-  // fit the register file next to the accumulators)
-  constexpr int R = (BN > 128 && REFINE && LSPCA_TN16_STAGES > 2) ? 2 : LSPCA_TN16_STAGES;
+  // register stages: one fewer for the wide refined tile and for 256
+  // accumulators per lane (the ring would not fit the register file next to
+  // the accumulators)
+  constexpr int R = (((BN > 128 && REFINE) || TM * TN >= 16) && LSPCA_TN16_STAGES > 2) ? 2 : LSPCA_TN16_STAGES;
   static_assert(XP >= 1 && AV >= 1, "tile too small");
   __shared__ uint16_t As[2][NPART * BM * LD];
   __shared__ uint16_t Bs[2][BN * LD];
@@ -412,11 +414,46 @@ __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
   const int64_t rbeg = (int64_t)bz * chunk;
   const int64_t rend = rbeg + chunk < rows ? rbeg + chunk : rows;
 
-  u16x8 ra[R][NPART][AV];
+  u16x8 ra[R][YF ? 1 : NPART][AV];
+  f32x4 rf[R][YF ? AV : 1][2];                        // YF: 8 FP32 rows of one column
   u16x8 rb[R][XP][2];
-  auto load = [&](int sl, int64_t r0) {
+  float scv[YF ? AV : 1];                             // YF: the scale of each loaded column
+  if constexpr (YF) {
 #pragma unroll
-    for (int part = 0; part < NPART; ++part) {
+    for (int v = 0; v < AV; ++v) {
+      const int i = (tid + v * 256) / (BK / 8);
+      scv[v] = yscale ? yscale[i0 + i < Mi ? i0 + i : Mi - 1] : 1.f;
+    }
+  }
+  auto load = [&](int sl, int64_t r0) {
+    if constexpr (YF) {
+#pragma unroll
+      for (int v = 0; v < AV; ++v) {
+        const int idx = tid + v * 256, i = idx / (BK / 8), kr = (idx % (BK / 8)) * 8;
+        const int64_t gr = r0 + kr;
+        if constexpr (VEC) {
+          const int ii = i0 + i < Mi ? i0 + i : Mi - 1;
+          const int64_t rr = gr + 8 <= ylim ? gr : ylim - 8;      // gr, ylim: multiples of 8
+          const float *src = Yf + (rr >> 3) * ysb + (int64_t)ii * ysc;
+          rf[sl][v][0] = *(const f32x4 *)src;
+          rf[sl][v][1] = *(const f32x4 *)(src + 4);
+        } else {
+          f32x4 a = {}, b = {};
+          if (i0 + i < Mi) {
+            const float *src = Yf + (gr >> 3) * ysb + (int64_t)(i0 + i) * ysc;   // gr % 8 == 0
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              a[e] = gr + e < rend ? src[e] : 0.f;
+              b[e] = gr + 4 + e < rend ? src[4 + e] : 0.f;
+            }
+          }
+          rf[sl][v][0] = a;
+          rf[sl][v][1] = b;
+        }
+      }
+    }
+#pragma unroll
+    for (int part = 0; part < (YF ? 0 : NPART); ++part) {
       const uint16_t *Ysrc = part ? Yl : Yh;
 #pragma unroll
       for (int v = 0; v < AV; ++v) {
@@ -463,8 +500,26 @@ __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
   };
   auto store = [&](int sl, int buf, int64_t r0) {
     const bool tail = VEC && r0 + BK > rend;            // uniform: the chunk's last K tile
+    if constexpr (YF) {
+      // scale and split on the way to LDS: Yh = rn(s y), Yl = rn(s y - Yh)
 #pragma unroll
-    for (int part = 0; part < NPART; ++part)
+      for (int v = 0; v < AV; ++v) {
+        const int idx = tid + v * 256, i = idx / (BK / 8), kr = (idx % (BK / 8)) * 8;
+        u16x8 h, l;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          float y = e < 4 ? rf[sl][v][0][e & 3] : rf[sl][v][1][e & 3];
+          if (tail && r0 + kr + e >= rend) y = 0.f;
+          y *= scv[v];
+          h[e] = H16<DT>::from_f32(y);
+          l[e] = H16<DT>::from_f32(y - H16<DT>::to_f32(h[e]));
+        }
+        *(u16x8 *)&As[buf][i * LD + kr] = h;
+        if constexpr (REFINE) *(u16x8 *)&As[buf][(BM + i) * LD + kr] = l;
+      }
+    }
+#pragma unroll
+    for (int part = 0; part < (YF ? 0 : NPART); ++part)
 #pragma unroll
       for (int v = 0; v < AV; ++v) {
         const int idx = tid + v * 256, i = idx / (BK / 8), kr = (idx % (BK / 8)) * 8;
@@ -700,23 +755,24 @@ int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld, 
 #define LSPCA_TN16_BN256 256
 #endif
 
-template <int DT, int BM, bool REFINE>
+template <int DT, int BM, bool REFINE, bool YF>
 static int tn16_typed(const uint16_t *Yh, const uint16_t *Yl, int64_t ysb, int64_t ysc, int64_t ylim,
                       const uint16_t *X, int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
-                      hipStream_t s) {
+                      hipStream_t s, const float *Yf = nullptr, const float *yscale = nullptr) {
   constexpr int BN = (BM <= 128 || LSPCA_TN16_WIDE_ALL) ? LSPCA_TN16_WIDE_BN : LSPCA_TN16_BN256;
   int64_t chunk = (rows + splits - 1) / splits;
   chunk = (chunk + 63) / 64 * 64;                 // a multiple of every K-tile depth
   dim3 grid((unsigned)((Nj + BN - 1) / BN), (unsigned)((Mi + BM - 1) / BM), (unsigned)splits);
-  const bool vec = (ysc % 8 == 0) && (ylim % 8 == 0) && ((uintptr_t)Yh % 16 == 0) &&
-                   (!REFINE || (uintptr_t)Yl % 16 == 0) && (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0) &&
+  const bool yvec = YF ? (uintptr_t)Yf % 16 == 0
+                       : (uintptr_t)Yh % 16 == 0 && (!REFINE || (uintptr_t)Yl % 16 == 0);
+  const bool vec = (ysc % 8 == 0) && (ylim % 8 == 0) && yvec && (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0) &&
                    (Nj % 8 == 0) && Nj >= 8 && ylim >= 8;
   if (vec)
-    hipLaunchKernelGGL((k_tn16<DT, BM, BN, REFINE, true>), grid, dim3(256), 0, s, Yh, Yl, ysb, ysc, ylim, X, ldx,
-                       P, rows, Mi, Nj, chunk);
+    hipLaunchKernelGGL((k_tn16<DT, BM, BN, REFINE, true, YF>), grid, dim3(256), 0, s, Yh, Yl, ysb, ysc, ylim, X,
+                       ldx, P, rows, Mi, Nj, chunk, Yf, yscale);
   else
-    hipLaunchKernelGGL((k_tn16<DT, BM, BN, REFINE, false>), grid, dim3(256), 0, s, Yh, Yl, ysb, ysc, ylim, X, ldx,
-                       P, rows, Mi, Nj, chunk);
+    hipLaunchKernelGGL((k_tn16<DT, BM, BN, REFINE, false, YF>), grid, dim3(256), 0, s, Yh, Yl, ysb, ysc, ylim, X,
+                       ldx, P, rows, Mi, Nj, chunk, Yf, yscale);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
 }
@@ -726,11 +782,11 @@ static int tn16_dt(const uint16_t *Yh, const uint16_t *Yl, int64_t ysb, int64_t 
                    const uint16_t *X, int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
                    hipStream_t s) {
   if (Mi > 128) {
-    if (Yl) return tn16_typed<DT, 256, true>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
-    return tn16_typed<DT, 256, false>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
+    if (Yl) return tn16_typed<DT, 256, true, false>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
+    return tn16_typed<DT, 256, false, false>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
   }
-  if (Yl) return tn16_typed<DT, 128, true>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
-  return tn16_typed<DT, 128, false>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
+  if (Yl) return tn16_typed<DT, 128, true, false>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
+  return tn16_typed<DT, 128, false, false>(Yh, Yl, ysb, ysc, ylim, X, ldx, P, rows, Mi, Nj, splits, s);
 }
 
 int launch_tn16(lspca_dtype dt, const void *Yh, const void *Yl, int64_t ldyt, const void *X,
@@ -748,6 +804,23 @@ int launch_tn16(lspca_dtype dt, const void *Yh, const void *Yl, int64_t ldyt, co
                               ldx, P, rows, Mi, Nj, splits, s);
   set_error("tn16 product: dtype %d", (int)dt);
   return LSPCA_ENOTSUP;
+}
+
+int launch_tn16_f32y(lspca_dtype dt, const float *Yt, const float *scale, int64_t ldyt, bool refine,
+                     const void *X, int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
+                     hipStream_t s) {
+  if (Mi <= 0 || Nj <= 0 || splits <= 0) return LSPCA_OK;
+  if (dt != LSPCA_F16) {
+    set_error("tn16 product from an FP32 sketch: dtype %d (FP16 only)", (int)dt);
+    return LSPCA_ENOTSUP;
+  }
+  const uint16_t *Xh = (const uint16_t *)X;
+  if (Mi > 128) {
+    if (refine) return tn16_typed<LSPCA_F16, 256, true, true>(nullptr, nullptr, 8, ldyt, ldyt, Xh, ldx, P, rows, Mi, Nj, splits, s, Yt, scale);
+    return tn16_typed<LSPCA_F16, 256, false, true>(nullptr, nullptr, 8, ldyt, ldyt, Xh, ldx, P, rows, Mi, Nj, splits, s, Yt, scale);
+  }
+  if (refine) return tn16_typed<LSPCA_F16, 128, true, true>(nullptr, nullptr, 8, ldyt, ldyt, Xh, ldx, P, rows, Mi, Nj, splits, s, Yt, scale);
+  return tn16_typed<LSPCA_F16, 128, false, true>(nullptr, nullptr, 8, ldyt, ldyt, Xh, ldx, P, rows, Mi, Nj, splits, s, Yt, scale);
 }
 
 // Per-column power-of-two scales for FP16 operands: scale[c] = 2^e with
