@@ -9,11 +9,12 @@
 //          writes Y transposed (Yt, rows contiguous) for k_tn16, and can
 //          record max |C| per column (for FP16 scaling).
 //  k_tn16: P[s][M x N] (FP32) = sum over rows r of chunk s of
-//          (Y_hi + Y_lo)[r][i] * X[r][j]: F = Y^T X with the FP32 sketch Y
-//          split on load into 16-bit parts, Y = Y_hi + Y_lo (refinement) or
-//          Y_hi alone; each column i of Y scaled by an exact power of two
-//          first (FP16 range). Both LDS tiles are row-index contiguous, so
-//          every MFMA fragment is one 16-byte read.
+//          (Y_hi + Y_lo)[r][i] * X[r][j]: F = Y^T X with the sketch in
+//          16-bit parts, Y = Y_hi + Y_lo (refinement) or Y_hi alone, either
+//          given split (BF16) or split from the FP32 sketch as its tiles are
+//          loaded, each column i scaled by an exact power of two first (FP16
+//          range). Both LDS tiles are row-index contiguous, so every MFMA
+//          fragment is one 16-byte read.
 #include "common.h"
 
 namespace lspca {
@@ -73,10 +74,6 @@ enum { OUT_ROWS = 0, OUT_T32 = 1, OUT_TSPLIT = 2 };
 #ifndef LSPCA_NT16_SKETCH_BM
 #define LSPCA_NT16_SKETCH_BM 128
 #endif
-// Streaming (nontemporal) loads of A when A is read once.
-#ifndef LSPCA_NT16_NTA
-#define LSPCA_NT16_NTA 0
-#endif
 
 // One BM x BN tile of C at (m0, n0); the LDS it stages through is free
 // again on return, so a workgroup may call it for several tiles in turn.
@@ -126,8 +123,7 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
       const int64_t gr = m0 + r;
       if constexpr (VEC) {
         const int kk = k0 + kc < K ? k0 + kc : K - 8;
-        const u16x8 *src = (const u16x8 *)(A + (gr < M ? gr : mlast) * lda + kk);
-        ra[sl][v] = LSPCA_NT16_NTA ? __builtin_nontemporal_load(src) : *src;
+        ra[sl][v] = *(const u16x8 *)(A + (gr < M ? gr : mlast) * lda + kk);
       } else {
         ra[sl][v] = ld8(A + gr * lda + k0 + kc, gr < M && k0 + kc < K, K - k0 - kc);
       }
@@ -358,12 +354,15 @@ __global__ void k_split16(const float *__restrict__ Yt, int64_t count, int64_t l
 }
 
 // ------------------------------------------------------------------- TN16 --
-// Tile: BM (columns of Y) x 128 (columns of X) x BK rows; 4 waves as 2 x 2.
+// Tile: BM (columns of Y) x BN (columns of X) x BK rows; 4 waves as 2 x 2.
 // Y arrives transposed and already split into 16-bit parts Yh, Yl (Yl NULL
 // without refinement), 8 consecutive rows of one column contiguous: element
 // (i, r) at (r / 8) * ysb + i * ysc + r % 8 (transposed: ysb = 8, ysc = the
 // leading dimension; blocked in 8-row blocks: ysb = 8 * columns, ysc = 8),
-// rows valid up to ylim, so its tiles go to LDS with 16-byte copies. X (16-bit rows,
+// rows valid up to ylim, so its tiles go to LDS with 16-byte copies; or (YF)
+// as the FP32 sketch Yf in the same indexing, each 8-row piece scaled by
+// yscale[i] (NULL: 1) and split into the two parts on its way to LDS (the
+// arithmetic of k_split16). X (16-bit rows,
 // leading dimension ldx): each thread loads pieces of 2 rows x 8 columns
 // and transposes them in registers into eight 2-row pieces of the
 // column-major LDS tile Bs[j][r]. Both LDS tiles are row-index contiguous,
@@ -377,10 +376,6 @@ __global__ void k_split16(const float *__restrict__ Yt, int64_t count, int64_t l
 #endif
 #ifndef LSPCA_TN16_BK
 #define LSPCA_TN16_BK 64
-#endif
-// Streaming (nontemporal) loads of X
-#ifndef LSPCA_TN16_NTX
-#define LSPCA_TN16_NTX 0
 #endif
 
 template <int DT, int BM, int BN, bool REFINE, bool VEC, bool YF>
@@ -484,8 +479,7 @@ __global__ __launch_bounds__(256) void k_tn16(const uint16_t *__restrict__ Yh,
         if constexpr (VEC) {
           const int64_t rr = gr < rows ? gr : rows - 1;
           const int cc = c < Nj ? c : Nj - 8;
-          const u16x8 *src = (const u16x8 *)(X + rr * ldx + cc);
-          rb[sl][p][h] = LSPCA_TN16_NTX ? __builtin_nontemporal_load(src) : *src;
+          rb[sl][p][h] = *(const u16x8 *)(X + rr * ldx + cc);
         } else {
           u16x8 x = {};
           if (gr < rend) {
