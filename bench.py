@@ -31,25 +31,30 @@ PEAKS = {  # MI355X published dense peaks
 
 # HBM bytes per launch of the sketch kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (one counter per run) scaled by the counters' reading for a
-# reference op of known traffic (profiles/sketch_*.md gives the commands and
-# figures). A figure holds only for the kernel source it was measured on:
+# reference op of known traffic (the profiles/*.md summaries give the
+# commands and figures). A figure holds only for the kernel source it was measured on:
 # when the sources' hash differs, traffic is reported as null.
 MEASURED_TRAFFIC = {
     ("f32", 1_000_000, 4096, 256, "gaussian"): {
         "sources": ["paper_1709_07175_amd/csrc/gemm.hip", "paper_1709_07175_amd/csrc/common.h"],
-        "sha256": "f3e207bf91087122f613eab0bc8b911c9eae22177f697d14b42fac50a69b23a2",
-        "bytes": 2.0009e+10,
+        "sha256": "a6c06c34af3f0f82be23ac1323ea82f648be0628fa8e635bbcbbad87f2a18efe",
+        "bytes": 1.9780e+10,
     },
     ("bf16", 1_000_000, 4096, 256, "sparse"): {
         "sources": ["paper_1709_07175_amd/csrc/sparse.hip", "paper_1709_07175_amd/csrc/philox.h",
                     "paper_1709_07175_amd/csrc/common.h"],
-        "sha256": "28b9a740739e3e028932c3d279ebf74ed1897be3c417db999786e96e73ede3da",
-        "bytes": 9.2164e+09,
+        "sha256": "ec93ed6fad9c048580301d99e098c778a7cd173830317aebb5828d9cd68aa454",
+        "bytes": 9.2162e+09,
+    },
+    ("f16", 4_600_000, 2048, 128, "gaussian"): {
+        "sources": ["paper_1709_07175_amd/csrc/gemm16.hip", "paper_1709_07175_amd/csrc/common.h"],
+        "sha256": "6ead9a0a1763e2cafef457f7578efe047cd4f24894a5f0a60b86713c18665faa",
+        "bytes": 2.1554e+10,
     },
     ("csr", 131_072, 98_450, 500, "sparse"): {   # k_csc_block, per row-block launch
         "sources": ["paper_1709_07175_amd/csrc/csr.hip", "paper_1709_07175_amd/csrc/common.h"],
-        "sha256": "749d646a9c8f55e873c13c510dbd99905b7f19a315bcc5024f7c93cb64c23249",
-        "bytes": 6.3313e+09,
+        "sha256": "ff3afe75e4e3f1cf3292bcb08e5dd0f86e4f91e7bc8f25840fcbd132a11a95c7",
+        "bytes": 6.3318e+09,
     },
 }
 
