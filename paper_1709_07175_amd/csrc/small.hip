@@ -233,87 +233,12 @@ template <int G> __device__ inline double sum_lanes(double v) {
 }
 
 // Rotation of a column pair from its Gram entries al = |a_p|^2,
-// be = |a_q|^2, ga = a_p.a_q. False (no rotation) when
-// |ga| <= tol |a_p| |a_q|; otherwise Rutishauser's formulas give c, s with
-// (c a_p - s a_q).(s a_p + c a_q) = 0.
-__device__ inline bool jacobi_cs(double al, double be, double ga, double tol, double &c, double &sn) {
-  // |ga| > tol sqrt(al be), squared (al, be >= 0)
-  if (!(ga != 0.0 && ga * ga > (tol * tol) * (al * be))) return false;
-  // t = sgn(zeta) / (|zeta| + sqrt(1 + zeta^2)) with zeta = (be - al) / (2 ga),
-  // multiplied through by 2|ga|:
-  // t = 2 ga sgn(be - al) / (|be - al| + sqrt((be - al)^2 + 4 ga^2)).
-  const double d = be - al;
-  const double t = (d >= 0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + sqrt(d * d + 4.0 * ga * ga));
-  c = 1.0 / sqrt(1.0 + t * t);
-  sn = c * t;
-  return true;
-}
-
-// Orthogonalise columns ap and aq (length len <= G * ROWS, in LDS) with
-// G lanes (gl = lane within the group; rows gl + G i), the pair's entries
-// held in registers.
-template <int ROWS, int G = 16>
-__device__ inline bool rotate_pair(double *ap, double *aq, int len, int gl, double tol) {
-  double x[ROWS], y[ROWS];
-#pragma unroll
-  for (int i = 0; i < ROWS; ++i) {
-    const int r = gl + G * i;
-    x[i] = r < len ? ap[r] : 0.0;
-    y[i] = r < len ? aq[r] : 0.0;
-  }
-  double al = 0, be = 0, ga = 0;
-#pragma unroll
-  for (int i = 0; i < ROWS; ++i) {
-    al += x[i] * x[i];
-    be += y[i] * y[i];
-    ga += x[i] * y[i];
-  }
-  double c, sn;
-  if (!jacobi_cs(sum_lanes<G>(al), sum_lanes<G>(be), sum_lanes<G>(ga), tol, c, sn)) return false;
-#pragma unroll
-  for (int i = 0; i < ROWS; ++i) {
-    const int r = gl + G * i;
-    if (r < len) {
-      ap[r] = c * x[i] - sn * y[i];
-      aq[r] = sn * x[i] + c * y[i];
-    }
-  }
-  return true;
-}
-
-// Any length: two passes over LDS (Gram entries, then the rotation).
-template <int G>
-__device__ inline bool rotate_long(double *ap, double *aq, int len, int gl, double tol) {
-  double al = 0, be = 0, ga = 0;
-  for (int r = gl; r < len; r += G) {
-    const double x = ap[r], y = aq[r];
-    al += x * x;
-    be += y * y;
-    ga += x * y;
-  }
-  double c, sn;
-  if (!jacobi_cs(sum_lanes<G>(al), sum_lanes<G>(be), sum_lanes<G>(ga), tol, c, sn)) return false;
-  for (int r = gl; r < len; r += G) {
-    const double x = ap[r], y = aq[r];
-    ap[r] = c * x - sn * y;
-    aq[r] = sn * x + c * y;
-  }
-  return true;
-}
-
-__device__ inline bool rotate_any(double *ap, double *aq, int len, int gl, double tol) {
-  if (len <= 32) return rotate_pair<2>(ap, aq, len, gl, tol);
-  if (len <= 64) return rotate_pair<4>(ap, aq, len, gl, tol);
-  if (len <= 128) return rotate_pair<8>(ap, aq, len, gl, tol);
-  if (len <= 256) return rotate_pair<16>(ap, aq, len, gl, tol);
-  return rotate_long<16>(ap, aq, len, gl, tol);
-}
-
-
-// Rotation of a pair from al, be, ga as jacobi_cs, also returning t = s / c,
-// with the square roots and reciprocals from the hardware estimates and one
-// Newton step each (relative error a few ulps; c^2 + s^2 = 1 to a few ulps,
-// which is what keeps the rotation orthogonal).
+// be = |a_q|^2, ga = a_p.a_q: false (no rotation) when |ga| <= tol |a_p|
+// |a_q|; otherwise Rutishauser's formulas give c, s with
+// (c a_p - s a_q).(s a_p + c a_q) = 0, and t = s / c, with the square roots
+// and reciprocals from the hardware estimates and one Newton step each
+// (relative error a few ulps; c^2 + s^2 = 1 to a few ulps, which is what
+// keeps the rotation orthogonal).
 __device__ inline double rsqrt_nr(double x) {
   const double y = __builtin_amdgcn_rsq(x);
   return y * fma(-0.5 * x * y, y, 1.5);
@@ -399,24 +324,34 @@ __device__ inline void rr_pair(int s, int i, int L, int &p, int &q) {
   }
 }
 
+__device__ inline bool rotate_nrm_any(double *ap, double *aq, double *np, double *nq, int len, int gl,
+                                      double tol) {
+  if (len <= 32) return rotate_nrm<16, 2>(ap, aq, np, nq, len, gl, tol);
+  if (len <= 64) return rotate_nrm<16, 4>(ap, aq, np, nq, len, gl, tol);
+  if (len <= 128) return rotate_nrm<16, 8>(ap, aq, np, nq, len, gl, tol);
+  return rotate_nrm<16, 0>(ap, aq, np, nq, len, gl, tol);
+}
+
 // One cyclic sweep over all pairs of the nc columns in LDS (column c at
-// cols + c * ld). Every pair of a round runs at once, 16 lanes per pair.
-// Adds the number of rotations to *counter.
-__device__ void lds_sweep_all(double *cols, int nc, int len, int ld, double tol, int *counter) {
+// cols + c * ld, squared norm nrm[c]). Every pair of a round runs at once,
+// 16 lanes per pair, with the norms updated by the rotation identities (as
+// the block kernel). Adds the number of rotations to *counter.
+__device__ void lds_sweep_all(double *cols, double *nrm, int nc, int len, int ld, double tol, int *counter) {
   const int ncp = (nc + 1) & ~1, L = ncp - 1, npairs = ncp / 2;
   const int g = threadIdx.x >> 4, gl = threadIdx.x & 15, ng = blockDim.x >> 4;
+  int rot = 0;
   for (int s = 0; s < L; ++s) {
     for (int i = g; i < npairs; i += ng) {
       int p, q;
       rr_pair(s, i, L, p, q);
       if (p < nc && q < nc) {
-        if (rotate_any(cols + (int64_t)min(p, q) * ld, cols + (int64_t)max(p, q) * ld, len, gl, tol) &&
-            gl == 0)
-          atomicAdd(counter, 1);
+        const int a = min(p, q), b = max(p, q);
+        rot += rotate_nrm_any(cols + (int64_t)a * ld, cols + (int64_t)b * ld, nrm + a, nrm + b, len, gl, tol);
       }
     }
     __syncthreads();
   }
+  if (gl == 0 && rot) atomicAdd(counter, rot);
 }
 
 // Whole k x k problem in one workgroup (k (k + 1) <= kLdsAlloc): Wc (column
@@ -424,15 +359,27 @@ __device__ void lds_sweep_all(double *cols, int nc, int len, int ld, double tol,
 __global__ __launch_bounds__(1024) void k_jacobi_lds(double *Wc, int k, double tol, int max_sweeps,
                                                      int *sweeps_out) {
   __shared__ double cols[kLdsAlloc];
+  __shared__ double nrm[128];
   __shared__ int counter;
   const int ld = k + 1;
   const int64_t kk = (int64_t)k * k;
+  const int g = threadIdx.x >> 4, gl = threadIdx.x & 15, ng = blockDim.x >> 4;
   for (int64_t e = threadIdx.x; e < kk; e += blockDim.x) cols[(e / k) * ld + e % k] = Wc[e];
   int sweep = 0;
   for (; sweep < max_sweeps; ++sweep) {
     if (threadIdx.x == 0) counter = 0;
     __syncthreads();
-    lds_sweep_all(cols, k, k, ld, tol, &counter);
+    // squared column norms from the columns themselves at every sweep (the
+    // rotation identities then carry them through the sweep)
+    for (int c = g; c < k; c += ng) {
+      double v = 0.0;
+      for (int r = gl; r < k; r += 16) v = fma(cols[c * ld + r], cols[c * ld + r], v);
+      v = sum_lanes<16>(v);
+      if (gl == 0) nrm[c] = v;
+    }
+    __syncthreads();
+    lds_sweep_all(cols, nrm, k, k, ld, tol, &counter);
+    __syncthreads();
     const int n = counter;
     __syncthreads();
     if (n == 0) break;
@@ -610,9 +557,10 @@ __global__ void k_scale_cols_inv(double *V, int64_t n, int k, const double *d) {
 
 // Sign of each column of V (n x k): its entry of largest magnitude made
 // positive, the first row on ties. Column maxima per chunk of kSignRows rows
-// (threads over columns, coalesced), then across chunks in order, then the
-// flip.
-constexpr int kSignRows = 256;
+// (threads over columns, coalesced, eight independent loads in flight), then
+// across chunks by one workgroup per column (a tree over the chunks with the
+// same tie rule), then the flip.
+constexpr int kSignRows = 32;
 __global__ __launch_bounds__(256) void k_colmax_part(const double *__restrict__ V, int64_t n, int k,
                                                      double *__restrict__ pv, int64_t *__restrict__ pi) {
   const int64_t r0 = (int64_t)blockIdx.x * kSignRows;
@@ -620,30 +568,55 @@ __global__ __launch_bounds__(256) void k_colmax_part(const double *__restrict__ 
   for (int c = threadIdx.x; c < k; c += blockDim.x) {
     double best = -1.0;
     int64_t bi = r0;
-    for (int64_t i = r0; i < r1; ++i) {
-      const double a = fabs(V[i * k + c]);
-      if (a > best) {
-        best = a;
-        bi = i;
-      }
+    for (int64_t i0 = r0; i0 < r1; i0 += 8) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = i0 + u < r1 ? fabs(V[(i0 + u) * k + c]) : -1.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (a[u] > best) {
+          best = a[u];
+          bi = i0 + u;
+        }
     }
     pv[(int64_t)blockIdx.x * k + c] = best;
     pi[(int64_t)blockIdx.x * k + c] = bi;
   }
 }
 
-__global__ void k_colmax_sign(const double *__restrict__ V, const double *__restrict__ pv,
-                              const int64_t *__restrict__ pi, int64_t chunks, int k, double *__restrict__ sgn) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= k) return;
+// (v, i) beats (w, j): larger magnitude, or equal and the earlier row.
+__device__ inline bool colmax_beats(double v, int64_t i, double w, int64_t j) {
+  return v > w || (v == w && i < j);
+}
+
+// One workgroup of 256 threads per column c.
+__global__ __launch_bounds__(256) void k_colmax_sign(const double *__restrict__ V, const double *__restrict__ pv,
+                                                     const int64_t *__restrict__ pi, int64_t chunks, int k,
+                                                     double *__restrict__ sgn) {
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  const int c = blockIdx.x, t = threadIdx.x;
   double best = -1.0;
-  int64_t bi = 0;
-  for (int64_t b = 0; b < chunks; ++b)
-    if (pv[b * k + c] > best) {
-      best = pv[b * k + c];
-      bi = pi[b * k + c];
+  int64_t bi = INT64_MAX;
+  for (int64_t b = t; b < chunks; b += 256) {
+    const double v = pv[b * k + c];
+    const int64_t i = pi[b * k + c];
+    if (colmax_beats(v, i, best, bi)) {
+      best = v;
+      bi = i;
     }
-  sgn[c] = V[bi * k + c] < 0.0 ? -1.0 : 1.0;
+  }
+  sv[t] = best;
+  si[t] = bi;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w && colmax_beats(sv[t + w], si[t + w], sv[t], si[t])) {
+      sv[t] = sv[t + w];
+      si[t] = si[t + w];
+    }
+    __syncthreads();
+  }
+  if (t == 0) sgn[c] = V[si[0] * k + c] < 0.0 ? -1.0 : 1.0;
 }
 
 __global__ void k_flip(double *__restrict__ V, int64_t n, int k, const double *__restrict__ sgn) {
@@ -664,7 +637,7 @@ static int sign_fix(double *V, int64_t n, int k, Workspace &ws, hipStream_t s) {
   double *sgn = ws.take<double>(k);
   hipLaunchKernelGGL(k_colmax_part, (unsigned)chunks, 256, 0, s, V, n, k, pv, pi);
   LSPCA_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_colmax_sign, (unsigned)((k + 255) / 256), 256, 0, s, V, pv, pi, chunks, k, sgn);
+  hipLaunchKernelGGL(k_colmax_sign, (unsigned)k, 256, 0, s, V, pv, pi, chunks, k, sgn);
   LSPCA_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_flip, (unsigned)std::min<int64_t>((n * k + 255) / 256, 65536), 256, 0, s, V, n, k, sgn);
   LSPCA_HIP(hipGetLastError());
@@ -932,18 +905,22 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
   LSPCA_TRY(launch_transpose_f64(F, k, (int)n, Ft, s));   // F (k x n) -> F^T (n x k)
 
   if (route == 0) {
-    // Cholesky QR passes on F^T: Q <- Q R_p^-1, R <- R_p R.
+    // Cholesky QR passes on F^T: Q <- Q R_p^-1, R <- R_p R. Each pass's
+    // Cholesky writes its own failure flag and the passes run without a host
+    // round trip: after a failed factor the later steps of the attempt only
+    // compute values that are then discarded. One round trip per attempt
+    // reads the flags and, for the plain attempt, whether R is graded.
     const double *Qin = Ft;
     double *Qout = Qa;
     bool shifted = false;
+    bool graded = false;
     int passes = 0;
     for (int attempt = 0; attempt < 2 && passes == 0; ++attempt) {
       const int npass = shifted ? 3 : 2;
       Qin = Ft;
       Qout = Qa;
-      bool failed = false;
+      LSPCA_TRY(zero_i32(dflag, 4, s));
       for (int pss = 0; pss < npass; ++pss) {
-        LSPCA_TRY(zero_i32(dflag, 4, s));
         LSPCA_TRY(gram(Qin, n, k, M, part, splits, s));
         if (shifted && pss == 0) {
           // shift = 11 (n k + k (k + 1)) u ||F||_F^2 (shifted Cholesky QR;
@@ -952,13 +929,7 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
           hipLaunchKernelGGL(k_shift_diag, 1, 256, 0, s, M, k, c);
           LSPCA_HIP(hipGetLastError());
         }
-        LSPCA_TRY(chol(M, k, dflag, scr, s));
-        LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
-        LSPCA_HIP(hipStreamSynchronize(s));
-        if (hflag[0]) {
-          failed = true;
-          break;
-        }
+        LSPCA_TRY(chol(M, k, dflag + pss, scr, s));
         LSPCA_TRY(trinv_t(M, k, XT, scr, s));
         LSPCA_TRY(launch_nt(LSPCA_F64, Qin, k, XT, k, Qout, k, n, k, k, s));
         if (pss == 0) {
@@ -971,9 +942,22 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
         Qin = Qout;
         Qout = (Qout == Qa) ? Qb : Qa;
       }
-      if (!failed) passes = npass;
-      else if (!shifted) shifted = true;
-      else break;
+      if (!shifted) {
+        hipLaunchKernelGGL(k_diag_graded, 1, 256, 0, s, Rall, k, kPrecondRatio, dflag + 3);
+        LSPCA_HIP(hipGetLastError());
+      }
+      LSPCA_HIP(hipMemcpyAsync(hflag, dflag, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+      LSPCA_HIP(hipStreamSynchronize(s));
+      bool failed = false;
+      for (int pss = 0; pss < npass; ++pss) failed = failed || hflag[pss] != 0;
+      if (!failed) {
+        passes = npass;
+        graded = !shifted && hflag[3] != 0;
+      } else if (!shifted) {
+        shifted = true;
+      } else {
+        break;
+      }
     }
     if (passes == 0) {
       set_error("factor: Cholesky QR of F^T failed (F is numerically rank deficient)");
@@ -988,27 +972,17 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
     // Jacobi on the columns of R2^T (= the rows of R2) needs far fewer sweeps
     // than on R when R is graded (Drmac and Veselic, SIAM J. Matrix Anal.
     // Appl. 29, 2008); applied only then (kPrecondRatio).
-    bool pre = !shifted;
-    if (pre) {
-      hipLaunchKernelGGL(k_diag_graded, 1, 256, 0, s, Rall, k, kPrecondRatio, dflag + 2);
-      LSPCA_HIP(hipGetLastError());
-      LSPCA_HIP(hipMemcpyAsync(hflag + 2, dflag + 2, sizeof(int), hipMemcpyDeviceToHost, s));
-      LSPCA_HIP(hipStreamSynchronize(s));
-      pre = hflag[2] != 0;
-      if (debug_on()) fprintf(stderr, "[lspca] small SVD preconditioner %s\n", pre ? "on" : "off");
-    }
+    bool pre = graded;
+    if (debug_on()) fprintf(stderr, "[lspca] small SVD preconditioner %s\n", pre ? "on" : "off");
     if (pre) {
       double *T = prebuf;                              // 4 k x k scratch matrices
       double *S1 = T + kk, *P = T + 2 * kk, *R2 = T + 3 * kk;
       LSPCA_TRY(launch_transpose_f64(Rall, k, k, T, s));            // T = R^T
-      for (int pss = 0; pss < 2 && pre; ++pss) {
+      LSPCA_TRY(zero_i32(dflag, 2, s));
+      for (int pss = 0; pss < 2; ++pss) {                           // flags read once after both
         const double *Tin = pss == 0 ? T : P;
-        LSPCA_TRY(zero_i32(dflag, 1, s));
         LSPCA_TRY(gram(Tin, k, k, M, part, tn_pick_splits(k, k, k), s));
-        LSPCA_TRY(chol(M, k, dflag, scr, s));
-        LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
-        LSPCA_HIP(hipStreamSynchronize(s));
-        if (hflag[0]) { pre = false; break; }
+        LSPCA_TRY(chol(M, k, dflag + pss, scr, s));
         LSPCA_TRY(trinv_t(M, k, XT, scr, s));
         double *Pout = pss == 0 ? P : S1;              // P = T S^-1
         LSPCA_TRY(launch_nt(LSPCA_F64, Tin, k, XT, k, Pout, k, k, k, k, s));
@@ -1020,6 +994,9 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
           LSPCA_TRY(launch_nt(LSPCA_F64, M, k, Rtmp, k, R2, k, k, k, k, s));
         }
       }
+      LSPCA_HIP(hipMemcpyAsync(hflag, dflag, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+      LSPCA_HIP(hipStreamSynchronize(s));
+      pre = hflag[0] == 0 && hflag[1] == 0;          // else Jacobi on R itself
       // the rows of R2 are the columns of R2^T: column storage as is
       if (pre) LSPCA_TRY(jacobi_svd(R2, true, k, Wc, UT, sw, dflag + 8, s));
     }
