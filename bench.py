@@ -48,8 +48,8 @@ MEASURED_TRAFFIC = {
     },
     ("f16", 4_600_000, 2048, 128, "gaussian"): {
         "sources": ["paper_1709_07175_amd/csrc/gemm16.hip", "paper_1709_07175_amd/csrc/common.h"],
-        "sha256": "6ead9a0a1763e2cafef457f7578efe047cd4f24894a5f0a60b86713c18665faa",
-        "bytes": 2.1554e+10,
+        "sha256": "93aa5bf6bc351ef8e1d66d93ffec294492931387f413381c4c448d59034db98e",
+        "bytes": 2.1574e+10,
     },
     ("csr", 131_072, 98_450, 500, "sparse"): {   # k_csc_block, per row-block launch
         "sources": ["paper_1709_07175_amd/csrc/csr.hip", "paper_1709_07175_amd/csrc/common.h"],
