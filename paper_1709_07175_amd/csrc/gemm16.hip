@@ -72,7 +72,14 @@ enum { OUT_ROWS = 0, OUT_T32 = 1, OUT_TSPLIT = 2 };
 #define LSPCA_NT16_PROJ_BM_NARROW 256
 #endif
 #ifndef LSPCA_NT16_SKETCH_BM
-#define LSPCA_NT16_SKETCH_BM 128
+#define LSPCA_NT16_SKETCH_BM 256
+#endif
+// Waves per workgroup of the unsplit product with N <= 128 (sketch; 4, or 8
+// as 4 x 2). With the 256-row tile, eight waves measured 5% faster than the
+// 128 x 128 tile of four waves (which fits two workgroups per CU); four
+// waves on the 256-row tile were slower.
+#ifndef LSPCA_NT16_SKETCH_WAVES
+#define LSPCA_NT16_SKETCH_WAVES 8
 #endif
 // Waves per workgroup of the split-B product (4 or 8). Eight waves (two per
 // SIMD) keep more loads and LDS reads in flight next to the matrix cores:
@@ -99,7 +106,6 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
   constexpr int WM = BM / WR, WN = BN / WC, TM = WM / 32, TN = WN / 32;
   constexpr int AV = BM * BK / 8 / NT, BV = BN * BK / 8 / NT;
   static_assert(AV >= 1 && BV >= 1, "tile too small");
-  static_assert(OUT != OUT_T32 || (WR == 2 && WC == 2), "column maxima assume 2 x 2 waves");
   __shared__ uint16_t As[2][BM * LD];
   __shared__ uint16_t Bs[2][(SPLITB ? 2 : 1) * BN * LD];
 
@@ -294,19 +300,22 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
     // waves of a column half meet in LDS; one plain store per column into
     // the partial row of this row tile (no atomics)
     if (colmax) {
-      float *red = reinterpret_cast<float *>(&As[0][0]);   // 2 x BN floats
+      float *red = reinterpret_cast<float *>(&As[0][0]);   // WR x BN floats
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
         const float mj = fmaxf(cm[j], __shfl_xor(cm[j], 32));
-        if (lane < 32) red[(wave >> 1) * BN + wn0 + j * 32 + lane] = mj;
+        if (lane < 32) red[(wave / WC) * BN + wn0 + j * 32 + lane] = mj;
       }
       __syncthreads();
       // one row per 128 rows of A (nt16_row_tiles), the same maximum in each
       // row this tile covers
       for (int t = tid; t < BN; t += NT)
         if (n0 + t < N) {
-          const unsigned mv = __float_as_uint(fmaxf(red[t], red[BN + t]));
+          float m = red[t];
+#pragma unroll
+          for (int w = 1; w < WR; ++w) m = fmaxf(m, red[w * BN + t]);
+          const unsigned mv = __float_as_uint(m);
 #pragma unroll
           for (int h = 0; h < BM / 128; ++h)
             if (m0 + 128 * h < M) colmax[(m0 / 128 + h) * (int64_t)N + n0 + t] = mv;
@@ -650,7 +659,8 @@ static int nt16_n(const uint16_t *A, int64_t lda, const uint16_t *Bh, const uint
   constexpr bool W8 = SPLITB && LSPCA_NT16_PROJ_WAVES == 8;
   if (N > 128)
     return nt16_typed<DT, BMW, 256, SPLITB, OUT, 2, W8 ? 4 : 2>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
-  return nt16_typed<DT, BMN, 128, SPLITB, OUT, W8 ? 4 : 2, 2>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
+  constexpr bool S8 = W8 || (!SPLITB && LSPCA_NT16_SKETCH_WAVES == 8);
+  return nt16_typed<DT, BMN, 128, SPLITB, OUT, S8 ? 4 : 2, 2>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl, s);
 }
 
 template <int DT>
