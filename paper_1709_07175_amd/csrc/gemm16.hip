@@ -692,8 +692,13 @@ int launch_nt16(lspca_dtype dt, const void *A, int64_t lda, const void *Bh, cons
 // ------------------------------------------------------ batched projection --
 // Persistent: workgroup b takes tiles b, b + grid, ... of the table; the
 // request of a tile is found by binary search over the tiles' first numbers.
+// Eight waves per workgroup, as the projection of lspca_transform (2 x 4 for
+// the 256-wide V tile, else 4 x 2): the same accumulation order per element.
+constexpr int kProjThreads = 512;
+template <int BN> constexpr int proj_wr() { return BN >= 256 ? 2 : 4; }
+
 template <int DT, int BM, int BN, bool VEC>
-__global__ __launch_bounds__(256) void k_proj_batch16(const ProjTable *__restrict__ tab,
+__global__ __launch_bounds__(kProjThreads) void k_proj_batch16(const ProjTable *__restrict__ tab,
                                                       const uint16_t *__restrict__ Vh,
                                                       const uint16_t *__restrict__ Vl, int64_t ldv,
                                                       int N, int K) {
@@ -707,9 +712,9 @@ __global__ __launch_bounds__(256) void k_proj_batch16(const ProjTable *__restric
     }
     const ProjReq &rq = tab->req[lo];
     const int local = t - rq.tile0, mt = local / ntn;
-    nt16_tile<DT, BM, BN, true, VEC, OUT_ROWS>((const uint16_t *)rq.X, rq.ldx, Vh, Vl, ldv, (float *)rq.Z,
-                                              rq.ldz, rq.rows, N, K, nullptr, nullptr, nullptr,
-                                              (int64_t)mt * BM, (local - mt * ntn) * BN);
+    nt16_tile<DT, BM, BN, true, VEC, OUT_ROWS, proj_wr<BN>(), 8 / proj_wr<BN>()>(
+        (const uint16_t *)rq.X, rq.ldx, Vh, Vl, ldv, (float *)rq.Z, rq.ldz, rq.rows, N, K, nullptr, nullptr,
+        nullptr, (int64_t)mt * BM, (local - mt * ntn) * BN);
   }
 }
 
@@ -730,7 +735,7 @@ int proj16_grid(lspca_dtype dt, int k, bool vec, int *grid) {
   int dev = 0, cus = 0, per = 0;
   LSPCA_HIP(hipGetDevice(&dev));
   LSPCA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  LSPCA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, proj16_kernel(dt, k, vec), 256, 0));
+  LSPCA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, proj16_kernel(dt, k, vec), kProjThreads, 0));
   *grid = cus * (per > 0 ? per : 1);
   return LSPCA_OK;
 }
@@ -738,7 +743,7 @@ int proj16_grid(lspca_dtype dt, int k, bool vec, int *grid) {
 int launch_proj_batch16(lspca_dtype dt, const ProjTable *tab, const void *VTh, const void *VTl, int64_t ldv,
                         int k, int n, bool vec, int grid, hipStream_t s) {
   void *args[] = {(void *)&tab, (void *)&VTh, (void *)&VTl, (void *)&ldv, (void *)&k, (void *)&n};
-  LSPCA_HIP(hipLaunchKernel(proj16_kernel(dt, k, vec), dim3(grid), dim3(256), args, 0, s));
+  LSPCA_HIP(hipLaunchKernel(proj16_kernel(dt, k, vec), dim3(grid), dim3(kProjThreads), args, 0, s));
   return LSPCA_OK;
 }
 
