@@ -48,8 +48,8 @@ MEASURED_TRAFFIC = {
     },
     ("f16", 4_600_000, 2048, 128, "gaussian"): {
         "sources": ["paper_1709_07175_amd/csrc/gemm16.hip", "paper_1709_07175_amd/csrc/common.h"],
-        "sha256": "ba415a84803f71cf2bfb8a958e6031e16c5bd5b87aa5142a0ed723443f65394a",
-        "bytes": 2.2044e+10,
+        "sha256": "89e3393376ed0ec92b525c16b748121f9bc5a53dd7b71136bfe8fa252ebb6388",
+        "bytes": 2.2001e+10,
     },
     ("csr", 131_072, 98_450, 500, "sparse"): {   # k_csc_block, per row-block launch
         "sources": ["paper_1709_07175_amd/csrc/csr.hip", "paper_1709_07175_amd/csrc/common.h"],

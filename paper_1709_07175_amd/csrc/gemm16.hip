@@ -764,8 +764,8 @@ int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld, 
   return LSPCA_OK;
 }
 
-// X-column tile: 256 when the Y side is one 128-column tile (halves the
-// re-reads of Y per X column), else 128.
+// X-column tile when the Y side is one 128-column tile (k <= 128): 512, so
+// the L2 reads of Y per byte of X are a quarter of a 128-wide tile's.
 #ifndef LSPCA_TN16_WIDE_BN
 #define LSPCA_TN16_WIDE_BN 512
 #endif
