@@ -163,8 +163,8 @@ __global__ __launch_bounds__(1024) void k_chol_lds(double *Mg, int n, int64_t ld
 // X[i][j] = -(sum_{p=i}^{j-1} X[i][p] R[p][j]) / R[j][j], 8 lanes per
 // row i. Writes XT[c][i] = X[i][c] (ld ldxt) and, if X != NULL, X itself
 // (ld ldx).
-__global__ __launch_bounds__(1024) void k_trinv_lds(const double *R, int n, int64_t ldr, double *XT,
-                                                    int64_t ldxt, double *X, int64_t ldx) {
+__device__ void trinv_block(const double *R, int n, int64_t ldr, double *XT, int64_t ldxt, double *X,
+                            int64_t ldx) {
   __shared__ double A[128 * 129];
   const int tid = threadIdx.x, nt = blockDim.x, s = n + 1;
   const int i = tid >> 3, sub = tid & 7;
@@ -189,6 +189,18 @@ __global__ __launch_bounds__(1024) void k_trinv_lds(const double *R, int n, int6
     XT[(int64_t)b * ldxt + a] = A[a * s + b];
     if (X) X[(int64_t)a * ldx + b] = A[a * s + b];
   }
+}
+
+__global__ __launch_bounds__(1024) void k_trinv_lds(const double *R, int n, int64_t ldr, double *XT,
+                                                    int64_t ldxt, double *X, int64_t ldx) {
+  trinv_block(R, n, ldr, XT, ldxt, X, ldx);
+}
+
+// The diagonal 128-blocks of XT = (R^-1)^T (R k x k), one workgroup each:
+// they are independent, so all of them in one launch.
+__global__ __launch_bounds__(1024) void k_trinv_blocks(const double *R, int k, double *XT) {
+  const int j0 = blockIdx.x * 128, jb = k - j0 < 128 ? k - j0 : 128;
+  trinv_block(R + (int64_t)j0 * k + j0, jb, k, XT + (int64_t)j0 * k + j0, k, nullptr, 0);
 }
 
 __global__ void k_zero_lower(double *M, int k) {
@@ -700,9 +712,10 @@ int chol(double *M, int k, int *dflag, double *scratch, hipStream_t s) {
 }
 
 // XT = (R^-1)^T for upper triangular R (k x k). k <= 128: one LDS kernel.
-// Larger k: diagonal blocks in LDS, then for each block column J and I < J
-// XT_JI = -XT_JJ sum_{P=I}^{J-1} R_PJ^T XT_PI (two products).
-// scratch: 3 * 128 * 128 doubles.
+// Larger k: the diagonal blocks XT_JJ in LDS (one launch for all), then for
+// each block column J and I < J, XT_JI = -XT_JJ S^T with
+// S^T = sum_{P=I}^{J-1} XT_PI^T R_PJ (two products). scratch: 128 * 128
+// doubles (at least).
 int trinv_t(const double *R, int k, double *XT, double *scratch, hipStream_t s) {
   if (k <= kBlk) {
     hipLaunchKernelGGL(k_trinv_lds, 1, 1024, 0, s, R, k, (int64_t)k, XT, (int64_t)k, nullptr, (int64_t)0);
@@ -710,22 +723,21 @@ int trinv_t(const double *R, int k, double *XT, double *scratch, hipStream_t s) 
     return LSPCA_OK;
   }
   const int nb = (k + kBlk - 1) / kBlk;
-  double *Xd = scratch, *S = scratch + kBlk * kBlk;
+  double *St = scratch;
   hipLaunchKernelGGL(k_zero_i32, (unsigned)(((int64_t)k * k * 2 + 255) / 256), 256, 0, s, (int *)XT, k * k * 2);
   LSPCA_HIP(hipGetLastError());
-  for (int J = 0; J < nb; ++J) {
+  hipLaunchKernelGGL(k_trinv_blocks, nb, 1024, 0, s, R, k, XT);
+  LSPCA_HIP(hipGetLastError());
+  for (int J = 1; J < nb; ++J) {
     const int j0 = J * kBlk, jb = std::min(kBlk, k - j0);
-    hipLaunchKernelGGL(k_trinv_lds, 1, 1024, 0, s, R + (int64_t)j0 * k + j0, jb, (int64_t)k,
-                       XT + (int64_t)j0 * k + j0, (int64_t)k, Xd, (int64_t)jb);
-    LSPCA_HIP(hipGetLastError());
     for (int I = 0; I < J; ++I) {
       const int i0 = I * kBlk, ib = std::min(kBlk, k - i0);
-      // S[r][c] = sum over rows p in [i0, j0) of R[p][j0+r] XT[p][i0+c]
-      LSPCA_TRY(launch_tn(LSPCA_F64, R + (int64_t)i0 * k + j0, k, XT + (int64_t)i0 * k + i0, k, S,
-                          j0 - i0, jb, ib, 1, s, ib, 1.0, 0.0));
-      // XT_JI = -XT_JJ S:  C[r][c] = -sum_p X_JJ[p][r] S[p][c]
-      LSPCA_TRY(launch_tn(LSPCA_F64, Xd, jb, S, ib, XT + (int64_t)j0 * k + i0, jb, jb, ib, 1, s, k,
-                          -1.0, 0.0));
+      // St[c][r] = sum over rows p in [i0, j0) of XT[p][i0+c] R[p][j0+r]  (ib x jb)
+      LSPCA_TRY(launch_tn(LSPCA_F64, XT + (int64_t)i0 * k + i0, k, R + (int64_t)i0 * k + j0, k, St,
+                          j0 - i0, ib, jb, 1, s, jb, 1.0, 0.0));
+      // XT_JI[r][c] = -sum_p XT_JJ[r][p] St[c][p]
+      LSPCA_TRY(launch_nt(LSPCA_F64, XT + (int64_t)j0 * k + j0, k, St, jb, XT + (int64_t)j0 * k + i0, k, jb,
+                          ib, jb, s, -1.0, 0.0));
     }
   }
   return LSPCA_OK;
