@@ -27,7 +27,12 @@
  *    and lspca_transform only enqueue: outputs are ready when the stream is.
  *  - The library keeps a per-device workspace (grown on demand, freed at
  *    process exit). Calls that overlap on one device from several host
- *    threads are serialised by a lock.
+ *    threads are serialised by a lock, and on the device each call's work
+ *    waits for the previous call's last use of the workspace (an event the
+ *    library records after each call), whichever streams the two calls
+ *    were queued on. Caller buffers are not ordered by the library: a
+ *    caller that hands one call's output to a call on another stream orders
+ *    the two streams itself.
  *  - X is never centred (Sec. I-B: the SPCA subspace does not need it).
  *  - Exceptions to "device pointers only": X of lspca_accumulate_host and
  *    lspca_fit_host lives in host memory, and the projection server's
@@ -73,7 +78,9 @@ typedef enum {
   LSPCA_EAGAIN = -6,    /* server: no capacity right now; retry */
   LSPCA_ENOTSUP = -7,   /* combination not supported */
   LSPCA_ETIMEDOUT = -8, /* server: wait timed out */
-  LSPCA_ENOTFOUND = -9  /* server: unknown or already collected ticket */
+  LSPCA_ENOTFOUND = -9, /* server: unknown or already collected ticket */
+  LSPCA_ENOCONV = -10   /* small stage: one-sided Jacobi reached its sweep
+                           limit with rotations still pending */
 } lspca_status;
 
 /*
@@ -155,9 +162,10 @@ LSPCA_API int lspca_omega(int64_t n, int32_t k, lspca_omega_kind kind, uint64_t 
  * horizontal slice X (m x n): U_s = X Omega, F += U_s^T X and G += U_s^T U_s.
  *  F: k x n FP64 (device), accumulated in place (caller zeroes it first).
  *  G: k x k FP64 (device) or NULL to skip the Gram. G feeds sigma_x.
- *  Products run in the type of X with FP32 accumulation (FP64 for F64);
- *  the slice's partial sums are added into F and G in FP64 in a fixed order,
- *  so results are deterministic for a given input and device.
+ *  Products run in the type of X with FP32 accumulation (FP64 for F64).
+ *  Each FP32 partial sum spans at most 65,536 rows of the slice; the
+ *  partials are added into F and G in FP64 in a fixed order, so results
+ *  are deterministic for a given input and device.
  *  Errors: EINVAL (m < 1, n < 1, k < 1, k > n, ldx < n, NULL X/F, bad kind),
  *  ENOMEM, EHIP. Asynchronous on opts->stream.
  */
@@ -177,16 +185,20 @@ LSPCA_API int lspca_accumulate(const void *X, lspca_dtype xdt, int64_t m, int64_
  *     R = chol(G), Q^T X = R^-T F (no tall QR).
  *  Errors: EINVAL, ENOMEM, EHIP, ERANK if F is numerically rank deficient
  *  (D_k <= 64 * n * eps * D_1) or, when sigma_x is requested, if chol(G)
- *  fails (Lemma of the footnote to Corollary 1 assumes rank(U) = k).
- *  Synchronous.
+ *  fails (Lemma of the footnote to Corollary 1 assumes rank(U) = k),
+ *  ENOCONV if a one-sided Jacobi run stopped at its sweep limit (60 for
+ *  k <= 128, else 40) while its last sweep still rotated. Synchronous.
  */
 LSPCA_API int lspca_factor(const double *F, const double *G, int32_t k, int64_t n,
                  const lspca_opts *opts, double *V, double *sigma,
                  double *sigma_x);
 
 /*
- * lspca_fit -- Lazy SPCA (Algorithm 2), one pass over X resident on the
- * device: lspca_accumulate over all of X, then lspca_factor.
+ * lspca_fit -- Lazy SPCA (Algorithm 2) of X resident on the device:
+ * lspca_accumulate over all of X, then lspca_factor. Each stripe of rows
+ * goes through two kernels, the sketch and then F = U^T X, so X is read
+ * twice from device memory for FP32/FP64 data and streamed by two kernels
+ * per stripe for 16-bit data.
  * Arguments as above; 1 <= k <= min(m, n) (Corollary 1 requires
  * l <= min{m, n}). Synchronous. Errors as lspca_accumulate/lspca_factor.
  */

@@ -27,7 +27,7 @@ KIND = {"gaussian": GAUSSIAN, "sparse": VERY_SPARSE, GAUSSIAN: GAUSSIAN, VERY_SP
 
 STATUS = {0: "LSPCA_OK", -1: "LSPCA_EINVAL", -2: "LSPCA_ENOMEM", -3: "LSPCA_EHIP",
           -4: "LSPCA_ERANK", -5: "LSPCA_E2BIG", -6: "LSPCA_EAGAIN", -7: "LSPCA_ENOTSUP",
-          -8: "LSPCA_ETIMEDOUT", -9: "LSPCA_ENOTFOUND"}
+          -8: "LSPCA_ETIMEDOUT", -9: "LSPCA_ENOTFOUND", -10: "LSPCA_ENOCONV"}
 
 # Every symbol include/lspca.h declares.
 EXPORTS = ["lspca_version", "lspca_strerror", "lspca_last_error", "lspca_last_timings",

@@ -67,6 +67,11 @@ struct DeviceState {
   std::mutex mu;
   Workspace ws;
   HostStreaming hs;
+  // Recorded on a call's stream after its last use of the workspace; the
+  // next call's stream waits on it before writing the workspace, so calls
+  // on different streams never overlap on the device in the shared slots.
+  hipEvent_t ws_done = nullptr;
+  bool ws_recorded = false;
 };
 
 static DeviceState &device_state(int dev) {
@@ -444,6 +449,31 @@ static int lock_device(Locked &L) {
   return LSPCA_OK;
 }
 
+// Device-side order of the workspace across streams. begin(): the call's
+// stream waits for the last use of the workspace by the previous call (on
+// whatever stream it ran); the destructor records the call's own last use,
+// also on an error return, so work already queued by a failed call is
+// covered. Declared after the Locked guard, it runs while the lock is held.
+struct WsOrder {
+  DeviceState *st = nullptr;
+  hipStream_t s = nullptr;
+  int begin(Locked &L, hipStream_t stream) {
+    DeviceState &d = *L.st;
+    if (!d.ws_done) LSPCA_HIP(hipEventCreateWithFlags(&d.ws_done, hipEventDisableTiming));
+    if (d.ws_recorded) LSPCA_HIP(hipStreamWaitEvent(stream, d.ws_done, 0));
+    st = &d;
+    s = stream;
+    return LSPCA_OK;
+  }
+  ~WsOrder() {
+    if (!st) return;
+    if (hipEventRecord(st->ws_done, s) == hipSuccess)
+      st->ws_recorded = true;
+    else
+      (void)hipGetLastError();
+  }
+};
+
 
 // ------------------------------------------------------ sparse (CSR) X -----
 static int check_csr_args(const int64_t *rowptr, const int32_t *colidx, const void *vals, int vdt,
@@ -704,6 +734,7 @@ const char *lspca_strerror(int status) {
     case LSPCA_ENOTSUP: return "not supported";
     case LSPCA_ETIMEDOUT: return "timed out";
     case LSPCA_ENOTFOUND: return "unknown ticket";
+    case LSPCA_ENOCONV: return "Jacobi sweep limit reached";
   }
   return "unknown status";
 }
@@ -736,6 +767,8 @@ int lspca_accumulate(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64
   if (!F) { set_error("F is NULL"); return LSPCA_EINVAL; }
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   PassPlan pl = plan_pass(xdt, m, n, k, G != nullptr, kind, o.p, o.stripe_rows);
   LSPCA_TRY(L.st->ws.ensure(pl.bytes));
   PhaseTimer tm;
@@ -755,6 +788,8 @@ int lspca_factor(const double *F, const double *G, int32_t k, int64_t n, const l
   if (k > 4096) { set_error("k > 4096 is not supported"); return LSPCA_ENOTSUP; }
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   LSPCA_TRY(L.st->ws.ensure(factor_bytes(n, k)));
   PhaseTimer tm;
   tm.begin(o.timing != 0, o.stream);
@@ -775,6 +810,8 @@ int lspca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx,
   if (k > m) { set_error("k must satisfy k <= min(m, n) (k=%d m=%lld)", k, (long long)m); return LSPCA_EINVAL; }
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   const bool want_g = sigma_x != nullptr;
   PassPlan pl = plan_pass(xdt, m, n, k, want_g, kind, o.p, o.stripe_rows);
   const size_t fg = ws_bytes<double>((size_t)k * n) + ws_bytes<double>((size_t)k * k);
@@ -807,6 +844,8 @@ int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t n, int64_
   if (!X || !V || !Z) { set_error("X, V and Z must not be NULL"); return LSPCA_EINVAL; }
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   const size_t es = dtype_size(xdt);
   const bool h16 = is16(xdt);
   LSPCA_TRY(L.st->ws.ensure((h16 ? 2 : 1) * ws_bytes<char>(es * (size_t)n * k)));
@@ -836,6 +875,8 @@ int lspca_accumulate_host(const void *X, lspca_dtype xdt, int64_t m, int64_t n, 
   LSPCA_TRY(check_host_ptr(X));
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   PhaseTimer tm;
   tm.begin(o.timing != 0, o.stream);
   LSPCA_TRY(host_pass(X, xdt, m, n, ldx, k, kind, seed, o, host_stripe(m, n, xdt, stripe_rows), F, G, *L.st));
@@ -856,6 +897,8 @@ int lspca_fit_host(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t
   LSPCA_TRY(check_host_ptr(X));
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   const bool want_g = sigma_x != nullptr;
   // F and G live in their own allocation: the workspace is re-planned below
   double *FG = nullptr;
@@ -901,6 +944,8 @@ int spca_fit_stream(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
   const size_t ys = dtype_size(ydt);
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   PassPlan pl = plan_pass(xdt, m, n, k, false, kind, o.p, o.stripe_rows);
   const size_t kb = (size_t)k * BR;
   const size_t keep = ws_bytes<double>((size_t)k * n) + 3 * ws_bytes<char>(ys * kb) +
@@ -967,6 +1012,8 @@ int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, 
   const int sf = tn_pick_splits(m, k, (int)n);
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   const int64_t ldt = tsqr_ld(m, ydt);
   const size_t need = ws_bytes<char>(xs * (size_t)n * k) + ws_bytes<char>(ys * (size_t)ldt * k) +
                       (h16 ? 2 * ws_bytes<uint16_t>((size_t)m * k) : ws_bytes<char>(ys * (size_t)m * k)) +
@@ -1033,6 +1080,8 @@ int lspca_accumulate_csr(const int64_t *rowptr, const int32_t *colidx, const voi
   if (!F) { set_error("F is NULL"); return LSPCA_EINVAL; }
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   Workspace &ws = L.st->ws;
   CsrPlan pl;
   LSPCA_TRY(plan_csr(rowptr, colidx, vdt, m, n, nnz, k, kind, G != nullptr, o, ws, pl));
@@ -1054,6 +1103,8 @@ int lspca_fit_csr(const int64_t *rowptr, const int32_t *colidx, const void *valu
   if (k > m) { set_error("k must satisfy k <= min(m, n) (k=%d m=%lld)", k, (long long)m); return LSPCA_EINVAL; }
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   Workspace &ws = L.st->ws;
   const bool want_g = sigma_x != nullptr;
   CsrPlan pl;
@@ -1089,6 +1140,8 @@ int lspca_transform_csr(const int64_t *rowptr, const int32_t *colidx, const void
   if (!V || !Z) { set_error("V and Z must not be NULL"); return LSPCA_EINVAL; }
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   Workspace &ws = L.st->ws;
   const size_t esz = dtype_size(vdt);
   const int64_t ldv = csr_ld(k, esz);
@@ -1131,6 +1184,8 @@ int spca_fit_csr(const int64_t *rowptr, const int32_t *colidx, const void *value
   }
   Locked L;
   LSPCA_TRY(lock_device(L));
+  WsOrder wo;
+  LSPCA_TRY(wo.begin(L, o.stream));
   Workspace &ws = L.st->ws;
   CsrPlan pl;
   LSPCA_TRY(plan_csr(rowptr, colidx, vdt, m, n, nnz, k, kind, false, o, ws, pl));

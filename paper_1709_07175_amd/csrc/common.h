@@ -156,6 +156,12 @@ int launch_tn(lspca_dtype dt, const void *A, int64_t lda, const void *B,
               int64_t ldb, void *P, int64_t M_rows, int Mi, int Nj, int splits,
               hipStream_t s, int64_t ldp = 0, double alpha = 1.0, double beta = 0.0);
 int tn_pick_splits(int64_t rows, int Mi, int Nj);
+// Rows summed in FP32 by one partial of a split product (at most 65,472
+// before the launchers' rounding of the chunk to 16 or 64 rows, so at most
+// 65,536 after it), and the split cap (the grid's z limit, a multiple of 8),
+// which keeps that depth for stripes of up to 4.29e9 rows.
+constexpr int64_t kTnMaxDepth = 65472;
+constexpr int64_t kTnMaxSplits = 65528;
 // 16-bit products (gemm16.hip). nt16 output mode: 0 row-major FP32 C;
 // 1 transposed FP32 C[c*ldc + r] with max |C| per column of each 128-row
 // tile (colmax[tile][c], see nt16_row_tiles); 2

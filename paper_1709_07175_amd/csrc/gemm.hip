@@ -358,8 +358,13 @@ int tn_pick_splits(int64_t rows, int Mi, int Nj) {
   int64_t maxs = (rows + 127) / 128;
   int64_t s = want < maxs ? want : maxs;
   if (s >= 8) s = s / 8 * 8;                 // multiple of 8 for the XCD map
+  // accuracy contract: each FP32 partial sums at most kTnMaxDepth rows (the
+  // launchers round the chunk up to a multiple of 64 at most, which keeps it
+  // within 65,536); the partials are then added in FP64
+  const int64_t deep = (rows + kTnMaxDepth - 1) / kTnMaxDepth;
+  if (s < deep) s = (deep + 7) / 8 * 8;
   if (s < 1) s = 1;
-  if (s > 4096) s = 4096;
+  if (s > kTnMaxSplits) s = kTnMaxSplits;
   return (int)s;
 }
 

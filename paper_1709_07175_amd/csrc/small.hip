@@ -232,6 +232,10 @@ constexpr int kLdsAlloc = 16640;     // allocation incl. padding (130 KB)
 constexpr int kBlockLdsAlloc = 17408;
 __host__ __device__ inline int jacobi_ld(int k) { return k <= 256 ? k + ((16 - k) & 31) : k + 1; }
 constexpr int kJacobiMaxSweeps = 40;
+// dflag slots of small_factor: non-convergence flags of its two Jacobi runs
+// (the SVD of F, then Sigma^s), clear of the sweep counters at dflag + 8
+// and dflag + 64 (kJacobiMaxSweeps + 1 ints each).
+constexpr int kNoConv = 120;
 namespace cg = cooperative_groups;
 
 // Sum over G lanes (16: one DPP row; 32, 64: rows combined by lane
@@ -369,7 +373,7 @@ __device__ void lds_sweep_all(double *cols, double *nrm, int nc, int len, int ld
 // Whole k x k problem in one workgroup (k (k + 1) <= kLdsAlloc): Wc (column
 // storage, global) is loaded into LDS, swept to convergence, written back.
 __global__ __launch_bounds__(1024) void k_jacobi_lds(double *Wc, int k, double tol, int max_sweeps,
-                                                     int *sweeps_out) {
+                                                     int *sweeps_out, int *noconv) {
   __shared__ double cols[kLdsAlloc];
   __shared__ double nrm[128];
   __shared__ int counter;
@@ -398,6 +402,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_lds(double *Wc, int k, double t
   }
   for (int64_t e = threadIdx.x; e < kk; e += blockDim.x) Wc[e] = cols[(e / k) * ld + e % k];
   if (threadIdx.x == 0 && sweeps_out) *sweeps_out = sweep;
+  // every sweep up to the limit still rotated: not converged
+  if (threadIdx.x == 0 && sweep == max_sweeps) *noconv = 1;
 }
 
 // Block one-sided Jacobi step for k too large for one workgroup: the k
@@ -499,7 +505,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double *Wc, int k, int b,
 // workgroup reads it after the sweep's last barrier, so all stop together.
 template <int G, int ROWS>
 __global__ __launch_bounds__(1024) void k_jacobi_coop(double *Wc, int k, int b, int nb, double tol,
-                                                      int max_sweeps, int *counts, int *sweeps_out) {
+                                                      int max_sweeps, int *counts, int *sweeps_out,
+                                                      int *noconv) {
   __shared__ double cols[kBlockLdsAlloc];
   __shared__ double nrm[64];
   __shared__ int counter, total;
@@ -518,7 +525,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_coop(double *Wc, int k, int b, 
     if (total == 0) break;
     __syncthreads();
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *sweeps_out = sweep;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *sweeps_out = sweep;
+    if (total != 0) *noconv = 1;             // the last sweep allowed still rotated
+  }
 }
 
 // Column norms sigma_c = |Wc[c]|, ranks by decreasing sigma (ties: lower c
@@ -668,6 +678,14 @@ int zero_i32(int *p, int count, hipStream_t s) {
   return LSPCA_OK;
 }
 
+__global__ void k_set_i32(int *p, int v) { *p = v; }
+
+static int set_i32(int *p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_i32, 1, 1, 0, s, p, v);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
 namespace {
 
 // M (k x k) = A^T A for A (rows x k, row-major), FP64.
@@ -792,12 +810,24 @@ static int round_threads(int n_pairs) {
   return t < 64 ? 64 : (t > 1024 ? 1024 : t);
 }
 
+// Sweep limit of the one-sided Jacobi: `dflt`, or LSPCA_JACOBI_SWEEPS when
+// it is smaller (a test knob that forces the non-convergence error).
+static int jacobi_sweep_limit(int dflt) {
+  if (const char *e = getenv("LSPCA_JACOBI_SWEEPS")) {
+    const int v = atoi(e);
+    if (v >= 1 && v < dflt) return v;
+  }
+  return dflt;
+}
+
 // One-sided Jacobi SVD of a k x k matrix A (singular values and left
 // singular vectors). A is row-major, or already in column storage
 // (Wc[c][i] = A[i][c]) when `cols_given`. Writes the sorted singular
-// values to sigma and, if UT != NULL, U^T (sorted rows).
+// values to sigma and, if UT != NULL, U^T (sorted rows). Sets the device
+// int *noconv (zeroed by the caller) when the sweep limit was reached with
+// rotations still made in the last sweep.
 int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, double *sigma,
-               int *dflag, hipStream_t s) {
+               int *dflag, int *noconv, hipStream_t s) {
   const int64_t kk = (int64_t)k * k;
   if (cols_given)
     LSPCA_HIP(hipMemcpyAsync(Wc, A, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -808,7 +838,8 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
   const double tol = 8.0 * (double)std::max(k, 16) * 0x1p-53;
   int sweeps = 0;
   if ((int64_t)k * (k + 1) <= kLdsAlloc) {
-    hipLaunchKernelGGL(k_jacobi_lds, 1, round_threads((k + 1) / 2), 0, s, Wc, k, tol, 60, dflag);
+    hipLaunchKernelGGL(k_jacobi_lds, 1, round_threads((k + 1) / 2), 0, s, Wc, k, tol, jacobi_sweep_limit(60),
+                       dflag, noconv);
     LSPCA_HIP(hipGetLastError());
     if (debug_on()) {
       LSPCA_HIP(hipMemcpyAsync(&sweeps, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -834,9 +865,10 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
       LSPCA_TRY(zero_i32(dflag, kJacobiMaxSweeps, s));
       int *counts = dflag, *swo = dflag + kJacobiMaxSweeps;
       double *wc = Wc;
-      int kk2 = k, bb = b, nbb = nb, ms = kJacobiMaxSweeps;
+      int kk2 = k, bb = b, nbb = nb, ms = jacobi_sweep_limit(kJacobiMaxSweeps);
       double tl = tol;
-      void *args[] = {&wc, &kk2, &bb, &nbb, &tl, &ms, &counts, &swo};
+      int *nc = noconv;
+      void *args[] = {&wc, &kk2, &bb, &nbb, &tl, &ms, &counts, &swo, &nc};
       const void *fn = G == 16 ? (const void *)k_jacobi_coop<16, 16>
                                : G == 32 ? (const void *)k_jacobi_coop<32, 16> : (const void *)k_jacobi_coop<64, 0>;
       const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(nb / 2), dim3(G * b), args, 0, s);
@@ -851,7 +883,8 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
       }
     }
     int hflag = 0;
-    for (int sweep = 0; !done && sweep < kJacobiMaxSweeps; ++sweep) {
+    const int lim = jacobi_sweep_limit(kJacobiMaxSweeps);
+    for (int sweep = 0; !done && sweep < lim; ++sweep) {
       LSPCA_TRY(zero_i32(dflag, 1, s));
       for (int round = 0; round < nb - 1; ++round) {
         if (G == 16)
@@ -867,6 +900,8 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
       sweeps = sweep + 1;
       if (!hflag) break;
     }
+    // the last sweep allowed still rotated: not converged
+    if (!done && hflag) LSPCA_TRY(set_i32(noconv, 1, s));
   }
   if (debug_on()) fprintf(stderr, "[lspca] jacobi k=%d sweeps=%d\n", k, sweeps);
   hipLaunchKernelGGL(k_jacobi_finish, 1, 1024, (size_t)k * (sizeof(double) + sizeof(int)) + 16, s,
@@ -914,6 +949,7 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
   int *dflag = ws.take<int>(kSmallFlags);
   int hflag[4];
 
+  LSPCA_TRY(zero_i32(dflag + kNoConv, 2, s));
   LSPCA_TRY(launch_transpose_f64(F, k, (int)n, Ft, s));   // F (k x n) -> F^T (n x k)
 
   if (route == 0) {
@@ -1010,9 +1046,9 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
       LSPCA_HIP(hipStreamSynchronize(s));
       pre = hflag[0] == 0 && hflag[1] == 0;          // else Jacobi on R itself
       // the rows of R2 are the columns of R2^T: column storage as is
-      if (pre) LSPCA_TRY(jacobi_svd(R2, true, k, Wc, UT, sw, dflag + 8, s));
+      if (pre) LSPCA_TRY(jacobi_svd(R2, true, k, Wc, UT, sw, dflag + 8, dflag + kNoConv, s));
     }
-    if (!pre) LSPCA_TRY(jacobi_svd(Rall, false, k, Wc, UT, sw, dflag + 8, s));
+    if (!pre) LSPCA_TRY(jacobi_svd(Rall, false, k, Wc, UT, sw, dflag + 8, dflag + kNoConv, s));
     LSPCA_TRY(launch_nt(LSPCA_F64, Q, k, UT, k, Vw, k, n, k, k, s));
   } else {
     // The route of the caption of the algorithm table: F F^T = W Lambda W^T
@@ -1021,7 +1057,7 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
     // Lambda^(1/2), V = F^T W D^-1, then one Cholesky QR pass on V.
     LSPCA_TRY(gram(Ft, n, k, M, part, splits, s));                 // M = F F^T
     LSPCA_HIP(hipMemcpyAsync(Rall, M, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
-    LSPCA_TRY(jacobi_svd(M, false, k, Wc, UT, sw, dflag + 8, s));   // UT = W^T, sw = Lambda
+    LSPCA_TRY(jacobi_svd(M, false, k, Wc, UT, sw, dflag + 8, dflag + kNoConv, s));   // UT = W^T, sw = Lambda
     hipLaunchKernelGGL(k_sqrt_vec, 1, 256, 0, s, sw, k);            // D
     LSPCA_HIP(hipGetLastError());
     LSPCA_TRY(launch_nt(LSPCA_F64, Ft, k, UT, k, Qa, k, n, k, k, s));      // F^T W
@@ -1051,7 +1087,7 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
     LSPCA_TRY(chol(M, k, dflag, scr, s));
     LSPCA_TRY(trinv_t(M, k, XT, scr, s));
     LSPCA_TRY(launch_nt(LSPCA_F64, Rall, k, XT, k, Rtmp, k, k, k, k, s));
-    LSPCA_TRY(jacobi_svd(Rtmp, false, k, Wc, nullptr, sx, dflag + 64, s));
+    LSPCA_TRY(jacobi_svd(Rtmp, false, k, Wc, nullptr, sx, dflag + 64, dflag + kNoConv + 1, s));
     LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
     LSPCA_HIP(hipStreamSynchronize(s));
     if (hflag[0]) {
@@ -1064,8 +1100,15 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
   // Rank check on D: D_k <= 64 n eps D_1 means F is numerically rank deficient
   // (the eigenvalue route squares: sqrt(64 n eps) D_1).
   std::vector<double> hs(k);
+  int hnc[2] = {0, 0};
   LSPCA_HIP(hipMemcpyAsync(hs.data(), sw, k * sizeof(double), hipMemcpyDeviceToHost, s));
+  LSPCA_HIP(hipMemcpyAsync(hnc, dflag + kNoConv, sizeof(hnc), hipMemcpyDeviceToHost, s));
   LSPCA_HIP(hipStreamSynchronize(s));
+  if (hnc[0] || hnc[1]) {
+    set_error("factor: one-sided Jacobi did not converge within its sweep limit (%s)",
+              hnc[0] ? "SVD of F" : "Sigma^s");
+    return LSPCA_ENOCONV;
+  }
   const double rel = 64.0 * (double)n * 0x1p-52;
   if (!(hs[k - 1] > (route == 0 ? rel : std::sqrt(rel)) * hs[0])) {
     set_error("factor: F is numerically rank deficient (D_k = %g, D_1 = %g)", hs[k - 1], hs[0]);

@@ -427,3 +427,25 @@ def test_sparse_sketch_fallback_gives_the_same_bits(gpu_lib, monkeypatch, kernel
     for key in env:
         monkeypatch.delenv(key)
     assert np.array_equal(F1.cpu().numpy(), F2.cpu().numpy())
+
+
+@pytest.mark.parametrize("k,knob", [(40, None), (200, None), (200, "launches")])
+def test_jacobi_sweep_limit_is_reported(gpu_lib, monkeypatch, k, knob):
+    """A one-sided Jacobi run that reaches its sweep limit while its last
+    sweep still rotated is an error (LSPCA_ENOCONV), never a silent result.
+    The limit is forced down to one sweep with the library's test knob; the
+    single-workgroup kernel (k <= 128), the cooperative block kernel and the
+    per-round launches are each covered."""
+    import torch
+    rng = np.random.default_rng(k)
+    F = torch.from_numpy(rng.standard_normal((k, 2 * k))).cuda()
+    if knob:
+        monkeypatch.setenv("LSPCA_JACOBI", knob)
+    monkeypatch.setenv("LSPCA_JACOBI_SWEEPS", "1")
+    with pytest.raises(gpu_lib.LspcaError) as e:
+        gpu_lib.factor(F)
+    assert e.value.name == "LSPCA_ENOCONV"
+    monkeypatch.delenv("LSPCA_JACOBI_SWEEPS")
+    V, s = gpu_lib.factor(F)
+    Vr, dr = O.truncated_svd(F.cpu().numpy(), k)
+    assert np.max(np.abs(s.cpu().numpy() - dr) / dr) < 1e-10

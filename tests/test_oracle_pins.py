@@ -332,6 +332,26 @@ def test_principal_sines_of_known_angles():
     assert abs(cd - math.sqrt(2) * np.linalg.norm(np.sin(t))) < 1e-14
 
 
+def test_pairwise_distances_hand_example():
+    """Euclidean distances of listed row pairs, written out by hand: a 3-4-5
+    triangle and more. A squared distance (25, 13, 2), the L1 distance (7, 5,
+    2) or an index mix-up gives other numbers."""
+    Z = np.array([[0.0, 0.0, 0.0],
+                  [3.0, 4.0, 0.0],
+                  [1.0, 1.0, 0.0],
+                  [1.0, 2.0, 2.0]])
+    pairs = [(0, 1), (1, 2), (0, 2), (3, 0), (2, 2)]
+    d = O.pairwise_distances(Z, pairs)
+    assert d.shape == (5,)
+    assert d[0] == 5.0
+    assert d[1] == math.sqrt(13.0)
+    assert d[2] == math.sqrt(2.0)
+    assert d[3] == 3.0                      # sqrt(1 + 4 + 4)
+    assert d[4] == 0.0
+    # symmetric in the pair's order, and one row of Z per index
+    assert np.array_equal(O.pairwise_distances(Z, [(1, 0), (2, 1)]), d[:2])
+
+
 def test_canonical_order_and_sign():
     V = np.array([[0.6, -0.8], [-0.8, -0.6]])
     s = np.array([1.0, 2.0])
