@@ -272,6 +272,33 @@ LSPCA_API int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t
                     const lspca_opts *opts);
 
 /*
+ * lspca_transform_noalloc -- lspca_transform for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc. Same arguments, kernels and results as
+ * lspca_transform (bitwise), but the one buffer the projection needs beyond
+ * X, V and Z (V^T in the type of X, two parts for BF16/FP16) lives in a
+ * fixed device array of LSPCA_NOALLOC_SCRATCH_BYTES that each device holds
+ * until the process ends; the call allocates nothing (no hipMalloc or
+ * hipFree, no library workspace, no events).
+ *  Limit: parts * size(X element) * n * k <= LSPCA_NOALLOC_SCRATCH_BYTES,
+ *  parts = 2 for BF16/FP16 and 1 otherwise, each part rounded up to 256
+ *  bytes: n * k <= 2^21 for FP64, 2^22 for FP32, BF16 and FP16. Larger
+ *  requests return E2BIG. opts->timing is ignored.
+ *  Every call on one device shares that device's array, which keeps the
+ *  last call's contents: calls that overlap on one device (several host
+ *  threads, or several streams whose work overlaps) race on it; the caller
+ *  orders them. Calls do not wait for other entry points, whose workspace
+ *  is separate.
+ *  The array's device address is looked up on the first call on each device
+ *  (with that device current). Errors: EINVAL, E2BIG, ENOTSUP (device
+ *  ordinal >= 64), EHIP. Asynchronous on opts->stream.
+ */
+#define LSPCA_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+LSPCA_API int lspca_transform_noalloc(const void *X, lspca_dtype xdt, int64_t r, int64_t n,
+                    int64_t ldx, const double *V, int32_t k, void *Z,
+                    const lspca_opts *opts);
+
+/*
  * Sparse X (Experiment 1, "Data and Method": the data are horizontal slices
  * of a sparse matrix with FP32 values; Proposition 4 prices both products
  * of the pass at O(nnz(X) l)). X is given in CSR form, all arrays on the

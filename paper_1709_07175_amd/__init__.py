@@ -32,7 +32,7 @@ STATUS = {0: "LSPCA_OK", -1: "LSPCA_EINVAL", -2: "LSPCA_ENOMEM", -3: "LSPCA_EHIP
 # Every symbol include/lspca.h declares.
 EXPORTS = ["lspca_version", "lspca_strerror", "lspca_last_error", "lspca_last_timings",
            "lspca_omega", "lspca_accumulate", "lspca_factor", "lspca_fit", "spca_fit",
-           "lspca_transform", "lspca_accumulate_host", "lspca_fit_host", "spca_fit_stream",
+           "lspca_transform", "lspca_transform_noalloc", "lspca_accumulate_host", "lspca_fit_host", "spca_fit_stream",
            "lspca_accumulate_csr", "lspca_fit_csr", "lspca_transform_csr", "spca_fit_csr",
            "lspca_server_create", "lspca_server_submit", "lspca_server_wait",
            "lspca_server_pause", "lspca_server_get_stats", "lspca_server_destroy"]
@@ -85,6 +85,8 @@ _SIGS = {
                   ctypes.POINTER(lspca_opts), _P, _P], ctypes.c_int),
     "lspca_transform": ([_P, ctypes.c_int, _I64, _I64, _I64, _P, _I32, _P,
                          ctypes.POINTER(lspca_opts)], ctypes.c_int),
+    "lspca_transform_noalloc": ([_P, ctypes.c_int, _I64, _I64, _I64, _P, _I32, _P,
+                                 ctypes.POINTER(lspca_opts)], ctypes.c_int),
     "spca_fit_stream": ([_P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
                          ctypes.POINTER(lspca_opts), _P, _P], ctypes.c_int),
     "lspca_accumulate_host": ([_P, ctypes.c_int, _I64, _I64, _I64, _I32, ctypes.c_int, _U64,
@@ -282,6 +284,31 @@ def transform(X, V, Z=None, **kw):
     o = _opts(**kw)
     _check(load().lspca_transform(X.data_ptr(), _dtype_code(X), r, n, ldx, _dev(V, "V").data_ptr(),
                                   k, Z.data_ptr(), ctypes.byref(o)))
+    return Z
+
+
+# Size of the fixed device array lspca_transform_noalloc uses (the header's
+# LSPCA_NOALLOC_SCRATCH_BYTES).
+NOALLOC_SCRATCH_BYTES = 16 << 20
+
+
+def transform_noalloc(X, V, Z, **kw):
+    """Z = X V like transform(), through lspca_transform_noalloc: the library
+    allocates nothing (V^T goes to its fixed per-device array), so Z must be
+    given. Calls that overlap on one device race on that array."""
+    torch = _torch()
+    ldx = _rowmajor(X)
+    r, n = X.shape
+    k = V.shape[1]
+    if V.dtype != torch.float64 or not V.is_contiguous():
+        raise ValueError("V must be a contiguous FP64 device tensor")
+    zdt = torch.float64 if X.dtype == torch.float64 else torch.float32
+    if Z.dtype != zdt or tuple(Z.shape) != (r, k) or not Z.is_contiguous():
+        raise ValueError(f"Z must be a contiguous {zdt} tensor of shape ({r}, {k})")
+    o = _opts(**kw)
+    _check(load().lspca_transform_noalloc(X.data_ptr(), _dtype_code(X), r, n, ldx,
+                                          _dev(V, "V").data_ptr(), k, _dev(Z, "Z").data_ptr(),
+                                          ctypes.byref(o)))
     return Z
 
 

@@ -713,6 +713,43 @@ static int csr_pass(const int64_t *rowptr, const int32_t *colidx, const void *va
   return LSPCA_OK;
 }
 
+// --------------------------------------- allocation-free projection -------
+// Scratch of lspca_transform_noalloc: V^T in the compute type of X (two
+// 16-bit parts for BF16/FP16 X), the only device memory that call uses
+// beyond its inputs and outputs. A file-scope device array, so the call
+// never allocates; every device holds its own copy until the process ends.
+// The host-side name is not a device address: host code uses the address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) char scratch[LSPCA_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+
+// The device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+static int noalloc_scratch(char **out) {
+  static std::mutex mu;
+  static char *ptrs[kMaxDevices] = {};
+  int dev = 0;
+  LSPCA_TRY(current_device(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device %d: lspca_transform_noalloc supports devices 0..%d", dev, kMaxDevices - 1);
+    return LSPCA_ENOTSUP;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptrs[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      set_error("hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+      return LSPCA_EHIP;
+    }
+    ptrs[dev] = (char *)p;
+  }
+  *out = ptrs[dev];
+  return LSPCA_OK;
+}
+
 }  // namespace lspca
 
 using namespace lspca;
@@ -861,6 +898,39 @@ int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t n, int64_
     LSPCA_TRY(launch_nt(xdt, X, ldx, VT, n, Z, k, r, k, (int)n, o.stream));
   tm.mark(PH_TRANSFORM);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
+  return LSPCA_OK;
+}
+
+int lspca_transform_noalloc(const void *X, lspca_dtype xdt, int64_t r, int64_t n, int64_t ldx,
+                            const double *V, int32_t k, void *Z, const lspca_opts *opts) {
+  Opts o;
+  LSPCA_TRY(read_opts(opts, o));
+  if (!valid_dtype(xdt)) { set_error("unknown dtype %d", (int)xdt); return LSPCA_EINVAL; }
+  if (r < 0 || n < 1 || k < 1 || ldx < n) { set_error("bad sizes (r=%lld n=%lld k=%d ldx=%lld)", (long long)r, (long long)n, k, (long long)ldx); return LSPCA_EINVAL; }
+  if (r == 0) return LSPCA_OK;
+  if (!X || !V || !Z) { set_error("X, V and Z must not be NULL"); return LSPCA_EINVAL; }
+  const size_t es = dtype_size(xdt);
+  const bool h16 = is16(xdt);
+  const size_t parts = h16 ? 2 : 1;
+  // V^T needs parts * es * n * k bytes (each part 256-byte aligned); checked
+  // by division first so n * k cannot overflow
+  const size_t cap = LSPCA_NOALLOC_SCRATCH_BYTES;
+  if ((size_t)n > cap / (parts * es) / (size_t)k ||
+      parts * ws_bytes<char>(es * (size_t)n * k) > cap) {
+    set_error("lspca_transform_noalloc: V^T of n=%lld x k=%d in the type of X needs more than the "
+              "%zu-byte scratch (n k <= %zu for this type)", (long long)n, k, cap, cap / (parts * es));
+    return LSPCA_E2BIG;
+  }
+  char *sp = nullptr;
+  LSPCA_TRY(noalloc_scratch(&sp));
+  char *VT = sp;
+  char *VTlo = h16 ? sp + ws_bytes<char>(es * (size_t)n * k) : nullptr;
+  LSPCA_TRY(launch_convert_vt(V, n, k, xdt, VT, VTlo, o.stream));
+  if (h16)
+    LSPCA_TRY(launch_nt16(xdt, X, ldx, VT, VTlo, n, (float *)Z, k, r, k, (int)n, nullptr, nullptr,
+                          nullptr, 0, o.stream));
+  else
+    LSPCA_TRY(launch_nt(xdt, X, ldx, VT, n, Z, k, r, k, (int)n, o.stream));
   return LSPCA_OK;
 }
 

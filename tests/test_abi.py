@@ -179,3 +179,18 @@ def test_csr_argument_checks(lib):
     assert tr(None, None, None, L.F32, 0, 10, 0, None, 3, None, None) == 0               # r = 0: no work
     assert tr(P, P, P, L.F32, 5, 10, 5, None, 3, F, None) == -1                          # V NULL
     assert tr(P, P, P, L.F32, -1, 10, 5, F, 3, G, None) == -1
+
+
+def test_transform_noalloc_argument_checks(lib):
+    tr = lib.lspca_transform_noalloc
+    assert tr(1 << 20, L.F32, 5, 10, 9, 1 << 21, 3, 1 << 22, None) == -1    # ldx < n
+    assert tr(None, L.F32, 0, 10, 10, None, 3, None, None) == 0             # r = 0: no work
+    assert tr(None, L.F32, 5, 10, 10, 1 << 21, 3, 1 << 22, None) == -1      # X NULL
+    assert tr(1 << 20, 9, 5, 10, 10, 1 << 21, 3, 1 << 22, None) == -1       # dtype
+    # V^T beyond the fixed scratch: refused before any device work
+    cap = L.NOALLOC_SCRATCH_BYTES
+    for dt, es, parts in ((L.F64, 8, 1), (L.F32, 4, 1), (L.BF16, 2, 2), (L.F16, 2, 2)):
+        nk = cap // (es * parts)
+        assert tr(1 << 20, dt, 5, nk // 256 + 1, nk // 256 + 1, 1 << 21, 256, 1 << 22, None) == -5
+        assert "scratch" in lib.lspca_last_error().decode()
+    assert tr(1 << 20, L.F32, 5, 1 << 40, 1 << 40, 1 << 21, 1 << 30, 1 << 22, None) == -5  # no overflow
