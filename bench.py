@@ -97,6 +97,78 @@ def roofline(cfg, m, n, k, xbytes, esz, sketch_ms):
             "algorithmic": f"X + Omega + Y = {alg_bytes:.4g} bytes per launch", "algorithmic_bytes": alg_bytes}
 
 
+def pass_rooflines(cfg, m, n, k, xbytes, esz, phases):
+    """Every kernel phase of the step against its bound (device times from the
+    library's events, averaged over the timed steps): the sketch, F = Y^T X,
+    the small FP64 stage (latency-bound: time only) and the projection."""
+    dt = cfg["dtype"]
+
+    def avg(key, which=0):
+        return sum(p[which][key] for p in phases) / len(phases)
+
+    h16 = dt in ("bf16", "f16")
+    mfma_peak = {"f64": PEAKS["fp64_mfma_TFs"], "f32": PEAKS["fp32_mfma_TFs"]}.get(dt, PEAKS["bf16_mfma_TFs"])
+    res = {"sketch": roofline(cfg, m, n, k, xbytes, esz, avg("sketch_ms"))}
+    f_ms = avg("factor_ms")
+    # F: one product per element for FP32/FP64, two for 16-bit data (the
+    # split sketch, Y_hi and Y_lo); the fits here ask for no Sigma^s, so the
+    # pass forms no G
+    flops = 2.0 * m * n * k * (2 if h16 else 1)
+    ybytes = m * k * (8 if dt == "f64" else 4)   # Y (FP64, FP32, or the two 16-bit parts)
+    f_bytes = xbytes + ybytes
+    tf = flops / (f_ms * 1e-3) / 1e12
+    res["F"] = {"kernel": "k_tn16 (F = Y_hi^T X + Y_lo^T X)" if h16 else "k_tn (F = Y^T X)",
+                "ms": round(f_ms, 4), "flop": flops, "TFLOPs": round(tf, 2),
+                "mfma_peak_TFs": mfma_peak, "mfma_frac": round(tf / mfma_peak, 4),
+                "hbm_bytes_algorithmic": f_bytes,
+                "hbm_frac": round(f_bytes / (f_ms * 1e-3) / 1e9 / PEAKS["hbm_GBs"], 4)}
+    res["small_fp64"] = {"ms": round(avg("small_ms"), 4), "bound": "latency"}
+    t_ms = avg("transform_ms", 1)
+    tflops = 2.0 * m * n * k * (2 if h16 else 1)
+    tbytes = xbytes + m * k * (8 if dt == "f64" else 4)
+    res["projection"] = {"kernel": "k_nt16 (Z = X V_hi + X V_lo)" if h16 else "k_nt (Z = X V)",
+                         "ms": round(t_ms, 4), "flop": tflops,
+                         "mfma_frac": round(tflops / (t_ms * 1e-3) / 1e12 / mfma_peak, 4),
+                         "hbm_frac": round(tbytes / (t_ms * 1e-3) / 1e9 / PEAKS["hbm_GBs"], 4)}
+    # the bound of the whole fit by the method's own work: X read once, the
+    # two products at the matrix-core peak (16-bit: with the refinement)
+    t_hbm = xbytes / (PEAKS["hbm_GBs"] * 1e9)
+    t_mfma = (2.0 * m * n * k + flops) / (mfma_peak * 1e12)
+    if cfg["kind"] == "sparse":
+        t_mfma = flops / (mfma_peak * 1e12)
+    bound_ms = max(t_hbm, t_mfma) * 1e3
+    res["fit_bound"] = {"ms": round(bound_ms, 4), "hbm_ms": round(t_hbm * 1e3, 4),
+                        "mfma_ms": round(t_mfma * 1e3, 4),
+                        "frac_fit": round(bound_ms / avg("total_ms"), 4),
+                        "frac_pass": round(bound_ms / (avg("sketch_ms") + f_ms + avg("reduce_ms") +
+                                                       avg("layout_ms")), 4)}
+    return res
+
+
+# The paper's own timings (context, not the target): the largest analysis of
+# Experiment 1 (Sec. I and Sec. IV-A), on one CPU machine.
+PAPER_CONTEXT = {
+    "spca_hours": 43.7, "lazy_spca_hours": 9.9, "speedup": round(43.7 / 9.9, 2),
+    "hardware": "one Amazon EC2 r3.8xlarge instance: 16 physical cores (32 hyperthreads), 244 GB RAM; "
+                "Julia v0.3.8, sparse products and QR in Intel MKL",
+    "workload": "sparse malware feature matrix, 4,608,517 samples x 98,450 features, mean density "
+                "0.0244, FP32 values, very sparse Omega; the k of the largest run is not stated "
+                "(k up to 20,000 in that experiment)",
+    "source": "Sec. I and Sec. IV-A of arXiv 1709.07175",
+}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -137,6 +209,7 @@ def cpu_baseline(cfg, X_dev, budget_s=20.0):
     esz = X_dev.element_size()
     gbs = 2 * rows * n * esz * len(times) / total / 1e9
     return {"value": round(gbs, 4), "unit": "GB/s", "cores": int(cores), "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"first {rows} rows of the same X (of {m}): FP64 oracle fit (Algorithm 2, "
                       f"numpy/BLAS) plus Z = X V, timed {len(times)}x, {total:.2f} s in all"}
 
@@ -328,7 +401,7 @@ def csr_cpu_baseline(c, rph, cih, vvh, budget_s=20.0):
     total = sum(times)
     nbytes = 2 * (8 * (rows + 1) + int(rph[rows]) * (4 + vvh.itemsize))
     return {"value": round(nbytes * len(times) / total / 1e9, 4), "unit": "GB/s", "cores": int(cores),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"first {rows} rows of the same CSR X: FP64 oracle fit (dense rows, numpy/BLAS) "
                       f"plus Z = X V, timed {len(times)}x, {total:.2f} s in all"}
 
@@ -450,8 +523,12 @@ def main():
                     help="skip the fit of an FP32 copy of 16-bit X (the plain FP32 path)")
     ap.add_argument("--no-host", action="store_true",
                     help="skip the fit of the same X from pinned host memory (Algorithm 4 streamed)")
-    ap.add_argument("--serve-counts", type=str, default="200,600,2000",
+    ap.add_argument("--serve-counts", type=str, default="1000,2000,4000",
                     help="requests at 50,200,800 QPS")
+    ap.add_argument("--also", type=str, default="1,3,4",
+                    help="other workloads measured after the headline one (sub-objects of the line); "
+                         "empty for none")
+    ap.add_argument("--also-steps", type=int, default=5)
     ap.add_argument("--serve-modes", type=str, default="device,host")
     ap.add_argument("--csr", action="store_true",
                     help="the sparse-X workload instead: CSR X 131,072 x 98,450 at density 0.0244 "
@@ -468,7 +545,7 @@ def main():
 
     import torch
     import paper_1709_07175_amd as lib
-    from synth import config, lowrank_torch
+    from synth import config
 
     lib.load()
     if args.csr:
@@ -476,9 +553,51 @@ def main():
     cfg = config(args.config)
     if args.m:
         cfg["m"] = args.m
-    m, n, k = cfg["m"], cfg["n"], cfg["k"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    out, X = dense_run(args, lib, torch, cfg, args.steps, args.warmup, headline=True)
+    m, n, k = cfg["m"], cfg["n"], cfg["k"]
+    if not args.no_serve and n == 4096 and k == 256:
+        # projection serving with the fitted V (the 4,096 x 256 map of this workload)
+        levels = (50, 200, 800)
+        counts = [int(c) for c in args.serve_counts.split(",")]
+        V, _ = lib.fit(X, k, cfg["kind"], cfg["omega_seed"], sparse_p=cfg.get("p", 64))
+        sv = serving(lib, V, X, levels, counts, args.serve_modes.split(","))
+        out["serving"] = sv
+        if "device" in sv:
+            out["projection_p99_ms"] = {q: sv["device"][q]["p99_ms"] for q in map(str, levels)}
+    if not args.no_cpu:
+        log("cpu baseline (oracle on a row sample)")
+        out["cpu_baseline"] = cpu_baseline(cfg, X)
+    del X
+    torch.cuda.empty_cache()
+    # the other workloads, each at its full size, fits and projections timed
+    # the same way (lighter: fewer steps, no serving, host or CPU legs)
+    extra = [int(c) for c in args.also.split(",") if c.strip()] if args.also else []
+    if extra:
+        out["workloads"] = {}
+    for cid in extra:
+        if cid == args.config:
+            continue
+        c2 = config(cid)
+        try:
+            sub, Xc = dense_run(args, lib, torch, c2, args.also_steps, 1, headline=False)
+            del Xc
+        except (RuntimeError, lib.LspcaError) as e:     # e.g. out of memory on a smaller device
+            sub = {"error": str(e)}
+        torch.cuda.empty_cache()
+        out["workloads"][str(cid)] = sub
+    out["paper_context"] = PAPER_CONTEXT
+    print(json.dumps(out), flush=True)
+
+
+def dense_run(args, lib, torch, cfg, steps, warmup, headline):
+    """One dense workload: `steps` timed steps (lspca_fit then lspca_transform
+    of the same X, inputs resident in HBM), the SPCA baselines on the same X
+    and, for 16-bit X, the plain FP32 path. Returns (record, X)."""
+    from synth import lowrank_torch
+    m, n, k = cfg["m"], cfg["n"], cfg["k"]
+    dev = torch.device("cuda:0")
     log(f"generating X {m}x{n} {cfg['dtype']} (seed {cfg['data_seed']})")
     t0 = time.time()
     X = lowrank_torch(m, n, cfg["r"], cfg["spectrum"], cfg["s"], cfg["data_seed"], cfg["dtype"],
@@ -487,34 +606,35 @@ def main():
     log(f"generated in {time.time() - t0:.1f}s")
     xbytes = X.numel() * X.element_size()
     stream = torch.cuda.current_stream()
-    if args.calib_gib > 0:
+    if headline and args.calib_gib > 0:
         calibrate(torch, dev, args.calib_gib)
+    sp = cfg.get("p", 64)
 
     def step(timing):
-        V, s = lib.fit(X, k, cfg["kind"], cfg["omega_seed"], timing=timing, sparse_p=cfg.get("p", 64))
+        V, s = lib.fit(X, k, cfg["kind"], cfg["omega_seed"], timing=timing, sparse_p=sp)
         tf = lib.last_timings() if timing else None
         Z = lib.transform(X, V, timing=timing)
         tt = lib.last_timings() if timing else None
         return V, s, Z, tf, tt
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         step(False)
         torch.cuda.synchronize()
-        log(f"warmup {i + 1}/{args.warmup} done")
+        log(f"warmup {i + 1}/{warmup} done")
 
     phases = []
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         _, _, _, tf, tt = step(True)
         phases.append((tf, tt))
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_step = ev0.elapsed_time(ev1) / args.steps
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (wall {wall / args.steps * 1e3:.3f})")
+    ms_step = ev0.elapsed_time(ev1) / steps
+    log(f"timed {steps} steps: {ms_step:.3f} ms/step (wall {wall / steps * 1e3:.3f})")
 
     def avg(key, which=0):
         return sum(p[which][key] for p in phases) / len(phases)
@@ -524,59 +644,70 @@ def main():
     sketch_ms = avg("sketch_ms", 0)
     factor_ms = avg("factor_ms", 0)
     small_ms = avg("small_ms", 0)
-    value = 2 * xbytes / (ms_step * 1e-3) / 1e9
-
+    pass_ms = sketch_ms + factor_ms + avg("reduce_ms") + avg("layout_ms")
+    workload = (f"lazy-spca fit+projection, X {m}x{n} {cfg['dtype']} low-rank+noise, "
+                f"{cfg['kind']} Omega, k={k}")
     out = {
         "metric": "X-stream GB/s (% HBM/MFMA roofline) per Lazy SPCA fit vs SPCA; projection p99 ms",
-        "value": round(value, 3),
+        "value": round(xbytes / (fit_ms * 1e-3) / 1e9, 3),
         "unit": "GB/s",
+        "value_basis": "bytes of X / device time of one whole lspca_fit (Omega, pass, small FP64 stage), "
+                       "averaged over the timed steps; each step also runs lspca_transform of the same X",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(ms_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"f64": "f64", "f32": "f32", "bf16": "bf16", "f16": "f16"}[cfg["dtype"]],
         "data": "synthetic",
-        "config": {"workload": f"lazy-spca fit+projection, X {m}x{n} {cfg['dtype']} low-rank+noise, "
-                               f"{cfg['kind']} Omega, k={k}",
-                   "m": m, "n": n, "k": k, "x_bytes": xbytes, "parallelism": "single-gpu"},
+        "config": {"workload": workload, "m": m, "n": n, "k": k, "x_bytes": xbytes,
+                   "parallelism": "single-gpu"},
         "phases_ms": {"fit_total": round(fit_ms, 4), "omega": round(avg("omega_ms"), 4),
                       "sketch": round(sketch_ms, 4), "layout": round(avg("layout_ms"), 4),
                       "factor_F_G": round(factor_ms, 4),
                       "reduce": round(avg("reduce_ms"), 4), "small_fp64": round(small_ms, 4),
                       "transform": round(tr_ms, 4)},
+        "fit_ms": round(fit_ms, 4),
         "fit_x_stream_GBs": round(xbytes / (fit_ms * 1e-3) / 1e9, 3),
-        "fit_pass_x_stream_GBs": round(xbytes / ((sketch_ms + factor_ms + avg('reduce_ms')) * 1e-3) / 1e9, 3),
+        "fit_pass_x_stream_GBs": round(xbytes / (pass_ms * 1e-3) / 1e9, 3),
+        "step_x_stream_GBs": round(2 * xbytes / (ms_step * 1e-3) / 1e9, 3),
         "transform_x_stream_GBs": round(xbytes / (tr_ms * 1e-3) / 1e9, 3),
         "roofline": roofline(cfg, m, n, k, xbytes, X.element_size(), sketch_ms),
+        "kernels": pass_rooflines(cfg, m, n, k, xbytes, X.element_size(), phases),
     }
+    if not headline:
+        out = {key: out[key] for key in ("value", "unit", "value_basis", "ms_per_step", "steps", "dtype",
+                                         "config", "phases_ms", "fit_ms", "fit_x_stream_GBs",
+                                         "fit_pass_x_stream_GBs", "step_x_stream_GBs",
+                                         "transform_x_stream_GBs", "roofline", "kernels")}
+    spca_steps = args.spca_steps if headline else 2
     if not args.no_spca:
         # the non-lazy baseline on the same X: Algorithm 1 with the GPU
         # tall-skinny Householder QR (two passes over X)
         try:
-            lib.spca_fit(X, k, cfg["kind"], cfg["omega_seed"], sparse_p=cfg.get("p", 64))
+            lib.spca_fit(X, k, cfg["kind"], cfg["omega_seed"], sparse_p=sp)
             torch.cuda.synchronize()
-            sp = []
-            for _ in range(args.spca_steps):
-                lib.spca_fit(X, k, cfg["kind"], cfg["omega_seed"], timing=True, sparse_p=cfg.get("p", 64))
-                sp.append(lib.last_timings())
-            sp_ms = sum(t["total_ms"] for t in sp) / len(sp)
+            sps = []
+            for _ in range(spca_steps):
+                lib.spca_fit(X, k, cfg["kind"], cfg["omega_seed"], timing=True, sparse_p=sp)
+                sps.append(lib.last_timings())
+            sp_ms = sum(t["total_ms"] for t in sps) / len(sps)
             out["spca"] = {
                 "fit_ms": round(sp_ms, 4),
                 "fit_x_stream_GBs": round(xbytes / (sp_ms * 1e-3) / 1e9, 3),
-                "phases_ms": {key: round(sum(t[key + "_ms"] for t in sp) / len(sp), 4)
+                "phases_ms": {key: round(sum(t[key + "_ms"] for t in sps) / len(sps), 4)
                               for key in ("omega", "sketch", "qr", "pass2", "reduce", "small")},
                 "lazy_fit_speedup": round(sp_ms / fit_ms, 3),
             }
             log(f"spca_fit {sp_ms:.3f} ms vs lazy fit {fit_ms:.3f} ms")
             # Algorithm 3: one pass with the R factor updated per stripe
-            lib.spca_fit_stream(X, k, cfg["kind"], cfg["omega_seed"], sparse_p=cfg.get("p", 64))
+            lib.spca_fit_stream(X, k, cfg["kind"], cfg["omega_seed"], sparse_p=sp)
             torch.cuda.synchronize()
             ss = []
-            for _ in range(args.spca_steps):
-                lib.spca_fit_stream(X, k, cfg["kind"], cfg["omega_seed"], timing=True, sparse_p=cfg.get("p", 64))
+            for _ in range(spca_steps):
+                lib.spca_fit_stream(X, k, cfg["kind"], cfg["omega_seed"], timing=True, sparse_p=sp)
                 ss.append(lib.last_timings())
             ss_ms = sum(t["total_ms"] for t in ss) / len(ss)
             out["spca_stream"] = {
@@ -593,11 +724,11 @@ def main():
         # the same values as FP32 through the plain FP32 path (exact copy)
         log("fit of an FP32 copy of X (plain FP32 path)")
         X32 = X.float()
-        lib.fit(X32, k, cfg["kind"], cfg["omega_seed"], sparse_p=cfg.get("p", 64))
+        lib.fit(X32, k, cfg["kind"], cfg["omega_seed"], sparse_p=sp)
         torch.cuda.synchronize()
         pts = []
         for _ in range(2):
-            lib.fit(X32, k, cfg["kind"], cfg["omega_seed"], timing=True, sparse_p=cfg.get("p", 64))
+            lib.fit(X32, k, cfg["kind"], cfg["omega_seed"], timing=True, sparse_p=sp)
             pts.append(lib.last_timings())
         p_ms = sum(t["total_ms"] for t in pts) / len(pts)
         out["fp32_plain"] = {"fit_ms": round(p_ms, 3),
@@ -608,17 +739,17 @@ def main():
         log(f"FP32 copy: fit {p_ms:.2f} ms vs {fit_ms:.2f} ms")
         del X32
         torch.cuda.empty_cache()
-    if not args.no_host:
+    if headline and not args.no_host:
         # Algorithm 4 with X in pinned host memory (the out-of-core regime):
         # host-to-device copies of stripes overlapped with the pass
         log("copying X to pinned host memory")
         Xh = torch.empty(X.shape, dtype=X.dtype, pin_memory=True)
         Xh.copy_(X)
         torch.cuda.synchronize()
-        lib.fit_host(Xh, k, cfg["kind"], cfg["omega_seed"], sparse_p=cfg.get("p", 64))
+        lib.fit_host(Xh, k, cfg["kind"], cfg["omega_seed"], sparse_p=sp)
         hts = []
         for _ in range(2):
-            lib.fit_host(Xh, k, cfg["kind"], cfg["omega_seed"], timing=True, sparse_p=cfg.get("p", 64))
+            lib.fit_host(Xh, k, cfg["kind"], cfg["omega_seed"], timing=True, sparse_p=sp)
             hts.append(lib.last_timings())
         h_ms = sum(t["total_ms"] for t in hts) / len(hts)
         out["fit_host"] = {"fit_ms": round(h_ms, 3), "x_stream_GBs": round(xbytes / (h_ms * 1e-3) / 1e9, 3),
@@ -627,19 +758,7 @@ def main():
                                    "previous stripe is processed (PCIe-inclusive, not the headline value)"}
         log(f"fit from host memory: {h_ms:.1f} ms")
         del Xh
-    if not args.no_serve and n == 4096 and k == 256:
-        # projection serving with the fitted V (the 4,096 x 256 map of this workload)
-        levels = (50, 200, 800)
-        counts = [int(c) for c in args.serve_counts.split(",")]
-        V, _ = lib.fit(X, k, cfg["kind"], cfg["omega_seed"], sparse_p=cfg.get("p", 64))
-        sv = serving(lib, V, X, levels, counts, args.serve_modes.split(","))
-        out["serving"] = sv
-        if "device" in sv:
-            out["projection_p99_ms"] = {q: sv["device"][q]["p99_ms"] for q in map(str, levels)}
-    if not args.no_cpu:
-        log("cpu baseline (oracle on a row sample)")
-        out["cpu_baseline"] = cpu_baseline(cfg, X)
-    print(json.dumps(out), flush=True)
+    return out, X
 
 
 if __name__ == "__main__":
