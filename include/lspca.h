@@ -378,13 +378,18 @@ LSPCA_API int lspca_transform_csr(const int64_t *rowptr, const int32_t *colidx, 
  * Requests enter a FIFO queue. The server's scheduler thread admits them in
  * order while fewer than max_inflight requests are admitted and unfinished
  * and, for host requests, while the staging arena has room for X and Z.
- * Admitted requests are packed, up to 64 at a time, into one launch of a
- * persistent kernel that walks the launch's row tiles across requests. Each
- * launch replays a HIP graph captured at creation (request-table upload and
- * kernel) and launches rotate over several streams, so requests that arrive
- * while others are on the device are launched at once and overlap them.
- * Each row is computed by the tile code lspca_transform uses, so a result
- * is bitwise the same alone, in any mix of requests, and as lspca_transform.
+ * Admitted requests are packed, up to 64 at a time, into one launch of
+ * persistent kernels that walk the launch's row tiles across requests: for
+ * BF16/FP16 data, requests of few rows (at most 4,096) take 32 x 64 tiles,
+ * so many workgroups share their walk over n, and the others the standard
+ * tiles. Each launch replays a HIP graph captured at creation (request-table
+ * upload and the kernels) and launches rotate over several streams, so
+ * requests that arrive while others are on the device are launched at once
+ * and overlap them. A request is launched from lspca_server_submit itself
+ * when a launch slot is free, else by the server's scheduler thread.
+ * Every tile shape computes an output element by the same chain of
+ * matrix-core steps as lspca_transform, so a result is bitwise the same
+ * alone, in any mix of requests, and as lspca_transform.
  * X and Z are both device pointers, or both host pointers (hipHostMalloc
  * memory gives asynchronous copies): host requests are copied into the
  * arena, projected there and copied back before they complete.

@@ -305,10 +305,13 @@ int small_factor(const double *F, const double *G, int k, int64_t n,
                  hipStream_t s, int *rank_flag, int route = 0);
 int launch_transpose_f64(const double *src, int64_t rows, int cols,
                          double *dst, hipStream_t s);
-// Request table of one batched projection launch (the projection server):
-// request i owns tiles [req[i].tile0, req[i+1].tile0), numbered row tile
-// major, ntn column tiles per row tile. X rows are n-contiguous (ldx), Z
-// rows k-contiguous (ldz).
+// Request table of one batched projection launch (the projection server).
+// Two tile classes (16-bit data): requests [0, nreq_s) use the small tiles
+// (proj_small_rows), requests [nreq_s, nreq) the standard ones. Within its
+// class, request i owns tiles [req[i].tile0, req[i+1].tile0), numbered row
+// tile major, ntn_s or ntn column tiles per row tile; ntiles_s and ntiles
+// count each class's tiles. X rows are n-contiguous (ldx), Z rows
+// k-contiguous (ldz).
 constexpr int kProjMaxReq = 64;
 struct ProjReq {
   const void *X;
@@ -317,9 +320,21 @@ struct ProjReq {
   int32_t tile0, pad;
 };
 struct ProjTable {
-  int32_t nreq, ntiles, ntn, pad;
+  int32_t nreq, ntiles, ntn, nreq_s;
+  int32_t ntiles_s, ntn_s, pad0, pad1;
   ProjReq req[kProjMaxReq];
 };
+// Small tiles of the 16-bit projection Z = X (V_hi + V_lo): 32 rows x 64
+// columns, two waves. Every output element is the same chain of matrix-core
+// steps (K ascending, V_hi then V_lo per step) in every tile shape, so a
+// row's bits do not depend on the tiles chosen. proj_small_rows: requests
+// (and lspca_transform calls) of at most this many rows use them (0 for
+// FP32/FP64 data, which has one tile class).
+constexpr int kProjSmallBM = 32, kProjSmallBN = 64;
+int64_t proj_small_rows(lspca_dtype dt);
+int proj_small_grid(lspca_dtype dt, bool vec, int *grid);
+int launch_proj_batch_small(lspca_dtype dt, const ProjTable *tab, const void *VTh, const void *VTl,
+                            int64_t ldv, int k, int n, bool vec, int grid, hipStream_t s);
 // Tile shape of the projection Z = X V for dtype dt and k columns: the one
 // lspca_transform uses, so a batched result is bitwise that of a single call.
 void proj_tile_shape(lspca_dtype dt, int k, int *BM, int *BN);

@@ -17,6 +17,8 @@
 //          fragment is one 16-byte read.
 #include "common.h"
 
+#include <cstdlib>
+
 namespace lspca {
 
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
@@ -60,6 +62,9 @@ enum { OUT_ROWS = 0, OUT_T32 = 1, OUT_TSPLIT = 2 };
 #endif
 #ifndef LSPCA_NT16_BK
 #define LSPCA_NT16_BK 64
+#endif
+#ifndef LSPCA_NT16_SMALL_STAGES
+#define LSPCA_NT16_SMALL_STAGES 3
 #endif
 // Row tile of the products whose B side is one column tile: the split-B
 // product with N > 128 (projection with k > 128) and with N <= 128, and the
@@ -114,7 +119,9 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
 
   // R register stages: the loads of K tile t + R are issued while tile t is
   // multiplied, so each load has R tile steps to arrive
-  constexpr int R = LSPCA_NT16_STAGES;
+  // the small projection tiles (one 32 x 32 block per wave, little work per
+  // K tile) keep more tiles in flight
+  constexpr int R = (BM == kProjSmallBM && BN == kProjSmallBN) ? LSPCA_NT16_SMALL_STAGES : LSPCA_NT16_STAGES;
   u16x8 ra[R][AV], rbh[R][BV], rbl[R][SPLITB ? BV : 1];
   // VEC: loads are issued unconditionally from clamped addresses (a row
   // past M or N only feeds outputs that are never written), so nothing
@@ -652,6 +659,12 @@ template <int DT, bool SPLITB, int OUT>
 static int nt16_n(const uint16_t *A, int64_t lda, const uint16_t *Bh, const uint16_t *Bl,
                   int64_t ldb, float *C, int64_t ldc, int64_t M, int N, int K, unsigned *colmax,
                   uint16_t *Ch, uint16_t *Cl, hipStream_t s) {
+  // projections of few rows: the small tiles (same bits per row, lower
+  // latency: many workgroups share the walk over K)
+  if constexpr (SPLITB && OUT == OUT_ROWS)
+    if (M <= proj_small_rows((lspca_dtype)DT))
+      return nt16_typed<DT, kProjSmallBM, kProjSmallBN, true, OUT, 1, 2>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K,
+                                                                       colmax, Ch, Cl, s);
   constexpr int BMW = SPLITB ? LSPCA_NT16_PROJ_BM : 128;
   constexpr int BMN = SPLITB ? LSPCA_NT16_PROJ_BM_NARROW : LSPCA_NT16_SKETCH_BM;
   // waves of the split-B (projection) product: 2 x 2, or eight as 2 x 4
@@ -704,7 +717,7 @@ __global__ __launch_bounds__(kProjThreads) void k_proj_batch16(const ProjTable *
                                                       int N, int K) {
   const int ntiles = tab->ntiles, nreq = tab->nreq, ntn = tab->ntn;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int lo = 0, hi = nreq - 1;
+    int lo = tab->nreq_s, hi = nreq - 1;             // the standard-tile requests
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
       if (tab->req[mid].tile0 <= t) lo = mid;
@@ -716,6 +729,72 @@ __global__ __launch_bounds__(kProjThreads) void k_proj_batch16(const ProjTable *
         (const uint16_t *)rq.X, rq.ldx, Vh, Vl, ldv, (float *)rq.Z, rq.ldz, rq.rows, N, K, nullptr, nullptr,
         nullptr, (int64_t)mt * BM, (local - mt * ntn) * BN);
   }
+}
+
+// The small-tile class: requests [0, nreq_s) of the table, 32 x 64 tiles of
+// two waves each (the same per-element chain as every other tile shape).
+constexpr int kProjSmallThreads = 128;
+template <int DT, bool VEC>
+__global__ __launch_bounds__(kProjSmallThreads) void k_proj_batch16s(const ProjTable *__restrict__ tab,
+                                                            const uint16_t *__restrict__ Vh,
+                                                            const uint16_t *__restrict__ Vl,
+                                                            int64_t ldv, int N, int K) {
+  const int ntiles = tab->ntiles_s, nreq = tab->nreq_s, ntn = tab->ntn_s;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    int lo = 0, hi = nreq - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (tab->req[mid].tile0 <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const ProjReq &rq = tab->req[lo];
+    const int local = t - rq.tile0, mt = local / ntn;
+    nt16_tile<DT, kProjSmallBM, kProjSmallBN, true, VEC, OUT_ROWS, 1, 2>(
+        (const uint16_t *)rq.X, rq.ldx, Vh, Vl, ldv, (float *)rq.Z, rq.ldz, rq.rows, N, K, nullptr, nullptr,
+        nullptr, (int64_t)mt * kProjSmallBM, (local - mt * ntn) * kProjSmallBN);
+  }
+}
+
+static const void *proj16s_kernel(lspca_dtype dt, bool vec) {
+  if (dt == LSPCA_BF16)
+    return vec ? (const void *)&k_proj_batch16s<LSPCA_BF16, true> : (const void *)&k_proj_batch16s<LSPCA_BF16, false>;
+  return vec ? (const void *)&k_proj_batch16s<LSPCA_F16, true> : (const void *)&k_proj_batch16s<LSPCA_F16, false>;
+}
+
+// Rows up to which the 16-bit projection uses the small tiles: below it the
+// latency of one standard tile (one workgroup walking all of K for a
+// 256-column block) dominates; above it the standard tiles read V fewer
+// times. LSPCA_PROJ_SMALL_ROWS overrides it (a tuning and test knob).
+#ifndef LSPCA_PROJ_SMALL_ROWS
+#define LSPCA_PROJ_SMALL_ROWS 8192
+#endif
+int64_t proj_small_rows(lspca_dtype dt) {
+  if (dt != LSPCA_BF16 && dt != LSPCA_F16) return 0;
+  if (const char *e = getenv("LSPCA_PROJ_SMALL_ROWS")) {
+    const long long x = atoll(e);
+    return x > 0 ? (int64_t)x : 0;
+  }
+  return LSPCA_PROJ_SMALL_ROWS;
+}
+
+int proj_small_grid(lspca_dtype dt, bool vec, int *grid) {
+  int dev = 0, cus = 0, per = 0;
+  LSPCA_HIP(hipGetDevice(&dev));
+  LSPCA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  LSPCA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, proj16s_kernel(dt, vec), kProjSmallThreads, 0));
+  *grid = cus * (per > 0 ? per : 1);
+  return LSPCA_OK;
+}
+
+int launch_proj_batch_small(lspca_dtype dt, const ProjTable *tab, const void *VTh, const void *VTl,
+                            int64_t ldv, int k, int n, bool vec, int grid, hipStream_t s) {
+  if (dt != LSPCA_BF16 && dt != LSPCA_F16) {
+    set_error("small projection tiles: dtype %d (16-bit only)", (int)dt);
+    return LSPCA_ENOTSUP;
+  }
+  void *args[] = {(void *)&tab, (void *)&VTh, (void *)&VTl, (void *)&ldv, (void *)&k, (void *)&n};
+  LSPCA_HIP(hipLaunchKernel(proj16s_kernel(dt, vec), dim3(grid), dim3(kProjSmallThreads), args, 0, s));
+  return LSPCA_OK;
 }
 
 template <int DT, int BN, bool VEC> static const void *proj16_fn() {

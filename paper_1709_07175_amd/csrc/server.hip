@@ -1,12 +1,13 @@
 // Projection server: continuous batching of Z = X V requests (the map of
 // eq. (dim_reduction_maps)) with V resident on the device.
 //
-// Host side: submit() appends to a FIFO queue; a scheduler thread (the only
-// thread that touches HIP streams) retires finished launches, admits queued
-// requests while fewer than max_inflight are unfinished and, for requests
-// in host memory, while the staging arena has room, then packs admitted
-// requests (up to kProjMaxReq) into the request table of a free launch
-// slot. Each slot owns a pinned host table, a device table and a HIP graph
+// Host side: submit() appends to a FIFO queue; admission and launches
+// happen under the server's lock, in submit() itself when a launch slot is
+// free and otherwise in a scheduler thread that also retires finished
+// launches. Queued requests are admitted while fewer than max_inflight are
+// unfinished and, for requests in host memory, while the staging arena has
+// room; admitted requests (up to kProjMaxReq) are packed into the request
+// table of a free launch slot. Each slot owns a pinned host table, a device table and a HIP graph
 // captured at creation (table upload + the persistent batch kernel); slots
 // rotate over several streams, so a launch made while others run overlaps
 // them on the device. Completion is seen by polling each slot's event.
@@ -40,6 +41,7 @@ struct Request {
   bool host = false;
   size_t off = 0, bx = 0, bz = 0;      // arena block of a host request: X then Z
   int64_t tiles = 0;
+  bool small = false;                  // small-tile class (few rows, 16-bit data)
   Clock::time_point t_submit, t_launch, t_done;
   int64_t enqueue_ns = 0;
   int status = 1;                      // 1 while pending; then LSPCA_OK or an error
@@ -115,6 +117,8 @@ struct lspca_server {
   lspca::Arena alloc;
   int max_inflight = 1, queue_cap = 16;
   int BM = 128, BN = 128, ntn = 1, grid = 256;
+  int64_t small_rows = 0;              // requests of at most this many rows: small tiles
+  int ntn_s = 1, grid_s = 0;
   bool vec = false;
   hipStream_t streams[lspca::kStreams] = {};
   lspca::Slot slots[lspca::kSlots];
@@ -164,27 +168,38 @@ bool launch_one(lspca_server *S) {
     }
   if (!sl) return false;
   ProjTable *t = sl->host_tab;
-  int nreq = 0;
-  int64_t tiles = 0;
-  while (!S->ready.empty() && nreq < kProjMaxReq) {
+  // take requests in FIFO order; small-tile ones go first in the table
+  int64_t tiles[2] = {0, 0};
+  while (!S->ready.empty() && (int)sl->reqs.size() < kProjMaxReq) {
     Request *r = S->ready.front();
-    if (nreq > 0 && tiles + r->tiles > (int64_t)1 << 30) break;
+    if (!sl->reqs.empty() && tiles[r->small] + r->tiles > (int64_t)1 << 30) break;
     S->ready.pop_front();
-    ProjReq &q = t->req[nreq++];
-    q.X = r->host ? (const void *)(S->arena + r->off) : r->X;
-    q.Z = r->host ? (void *)(S->arena + r->off + r->bx) : r->Z;
-    q.ldx = S->n;
-    q.ldz = S->k;
-    q.rows = r->rows;
-    q.tile0 = (int32_t)tiles;
-    q.pad = 0;
-    tiles += r->tiles;
+    tiles[r->small] += r->tiles;
     sl->reqs.push_back(r);
   }
+  int nreq = 0;
+  int64_t t0[2] = {0, 0};
+  for (int cls = 1; cls >= 0; --cls)
+    for (Request *r : sl->reqs) {
+      if ((int)r->small != cls) continue;
+      ProjReq &q = t->req[nreq++];
+      q.X = r->host ? (const void *)(S->arena + r->off) : r->X;
+      q.Z = r->host ? (void *)(S->arena + r->off + r->bx) : r->Z;
+      q.ldx = S->n;
+      q.ldz = S->k;
+      q.rows = r->rows;
+      q.tile0 = (int32_t)t0[cls];
+      q.pad = 0;
+      t0[cls] += r->tiles;
+    }
   t->nreq = nreq;
-  t->ntiles = (int32_t)tiles;
+  t->ntiles = (int32_t)tiles[0];
   t->ntn = S->ntn;
-  t->pad = 0;
+  t->ntiles_s = (int32_t)tiles[1];
+  t->ntn_s = S->ntn_s;
+  t->nreq_s = 0;
+  for (Request *r : sl->reqs) t->nreq_s += r->small ? 1 : 0;
+  t->pad0 = t->pad1 = 0;
   const auto t_start = Clock::now();
   hipError_t e = hipSuccess;
   for (Request *r : sl->reqs)
@@ -217,6 +232,27 @@ bool launch_one(lspca_server *S) {
   return true;
 }
 
+// Admit queued requests in FIFO order and launch what is admitted (called
+// with S->mu held, by the scheduler and by submit). Returns whether
+// anything moved.
+bool pump(lspca_server *S) {
+  bool progressed = false;
+  while (!S->pending.empty() && S->inflight < S->max_inflight) {
+    Request *r = S->pending.front();
+    if (r->host) {
+      if (!S->alloc.alloc(r->bx + r->bz, &r->off)) break;
+      if (S->alloc.used() > S->st.arena_peak_bytes) S->st.arena_peak_bytes = S->alloc.used();
+    }
+    S->pending.pop_front();
+    ++S->inflight;
+    S->ready.push_back(r);
+    progressed = true;
+  }
+  if (!S->paused)
+    while (!S->ready.empty() && launch_one(S)) progressed = true;
+  return progressed;
+}
+
 void scheduler(lspca_server *S) {
   (void)hipSetDevice(S->dev);
   std::unique_lock<std::mutex> lk(S->mu);
@@ -234,21 +270,8 @@ void scheduler(lspca_server *S) {
       progressed = true;
     }
     if (progressed) S->cv_done.notify_all();
-    // admit in FIFO order
-    while (!S->pending.empty() && S->inflight < S->max_inflight) {
-      Request *r = S->pending.front();
-      if (r->host) {
-        if (!S->alloc.alloc(r->bx + r->bz, &r->off)) break;
-        if (S->alloc.used() > S->st.arena_peak_bytes) S->st.arena_peak_bytes = S->alloc.used();
-      }
-      S->pending.pop_front();
-      ++S->inflight;
-      S->ready.push_back(r);
-      progressed = true;
-    }
-    // launch
-    if (!S->paused)
-      while (!S->ready.empty() && launch_one(S)) progressed = true;
+    // admit in FIFO order and launch
+    if (pump(S)) progressed = true;
     if (S->stop && S->pending.empty() && S->ready.empty() && busy_slots(S) == 0) break;
     if (progressed) continue;
     if (busy_slots(S) > 0) {
@@ -302,9 +325,15 @@ int create_resources(lspca_server *S, const double *V) {
     LSPCA_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
     LSPCA_HIP(hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal));
     hipError_t e = hipMemcpyAsync(sl.dev_tab, sl.host_tab, sizeof(ProjTable), hipMemcpyHostToDevice, sl.stream);
-    int rc = e == hipSuccess ? launch_proj_batch(S->xdt, sl.dev_tab, S->VTh, S->VTl, S->n, S->k, (int)S->n, S->vec,
-                                                 S->grid, sl.stream)
-                             : LSPCA_EHIP;
+    // the small-tile kernel first (the latency-bound requests), then the
+    // standard one; a class with no tiles in a launch exits at once
+    int rc = e == hipSuccess ? LSPCA_OK : LSPCA_EHIP;
+    if (rc == LSPCA_OK && S->small_rows > 0)
+      rc = launch_proj_batch_small(S->xdt, sl.dev_tab, S->VTh, S->VTl, S->n, S->k, (int)S->n, S->vec,
+                                   S->grid_s, sl.stream);
+    if (rc == LSPCA_OK)
+      rc = launch_proj_batch(S->xdt, sl.dev_tab, S->VTh, S->VTl, S->n, S->k, (int)S->n, S->vec, S->grid,
+                             sl.stream);
     const hipError_t ee = hipStreamEndCapture(sl.stream, &sl.graph);
     if (e != hipSuccess) {
       set_error("server: table upload capture failed: %s", hipGetErrorString(e));
@@ -351,6 +380,12 @@ int lspca_server_create(const double *V, int64_t n, int32_t k, lspca_dtype xdt, 
     S->vec = (n * (int64_t)S->esz) % 16 == 0;
     rc = lspca::proj_batch_grid(xdt, k, S->vec, &S->grid);
     if (rc != LSPCA_OK) break;
+    S->small_rows = lspca::proj_small_rows(xdt);
+    if (S->small_rows > 0) {
+      S->ntn_s = (k + lspca::kProjSmallBN - 1) / lspca::kProjSmallBN;
+      rc = lspca::proj_small_grid(xdt, S->vec, &S->grid_s);
+      if (rc != LSPCA_OK) break;
+    }
     rc = lspca::create_resources(S, V);
   } while (false);
   if (rc != LSPCA_OK) {
@@ -379,7 +414,9 @@ int lspca_server_submit(lspca_server *S, const void *X, int64_t r, void *Z, uint
     q->host = hx;
     if (!hx && S->vec && (uintptr_t)X % 16 != 0) { delete q; set_error("device X must be 16-byte aligned"); return LSPCA_EINVAL; }
     if (!hx && (uintptr_t)Z % S->zsz != 0) { delete q; set_error("Z misaligned"); return LSPCA_EINVAL; }
-    q->tiles = (r + S->BM - 1) / S->BM * S->ntn;
+    q->small = r <= S->small_rows;
+    q->tiles = q->small ? (r + lspca::kProjSmallBM - 1) / lspca::kProjSmallBM * S->ntn_s
+                        : (r + S->BM - 1) / S->BM * S->ntn;
     if (hx) {
       q->bx = lspca::round_up((size_t)r * S->n * S->esz);
       q->bz = lspca::round_up((size_t)r * S->k * S->zsz);
@@ -409,6 +446,10 @@ int lspca_server_submit(lspca_server *S, const void *X, int64_t r, void *Z, uint
     return LSPCA_OK;
   }
   S->pending.push_back(q);
+  // admit and launch from the submitting thread when a slot is free (no
+  // wake-up of the scheduler on the request's path); the scheduler is woken
+  // to retire it
+  if (S->th.joinable() && !S->stop) (void)lspca::pump(S);
   S->cv_sched.notify_one();
   return LSPCA_OK;
 }

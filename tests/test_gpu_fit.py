@@ -329,6 +329,28 @@ def test_transform_rows_are_independent(gpu_lib):
         assert np.array_equal(Zp, Zall[r0:r1])
 
 
+@pytest.mark.parametrize("dtype,n,k", [("bf16", 4096, 256), ("f16", 2048, 128), ("bf16", 203, 17),
+                                       ("f16", 520, 100)])
+def test_transform_small_and_standard_tiles_agree_bitwise(gpu_lib, monkeypatch, dtype, n, k):
+    """16-bit projections of few rows take 32 x 64 tiles; every tile shape
+    runs the same chain of matrix-core steps per output element, so the
+    rows are bitwise those of the standard tiles (n = 203: element loads)."""
+    import torch
+    Xs, _ = _data(5000, n, min(k, 16), dtype, seed=4)
+    X = to_device(Xs, dtype)
+    V = torch.from_numpy(random_orthonormal_np(n, k, np.random.default_rng(3))).cuda()
+    for r in (1, 31, 33, 300, 4096, 5000):
+        monkeypatch.setenv("LSPCA_PROJ_SMALL_ROWS", "0")           # standard tiles only
+        Zb = gpu_lib.transform(X[:r], V)
+        monkeypatch.setenv("LSPCA_PROJ_SMALL_ROWS", "1000000")     # small tiles only
+        Zs = gpu_lib.transform(X[:r], V)
+        monkeypatch.delenv("LSPCA_PROJ_SMALL_ROWS")
+        Zd = gpu_lib.transform(X[:r], V)                           # the default choice
+        torch.cuda.synchronize()
+        assert torch.equal(Zs, Zb), (dtype, n, k, r)
+        assert torch.equal(Zd, Zb), (dtype, n, k, r)
+
+
 # --------------------------------------------------------------- 16-bit --
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])

@@ -92,6 +92,47 @@ def test_alone_mix_and_transform_agree_bitwise(gpu_lib, dtype, n, k):
         assert np.all(np.abs(Z.cpu().numpy().astype(np.float64) - ref) <= _bound(X64[r0:r0 + r], Vq, dtype))
 
 
+def test_small_tile_class_gives_the_standard_bits(gpu_lib, monkeypatch):
+    """A server whose requests all take the standard tiles (small class
+    switched off) and the default one (requests of at most 4,096 rows in
+    32 x 64 tiles) give the same bits, alone and with both classes in one
+    launch."""
+    import torch
+    n, k, total = 4096, 256, 12000
+    Xs, _ = _pool(total, n, "bf16", seed=14)
+    X = to_device(Xs, "bf16")
+    V = _v(n, k, seed=15)
+    sizes = [1, 7, 64, 500, 4096, 4097, 9000, 3]
+    rng = np.random.default_rng(6)
+    reqs = _slices(total, sizes, rng)
+    outs = {}
+    for label, env in (("standard", "0"), ("default", None)):
+        if env is None:
+            monkeypatch.delenv("LSPCA_PROJ_SMALL_ROWS", raising=False)
+        else:
+            monkeypatch.setenv("LSPCA_PROJ_SMALL_ROWS", env)
+        with gpu_lib.Server(V, CODE["bf16"], max_inflight=16) as srv:
+            Zs = [torch.full((r, k), float("nan"), dtype=torch.float32, device="cuda") for _, r in reqs]
+            Zm = [torch.full((r, k), float("nan"), dtype=torch.float32, device="cuda") for _, r in reqs]
+            torch.cuda.synchronize()
+            for (r0, r), Z in zip(reqs, Zs):                       # one at a time
+                srv.wait(srv.submit(X[r0:r0 + r], Z))
+            srv.pause(True)                                         # all in one launch
+            tickets = [srv.submit(X[r0:r0 + r], Z) for (r0, r), Z in zip(reqs, Zm)]
+            srv.pause(False)
+            for t in tickets:
+                srv.wait(t)
+            assert srv.stats()["max_requests_per_launch"] == len(reqs)
+        outs[label] = (Zs, Zm)
+    monkeypatch.delenv("LSPCA_PROJ_SMALL_ROWS", raising=False)
+    for i, (r0, r) in enumerate(reqs):
+        ref = outs["standard"][0][i]
+        assert torch.equal(outs["standard"][1][i], ref), r
+        assert torch.equal(outs["default"][0][i], ref), r
+        assert torch.equal(outs["default"][1][i], ref), r
+        assert torch.equal(gpu_lib.transform(X[r0:r0 + r], V), ref), r
+
+
 def test_overlapping_submissions_complete_correctly(gpu_lib):
     """Requests submitted while earlier ones run (no pause): log-uniform row
     counts as the serving workload, every result bitwise its lone value."""
