@@ -421,7 +421,11 @@ __global__ __launch_bounds__(64 * WR * WC) void k_tn16(const uint16_t *__restric
   // register stages: one fewer for the wide refined tile and for 256
   // accumulators per lane (the ring would not fit the register file next to
   // the accumulators)
+#ifdef LSPCA_TN16_R
+  constexpr int R = LSPCA_TN16_R;
+#else
   constexpr int R = (((BN > 128 && REFINE) || TM * TN >= 16) && LSPCA_TN16_STAGES > 2) ? 2 : LSPCA_TN16_STAGES;
+#endif
   static_assert(XP >= 1 && AV >= 1, "tile too small");
   __shared__ uint16_t As[2][NPART * BM * LD];
   __shared__ uint16_t Bs[2][BN * LD];
