@@ -13,8 +13,9 @@
 //    L2, for rows with ordered columns; k_csr_spmm (one wave per row)
 //    otherwise.
 //  * the column-ordered form of a stripe of rows in row blocks, built on
-//    the device by a stable radix sort, so every column sum has a fixed
-//    order.
+//    the device by a stable LSD radix sort (own kernels: per-tile digit
+//    counts, a prefix sum over (digit, tile), a ranked scatter), so every
+//    column sum has a fixed order.
 //  * k_csc_block: F += Y^T X, one row block per launch, one column slice of
 //    the block's sketch rows per XCD, FP64 sums; columns are cut into
 //    segments (one wave each) so a dense column does not serialise the
@@ -25,10 +26,298 @@
 // any kernel indexes with them.
 #include "common.h"
 
-#include <hipcub/device/device_radix_sort.hpp>
-#include <hipcub/device/device_scan.hpp>
+#include <algorithm>
+#include <utility>
 
 namespace lspca {
+
+// ---- exclusive prefix sums (int32 or int64 counts): per-tile sums, one
+// workgroup scanning the tile sums, per-tile rescans adding the tile's
+// offset. Integer sums, so the order does not matter for the result.
+constexpr int kScanThreads = 256, kScanItems = 16, kScanTile = kScanThreads * kScanItems;
+
+// Exclusive scan of v over the workgroup's 256 threads; *total gets the sum.
+template <typename T>
+__device__ T wg_exclusive_scan(T v, T *lds, T *total) {
+  const int t = threadIdx.x;
+  lds[t] = v;
+  __syncthreads();
+  for (int d = 1; d < kScanThreads; d <<= 1) {
+    const T x = t >= d ? lds[t - d] : T(0);
+    __syncthreads();
+    lds[t] += x;
+    __syncthreads();
+  }
+  *total = lds[kScanThreads - 1];
+  const T incl = lds[t];
+  __syncthreads();
+  return incl - v;
+}
+
+// tile[] (kScanTile, LDS) <- in[b0 ...] (zeros past count), loaded striped
+template <typename T>
+__device__ void scan_load(const T *__restrict__ in, int64_t b0, int64_t count, T *tile) {
+  for (int i = threadIdx.x; i < kScanTile; i += kScanThreads) tile[i] = b0 + i < count ? in[b0 + i] : T(0);
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_tile_sums(const T *__restrict__ in, int64_t count,
+                                                        T *__restrict__ sums) {
+  __shared__ T tile[kScanTile];
+  __shared__ T lds[kScanThreads];
+  scan_load(in, (int64_t)blockIdx.x * kScanTile, count, tile);
+  T v = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) v += tile[threadIdx.x * kScanItems + i];
+  T total;
+  (void)wg_exclusive_scan(v, lds, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of one tile in LDS with a starting offset; returns the
+// tile's total (every thread).
+template <typename T>
+__device__ T scan_tile_lds(T *tile, T *lds, T offset) {
+  T v = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) v += tile[threadIdx.x * kScanItems + i];
+  T total;
+  T run = offset + wg_exclusive_scan(v, lds, &total);
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    const T x = tile[threadIdx.x * kScanItems + i];
+    tile[threadIdx.x * kScanItems + i] = run;
+    run += x;
+  }
+  __syncthreads();
+  return total;
+}
+
+// In-place exclusive scan of the tile sums by one workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_sums(T *__restrict__ sums, int64_t count) {
+  __shared__ T tile[kScanTile];
+  __shared__ T lds[kScanThreads];
+  T carry = 0;
+  for (int64_t b0 = 0; b0 < count; b0 += kScanTile) {
+    scan_load(sums, b0, count, tile);
+    const T total = scan_tile_lds(tile, lds, carry);
+    for (int i = threadIdx.x; i < kScanTile; i += kScanThreads)
+      if (b0 + i < count) sums[b0 + i] = tile[i];
+    carry += total;
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_scan_apply(const T *__restrict__ in, int64_t count,
+                                                    const T *__restrict__ sums, T *__restrict__ out) {
+  __shared__ T tile[kScanTile];
+  __shared__ T lds[kScanThreads];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanTile;
+  scan_load(in, b0, count, tile);
+  (void)scan_tile_lds(tile, lds, sums[blockIdx.x]);
+  for (int i = threadIdx.x; i < kScanTile; i += kScanThreads)
+    if (b0 + i < count) out[b0 + i] = tile[i];
+}
+
+template <typename T> size_t scan_temp_bytes(int64_t count) {
+  return ((count + kScanTile - 1) / kScanTile) * sizeof(T) + 256;
+}
+
+// out[i] = sum of in[0 .. i) for i < count (in and out may not overlap).
+template <typename T>
+int exclusive_scan(const T *in, T *out, int64_t count, void *temp, size_t temp_bytes, hipStream_t s) {
+  if (count <= 0) return LSPCA_OK;
+  const int64_t tiles = (count + kScanTile - 1) / kScanTile;
+  if (temp_bytes < (size_t)tiles * sizeof(T)) {
+    set_error("scan: temporary buffer too small");
+    return LSPCA_EINVAL;
+  }
+  T *sums = (T *)temp;
+  hipLaunchKernelGGL(k_scan_tile_sums<T>, (unsigned)tiles, kScanThreads, 0, s, in, count, sums);
+  LSPCA_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_scan_sums<T>, 1, kScanThreads, 0, s, sums, tiles);
+  LSPCA_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_scan_apply<T>, (unsigned)tiles, kScanThreads, 0, s, in, count, (const T *)sums, out);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+// ---- stable LSD radix sort of (key, value) pairs: digits of up to 10 bits,
+// one pass for keys below 2^10, two below 2^20, three below 2^30. Per pass:
+// digit counts of each tile of 4,096 pairs (LDS atomics; counts only), an
+// exclusive scan of the counts in (digit, tile) order, then a scatter in
+// which each pair's rank within its digit follows its position in the tile
+// (earlier waves' quarters, earlier rounds, lower lanes), so equal keys keep
+// their input order; the tile's pairs are placed in LDS grouped by digit and
+// written out in that order, so each digit's pairs leave as one contiguous
+// run.
+constexpr int kSortMaxBits = 10, kSortBuckets = 1 << kSortMaxBits, kSortThreads = 256, kSortRounds = 16;
+constexpr int kSortTile = kSortThreads * kSortRounds;
+static_assert(kSortBuckets % kScanThreads == 0, "digits per thread in the tile scan");
+
+__global__ __launch_bounds__(256) void k_radix_count(const uint32_t *__restrict__ keys, int64_t cnt, int shift,
+                                                     int dbits, int64_t ntiles, int32_t *__restrict__ counts) {
+  __shared__ int32_t h[kSortBuckets];
+  const int nb = 1 << dbits;
+  for (int d = threadIdx.x; d < nb; d += kSortThreads) h[d] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + r * kSortThreads + threadIdx.x;
+    if (i < cnt) atomicAdd(&h[(keys[i] >> shift) & (nb - 1)], 1);
+  }
+  __syncthreads();
+  for (int d = threadIdx.x; d < nb; d += kSortThreads) counts[(int64_t)d * ntiles + blockIdx.x] = h[d];
+}
+
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint32_t *__restrict__ kin,
+                                                       const uint32_t *__restrict__ vin, int64_t cnt, int shift,
+                                                       int dbits, int64_t ntiles, const int32_t *__restrict__ offs,
+                                                       uint32_t *__restrict__ kout, uint32_t *__restrict__ vout) {
+  // wave w ranks the tile's pairs [w * 1024, (w + 1) * 1024) in order (16
+  // rounds of 64 lanes) against its own per-digit counts, so the waves need
+  // no barrier until the tile's totals are combined
+  __shared__ int32_t wrun[4][kSortBuckets];      // pairs of the digit ranked so far by the wave
+  __shared__ int32_t start[kSortBuckets];        // the digit's first slot in the tile's order
+  __shared__ int32_t obase[kSortBuckets];        // output position of slot 0 of the digit's run
+  __shared__ uint32_t lk[kSortTile], lv[kSortTile];
+  __shared__ int32_t scan_tmp[kScanThreads];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int nb = 1 << dbits, mask = nb - 1;
+  const uint64_t lower = lane ? (~0ull >> (64 - lane)) : 0ull;
+  for (int d = t; d < nb; d += kSortThreads) wrun[0][d] = wrun[1][d] = wrun[2][d] = wrun[3][d] = 0;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile + w * (kSortTile / 4);
+  uint32_t key[kSortRounds], val[kSortRounds];
+  int slot[kSortRounds];
+  // all of the wave's loads first, so they are in flight together
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int64_t i = base + r * 64 + lane;
+    key[r] = i < cnt ? kin[i] : 0u;
+    val[r] = i < cnt ? vin[i] : 0u;
+  }
+  __syncthreads();                                  // counters cleared
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const bool ok = base + r * 64 + lane < cnt;
+    const int dig = (int)((key[r] >> shift) & mask);
+    // lanes of this wave holding a pair of the same digit
+    uint64_t peers = __ballot(ok);
+#pragma unroll
+    for (int b = 0; b < kSortMaxBits; ++b) {
+      if (b < dbits) {                              // uniform
+        const bool bit = (dig >> b) & 1;
+        const uint64_t bb = __ballot(bit);
+        peers &= bit ? bb : ~bb;
+      }
+    }
+    const int rank = __popcll(peers & lower);
+    slot[r] = ok ? wrun[w][dig] + rank : -1;      // rank within the digit among the wave's pairs
+    // the group's first lane moves the digit's count on (lanes of one wave
+    // see their own LDS stores in order)
+    if (ok && rank == 0) wrun[w][dig] += __popcll(peers);
+  }
+  __syncthreads();
+  // the digits' starts in the tile: exclusive scan of the tile's counts
+  // (contiguous digits per thread); each wave's run starts after the lower
+  // waves' pairs of the digit
+  {
+    constexpr int per = kSortBuckets / kScanThreads;
+    int32_t v[per], sum = 0;
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+      const int d = t * per + q;
+      v[q] = d < nb ? wrun[0][d] + wrun[1][d] + wrun[2][d] + wrun[3][d] : 0;
+      sum += v[q];
+    }
+    int32_t total;
+    int32_t ex = wg_exclusive_scan<int32_t>(sum, scan_tmp, &total);
+#pragma unroll
+    for (int q = 0; q < per; ++q) {
+      const int d = t * per + q;
+      if (d < nb) {
+        start[d] = ex;
+        obase[d] = offs[(int64_t)d * ntiles + blockIdx.x] - ex;
+      }
+      ex += v[q];
+    }
+  }
+  __syncthreads();
+  {
+    // slot offsets of this wave within each digit's run
+#pragma unroll
+    for (int r = 0; r < kSortRounds; ++r)
+      if (slot[r] >= 0) {
+        const int dig = (int)((key[r] >> shift) & mask);
+        int at = start[dig] + slot[r];
+        for (int w2 = 0; w2 < w; ++w2) at += wrun[w2][dig];
+        lk[at] = key[r];
+        lv[at] = val[r];
+      }
+  }
+  __syncthreads();
+  const int64_t tb = (int64_t)blockIdx.x * kSortTile;
+  const int n_tile = (int)(cnt - tb < kSortTile ? cnt - tb : kSortTile);
+  for (int q = t; q < n_tile; q += kSortThreads) {
+    const uint32_t k = lk[q];
+    const int dig = (int)((k >> shift) & mask);
+    const int64_t pos = (int64_t)obase[dig] + q;
+    kout[pos] = k;
+    vout[pos] = lv[q];
+  }
+}
+
+static int sort_passes(int bits) { return bits <= kSortMaxBits ? 1 : (bits <= 2 * kSortMaxBits ? 2 : 3); }
+
+size_t radix_temp_bytes(int64_t cnt) {
+  const int64_t ntiles = (cnt + kSortTile - 1) / kSortTile;
+  const int64_t nc = ntiles * kSortBuckets;
+  return 2 * ws_bytes<int32_t>((size_t)nc) + scan_temp_bytes<int32_t>(nc);
+}
+
+// Stable sort of (keys, vals) by keys < 2^bits (bits <= 30). Returns in
+// *in_place whether the result is in (keys, vals) (an even number of passes)
+// rather than in (kout, vout); the other pair of buffers is overwritten.
+int radix_sort_pairs(uint32_t *keys, uint32_t *vals, uint32_t *kout, uint32_t *vout, int64_t cnt, int bits,
+                     void *temp, size_t temp_bytes, bool *in_place, hipStream_t s) {
+  *in_place = false;
+  if (cnt <= 0) return LSPCA_OK;
+  if (bits > 3 * kSortMaxBits) {
+    set_error("radix sort: keys of %d bits", bits);
+    return LSPCA_EINVAL;
+  }
+  if (cnt > 0x7fffffffLL || temp_bytes < radix_temp_bytes(cnt)) {
+    set_error("radix sort: %lld pairs or temporary buffer too small", (long long)cnt);
+    return LSPCA_EINVAL;
+  }
+  const int64_t ntiles = (cnt + kSortTile - 1) / kSortTile;
+  const int passes = sort_passes(bits);
+  const int dbits = (bits + passes - 1) / passes;
+  const int64_t nc = ntiles << dbits;
+  const size_t cbytes = ws_bytes<int32_t>((size_t)ntiles * kSortBuckets);
+  int32_t *counts = (int32_t *)temp;
+  int32_t *offs = (int32_t *)((char *)temp + cbytes);
+  char *scan_tmp = (char *)temp + 2 * cbytes;
+  const size_t scan_bytes = temp_bytes - 2 * cbytes;
+  uint32_t *ki = keys, *vi = vals, *ko = kout, *vo = vout;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * dbits;
+    hipLaunchKernelGGL(k_radix_count, (unsigned)ntiles, kSortThreads, 0, s, ki, cnt, shift, dbits, ntiles, counts);
+    LSPCA_HIP(hipGetLastError());
+    LSPCA_TRY(exclusive_scan<int32_t>(counts, offs, nc, scan_tmp, scan_bytes, s));
+    hipLaunchKernelGGL(k_radix_scatter, (unsigned)ntiles, kSortThreads, 0, s, ki, vi, cnt, shift, dbits, ntiles,
+                       offs, ko, vo);
+    LSPCA_HIP(hipGetLastError());
+    std::swap(ki, ko);
+    std::swap(vi, vo);
+  }
+  *in_place = (passes % 2) == 0;
+  return LSPCA_OK;
+}
+
 
 // ---- input check: flag bit 0 rowptr, bit 1 colidx
 __global__ void k_csr_check(const int64_t *__restrict__ rowptr, const int32_t *__restrict__ colidx,
@@ -365,12 +654,7 @@ __global__ __launch_bounds__(256) void k_om_fill(const T *__restrict__ Om, int64
   }
 }
 
-size_t om_scan_bytes(int64_t n) {
-  size_t scan = 0;
-  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (const int32_t *)nullptr, (int32_t *)nullptr,
-                                         (int)(n + 1));
-  return scan;
-}
+size_t om_scan_bytes(int64_t n) { return scan_temp_bytes<int32_t>(n + 1); }
 
 int build_omega_lists(lspca_dtype vdt, const void *Om, int64_t ldo, int64_t n, int k, int32_t *cnt,
                       int32_t *optr, int32_t *oc, void *temp, size_t temp_bytes, hipStream_t s) {
@@ -380,8 +664,7 @@ int build_omega_lists(lspca_dtype vdt, const void *Om, int64_t ldo, int64_t n, i
   else
     hipLaunchKernelGGL(k_om_count<double>, g, 256, 0, s, (const double *)Om, ldo, n, k, cnt);
   LSPCA_HIP(hipGetLastError());
-  size_t tb = temp_bytes;
-  LSPCA_HIP(hipcub::DeviceScan::ExclusiveSum(temp, tb, cnt, optr, (int)(n + 1), s));
+  LSPCA_TRY(exclusive_scan<int32_t>(cnt, optr, n + 1, temp, temp_bytes, s));
   if (vdt == LSPCA_F32)
     hipLaunchKernelGGL(k_om_fill<float>, g, 256, 0, s, (const float *)Om, ldo, n, k, optr, oc);
   else
@@ -583,13 +866,7 @@ CscShape csc_shape(int64_t rows, int64_t n, int64_t cnt, int k, size_t esz) {
 }
 
 size_t csc_temp_bytes(int64_t cnt, int64_t lists) {
-  size_t sort = 0, scan = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, sort, (const int32_t *)nullptr, (int32_t *)nullptr,
-                                           (const uint32_t *)nullptr, (uint32_t *)nullptr, (int)cnt, 0,
-                                           key_bits(lists));
-  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, scan, (const int64_t *)nullptr, (int64_t *)nullptr,
-                                         (int)(lists + 1));
-  return sort > scan ? sort : scan;
+  return std::max(radix_temp_bytes(cnt), scan_temp_bytes<int64_t>(lists + 1));
 }
 
 int build_csc(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, const void *vals, int64_t r0,
@@ -600,9 +877,14 @@ int build_csc(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, con
     hipLaunchKernelGGL(k_csr_expand, (unsigned)((rows + 3) / 4), 256, 0, s, rowptr, colidx, r0, rows, e0, n,
                        sh.rb, b.keys, b.idx, b.rowof);
     LSPCA_HIP(hipGetLastError());
-    size_t tb = b.temp_bytes;
-    LSPCA_HIP(hipcub::DeviceRadixSort::SortPairs(b.temp, tb, b.keys, b.skeys, b.idx, b.sidx, (int)cnt, 0,
-                                                 key_bits(L), s));
+    bool in_place = false;
+    LSPCA_TRY(radix_sort_pairs((uint32_t *)b.keys, b.idx, (uint32_t *)b.skeys, b.sidx, cnt, key_bits(L), b.temp,
+                               b.temp_bytes, &in_place, s));
+    if (in_place) {                               // sorted pairs in (keys, idx): swap the roles
+      std::swap(b.keys, b.skeys);
+      std::swap(b.idx, b.sidx);
+    }
+    b.crow = b.keys;                              // the unsorted keys are dead after the sort
     const unsigned g = (unsigned)((cnt + 255) / 256);
     if (vdt == LSPCA_F32)
       hipLaunchKernelGGL(k_csc_gather<float>, g, 256, 0, s, b.sidx, b.rowof, (const float *)vals, e0, cnt,
@@ -617,12 +899,10 @@ int build_csc(lspca_dtype vdt, const int64_t *rowptr, const int32_t *colidx, con
   LSPCA_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_seg_count, gl, 256, 0, s, b.colptr, L, sh.seg, b.cnt);
   LSPCA_HIP(hipGetLastError());
-  size_t tb = b.temp_bytes;
-  LSPCA_HIP(hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.cnt, b.segoff, (int)(L + 1), s));
+  LSPCA_TRY(exclusive_scan<int64_t>(b.cnt, b.segoff, L + 1, b.temp, b.temp_bytes, s));
   hipLaunchKernelGGL(k_multi_count, gl, 256, 0, s, b.segoff, L, b.cnt);
   LSPCA_HIP(hipGetLastError());
-  tb = b.temp_bytes;
-  LSPCA_HIP(hipcub::DeviceScan::ExclusiveSum(b.temp, tb, b.cnt, b.moff, (int)(L + 1), s));
+  LSPCA_TRY(exclusive_scan<int64_t>(b.cnt, b.moff, L + 1, b.temp, b.temp_bytes, s));
   hipLaunchKernelGGL(k_seg_fill, (unsigned)((L + 255) / 256), 256, 0, s, b.segoff, L, b.segcol);
   LSPCA_HIP(hipGetLastError());
   return LSPCA_OK;
