@@ -18,6 +18,7 @@
 #include "common.h"
 
 #include <cstdlib>
+#include <type_traits>
 
 namespace lspca {
 
@@ -643,6 +644,243 @@ __global__ __launch_bounds__(64 * WR * WC) void k_tn16(const uint16_t *__restric
       }
 }
 
+// ------------------------------------------------------------------ TN16 v2 --
+// F = Y^T X as k_tn16 (split Y, no FP32 sketch), with both operands copied
+// from global memory straight into LDS (global_load_lds, 16 bytes per lane: a
+// wave instruction fills 1 KB of LDS, lane l the bytes 16 l .. 16 l + 15
+// after the instruction's base) through SX LDS stages: no register staging,
+// no LDS stores by the waves, one barrier per K tile. The MFMA fragments of a
+// k step are read into registers while the previous step's products run, and
+// the first step of tile t + 1 is read before the last products of tile t,
+// so the barrier and the LDS latency sit behind matrix-core work. The
+// accumulation order per output element is that of k_tn16 (k steps of 16 in
+// order; high part, then low part), so the two give the same bits.
+// X stays row-major in LDS; its B fragments (8 rows of one X column) come
+// from ds_read_b64_tr_b16: within each 16-lane group, source lane s gives the
+// address of 4 consecutive 16-bit elements and lane 4 a + e receives element
+// e of source lanes a, a + 4, a + 8, a + 12 (checked on gfx950); so source
+// lane s points at row s / 4 of a 4-row block, columns 4 (s % 4) .. + 3, and
+// lane j gets column j's 4 rows. Bank conflicts: 16-byte chunks are swizzled
+// within a row (X: chunk c of row r at position c ^ 4 (r % 4); Y: chunk c of
+// row i at c ^ ((i / rows-per-256-bytes) % chunks-per-row)), so each
+// half-wave's fragment reads cover the 64 banks once; the copies pick the
+// source chunk for the position they fill, so the swizzle costs nothing.
+// Rows past the chunk: the copies read clamped rows, and in the chunk's last
+// tile the k rows at or past its end are zeroed in both fragments.
+#ifndef LSPCA_TN16V2_BK
+#define LSPCA_TN16V2_BK 32
+#endif
+#ifndef LSPCA_TN16V2_STAGES
+#define LSPCA_TN16V2_STAGES 3
+#endif
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_cvoid_t;
+typedef __attribute__((address_space(3))) v4i16 lds_v4i16_t;
+
+// One copy instruction; lds_base is wave-uniform. Written as asm: the
+// compiler's own waits for such copies are a full vmcnt(0) before every LDS
+// read, which would drain the copies in flight; here the kernel waits for
+// exactly the copies it needs (wait_vmcnt) before a barrier. The copy has no
+// destination register, and its address registers are read at issue. One
+// wait state between the M0 write and the copy.
+__device__ __forceinline__ void copy16_to_lds(const void *g, uint32_t lds_base) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds_base)
+               : "memory", "m0");
+}
+__device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(uintptr_t)(lds_void_t *)p; }
+
+// Waits and barrier as asm statements that clobber memory, so that the
+// compiler moves no LDS access across them; the copies into LDS are counted
+// by vmcnt (complete once the data is in LDS).
+template <int N> __device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+template <int DT, int BM, int BN, bool REFINE, int WR, int WC>
+__global__ __launch_bounds__(64 * WR * WC) void k_tn16v2(const uint16_t *__restrict__ Yh,
+                                                const uint16_t *__restrict__ Yl, int64_t ysb, int64_t ysc,
+                                                int64_t ylim, const uint16_t *__restrict__ X, int64_t ldx,
+                                                float *__restrict__ P, int64_t rows, int Mi, int Nj,
+                                                int64_t chunk) {
+  constexpr int NPART = REFINE ? 2 : 1;
+  constexpr int BK = LSPCA_TN16V2_BK, SX = LSPCA_TN16V2_STAGES;
+  constexpr int NW = WR * WC;
+  constexpr int WM = BM / WR, WN = BN / WC, TM = WM / 32, TN = WN / 32;
+  constexpr int KS = BK / 16;                      // MFMA k steps per tile
+  constexpr int CPR = BK / 8;                      // 16-byte chunks per Y row (k runs)
+  constexpr int RPB = 16 / CPR;                    // Y rows per 256 bytes
+  constexpr int CPX = BN / 8;                      // 16-byte chunks per X row
+  constexpr int YBYTES = NPART * BM * BK * 2, XBYTES = BK * BN * 2;
+  constexpr int STAGE = YBYTES + XBYTES;
+  constexpr int YI = YBYTES / 1024, XI = XBYTES / 1024;  // 1 KB copy instructions per stage
+  static_assert(YI % NW == 0 && XI % NW == 0, "copies split evenly over the waves");
+  static_assert(CPX >= 16 && BK % 32 == 0 && BK <= 64 && SX >= 2, "tile shape");
+  constexpr int YIW = YI / NW, XIW = XI / NW, LPW = YIW + XIW;
+  static_assert((SX - 1) * LPW < 64, "copies in flight");
+  __shared__ __align__(16) char lds[SX * STAGE];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = (wave / WC) * WM, wn0 = (wave % WC) * WN;
+  int bx, by, bz;
+  xcd_map(bx, by, bz);
+  const int j0 = bx * BN, i0 = by * BM;
+  const int64_t rbeg = (int64_t)bz * chunk;
+  const int64_t rend = rbeg + chunk < rows ? rbeg + chunk : rows;
+  const int64_t nt = rend > rbeg ? (rend - rbeg + BK - 1) / BK : 0;
+  const uint32_t lds0 = lds_addr(lds);
+
+  // copies of K tile t (rows rbeg + t BK ..) into stage sl
+  auto issue = [&](int sl, int64_t t) {
+    const uint32_t st = lds0 + sl * STAGE;
+    const int64_t r0 = rbeg + t * BK;
+#pragma unroll
+    for (int q = 0; q < YIW; ++q) {
+      const int ins = wave + q * NW;               // which KB of the stage's Y part
+      const int c = ins * 64 + lane;               // chunk index within the Y tiles
+      const int part = c / (BM * CPR), cc = c % (BM * CPR);
+      const int i = cc / CPR, pos = cc % CPR;
+      const int kc = pos ^ ((i / RPB) % CPR);
+      const int ii = i0 + i < Mi ? i0 + i : Mi - 1;
+      const int64_t gr = r0 + 8 * kc;
+      const int64_t rr = gr + 8 <= ylim ? gr : ylim - 8;
+      const uint16_t *src = (part ? Yl : Yh) + (rr >> 3) * ysb + (int64_t)ii * ysc;
+      copy16_to_lds(src, st + ins * 1024);
+    }
+#pragma unroll
+    for (int q = 0; q < XIW; ++q) {
+      const int ins = wave + q * NW;
+      const int c = ins * 64 + lane;
+      const int r = c / CPX, pos = c % CPX;
+      const int cx = pos ^ (4 * (r & 3));
+      const int64_t gr = r0 + r < rows ? r0 + r : rows - 1;
+      const int col = j0 + 8 * cx < Nj ? j0 + 8 * cx : Nj - 8;
+      copy16_to_lds(X + gr * ldx + col, st + YBYTES + ins * 1024);
+    }
+  };
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = {};
+
+  // per-lane parts of the fragment addresses
+  const int arow = lane & 31, akh = lane >> 5;     // A: row in a 32-row block, k half
+  const int g = lane >> 4, s = lane & 15;          // B: 16-lane group, source lane
+  const int brow = 8 * (g >> 1) + (s >> 2);        // B: row within a 16-row k step (+ 4 h)
+  const int bcol = 16 * (g & 1) + 4 * (s & 3);     // B: column within a 32-column block
+  const int bk0 = 8 * (lane >> 5);                 // B: first k row this lane receives (+ 4 h)
+
+  // Fragments of one k step, in two register sets (the step being multiplied
+  // and the next one).
+  u16x8 fa[2][NPART][TM], fb[2][TN];
+  auto load_frag = [&](int set, int sl, int kk) {
+    const char *st = lds + sl * STAGE;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int col = wn0 + j * 32 + bcol;
+      v4i16 h2[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = kk + brow + 4 * h;
+        const int pos = (col >> 3) ^ (4 * (r & 3));
+        h2[h] = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+            (lds_v4i16_t *)(st + YBYTES + r * (2 * BN) + 16 * pos + 2 * (col & 7)));
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        fb[set][j][e] = (uint16_t)h2[0][e];
+        fb[set][j][4 + e] = (uint16_t)h2[1][e];
+      }
+    }
+#pragma unroll
+    for (int part = 0; part < NPART; ++part)
+#pragma unroll
+      for (int i = 0; i < TM; ++i) {
+        const int row = wm0 + i * 32 + arow;
+        const int kc = (kk >> 3) + akh;
+        const int pos = kc ^ ((row / RPB) % CPR);
+        fa[set][part][i] = *(const u16x8 *)(st + part * (BM * BK * 2) + row * (BK * 2) + 16 * pos);
+      }
+  };
+  // The products of one k step. TAIL (the chunk's last tile, first row r0):
+  // the k rows at or past the chunk's end are zeroed in both operands first.
+  auto mma = [&](int set, auto tailc, int kk, int64_t r0) {
+    constexpr bool TAIL = decltype(tailc)::value;
+    if constexpr (TAIL) {
+      const int64_t lim = rend - r0 - kk;           // k rows of this step below lim are kept
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool za = 8 * akh + e >= lim, zb = bk0 + 4 * (e >> 2) + (e & 3) >= lim;
+#pragma unroll
+        for (int part = 0; part < NPART; ++part)
+#pragma unroll
+          for (int i = 0; i < TM; ++i) fa[set][part][i][e] = za ? 0 : fa[set][part][i][e];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) fb[set][j][e] = zb ? 0 : fb[set][j][e];
+      }
+    }
+#pragma unroll
+    for (int part = 0; part < NPART; ++part)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = H16<DT>::mfma(fa[set][part][i], fb[set][j], acc[i][j]);
+  };
+  // one K tile: KS steps; the last step's loads are those of the next tile's
+  // first step, after the wait for that tile and the refill of this stage
+  auto tile = [&](int64_t t, auto tailc) {
+    constexpr bool TAIL = decltype(tailc)::value;
+    const int sl = (int)(t % SX);
+    const int64_t r0 = rbeg + t * BK;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int cur = ks & 1;                       // KS is even: step 0 of each tile in set 0
+      if (ks + 1 < KS) {
+        load_frag(cur ^ 1, sl, 16 * (ks + 1));
+      } else if constexpr (!TAIL) {
+        // tile t read into registers: tile t + 1 must have landed; then
+        // stage sl is free for tile t + SX
+        wait_vmcnt<(SX - 2) * LPW>();
+        lds_barrier();
+        issue(sl, t + SX < nt ? t + SX : nt - 1);
+        load_frag(cur ^ 1, (int)((t + 1) % SX), 0);
+      }
+      mma(cur, tailc, 16 * ks, r0);
+    }
+  };
+
+  if (nt > 0) {
+    // every stage filled first (tiles past the last are copies of the last,
+    // never read: they keep the count of copies per tile uniform)
+#pragma unroll
+    for (int sl = 0; sl < SX; ++sl) issue(sl, sl < nt ? sl : nt - 1);
+    wait_vmcnt<(SX - 1) * LPW>();                  // tile 0 landed (this wave's copies)
+    lds_barrier();                                  // (every wave's)
+    load_frag(0, 0, 0);
+    for (int64_t t = 0; t + 1 < nt; ++t) tile(t, std::false_type{});
+    tile(nt - 1, std::true_type{});
+  }
+  wait_vmcnt<0>();                                  // no copy may land after the workgroup ends
+
+  float *Pz = P + (int64_t)bz * Mi * Nj;
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int r = i0 + wm0 + i * 32 + mrow(lane, v);
+        const int c = j0 + wn0 + j * 32 + (lane & 31);
+        if (r < Mi && c < Nj) Pz[(int64_t)r * Nj + c] = acc[i][j][v];
+      }
+}
+
 // ------------------------------------------------------------- launchers --
 template <int DT, int BM, int BN, bool SPLITB, int OUT, int WR = 2, int WC = 2>
 static int nt16_typed(const uint16_t *A, int64_t lda, const uint16_t *Bh, const uint16_t *Bl,
@@ -866,6 +1104,18 @@ int launch_split16(lspca_dtype dt, const float *Yt, int64_t rows_k, int64_t ld, 
 #define LSPCA_TN16_WAVES 8
 #endif
 
+// The direct-to-LDS form of F = Y^T X (k_tn16v2) for split Y, vector-aligned
+// operands: the default; LSPCA_TN16_DIRECT=0 in the environment selects the
+// register-staged k_tn16 instead (same bits: the same MFMA chain per output
+// element), read per call.
+#ifndef LSPCA_TN16_DIRECT_DEFAULT
+#define LSPCA_TN16_DIRECT_DEFAULT 1
+#endif
+static bool tn16_direct() {
+  const char *e = getenv("LSPCA_TN16_DIRECT");
+  return e && *e ? atoi(e) != 0 : LSPCA_TN16_DIRECT_DEFAULT != 0;
+}
+
 template <int DT, int BM, bool REFINE, bool YF>
 static int tn16_typed(const uint16_t *Yh, const uint16_t *Yl, int64_t ysb, int64_t ysc, int64_t ylim,
                       const uint16_t *X, int64_t ldx, float *P, int64_t rows, int Mi, int Nj, int splits,
@@ -880,6 +1130,14 @@ static int tn16_typed(const uint16_t *Yh, const uint16_t *Yl, int64_t ysb, int64
                        : (uintptr_t)Yh % 16 == 0 && (!REFINE || (uintptr_t)Yl % 16 == 0);
   const bool vec = (ysc % 8 == 0) && (ylim % 8 == 0) && yvec && (ldx % 8 == 0) && ((uintptr_t)X % 16 == 0) &&
                    (Nj % 8 == 0) && Nj >= 8 && ylim >= 8;
+  if constexpr (!YF) {
+    if (vec && tn16_direct()) {
+      hipLaunchKernelGGL((k_tn16v2<DT, BM, BN, REFINE, WR, WC>), grid, dim3(64 * WR * WC), 0, s, Yh, Yl, ysb, ysc,
+                         ylim, X, ldx, P, rows, Mi, Nj, chunk);
+      LSPCA_HIP(hipGetLastError());
+      return LSPCA_OK;
+    }
+  }
   if (vec)
     hipLaunchKernelGGL((k_tn16<DT, BM, BN, REFINE, true, YF, WR, WC>), grid, dim3(64 * WR * WC), 0, s, Yh, Yl, ysb,
                        ysc, ylim, X, ldx, P, rows, Mi, Nj, chunk, Yf, yscale);

@@ -451,6 +451,33 @@ def test_sparse_sketch_fallback_gives_the_same_bits(gpu_lib, monkeypatch, kernel
     assert np.array_equal(F1.cpu().numpy(), F2.cpu().numpy())
 
 
+@pytest.mark.parametrize("dtype,kind,m,n,k,refine", [("bf16", "sparse", 3001, 520, 136, 1),
+                                                     ("bf16", "sparse", 4099, 1024, 256, 0),
+                                                     ("f16", "sparse", 777, 1032, 128, 1),
+                                                     ("f16", "gaussian", 2050, 512, 64, 1),
+                                                     ("bf16", "gaussian", 65, 264, 200, 1),
+                                                     ("bf16", "sparse", 20000, 776, 24, 1)])
+def test_direct_and_staged_F_products_agree_bitwise(gpu_lib, monkeypatch, dtype, kind, m, n, k, refine):
+    """F = Y^T X from operands copied straight into LDS (the default) and from
+    register-staged tiles (LSPCA_TN16_DIRECT=0): the same MFMA chain per
+    element of F, so the same bits, also over ragged row chunks."""
+    import torch
+    Xs, _ = _data(m, n, min(k, 32), dtype)
+    X = to_device(Xs, dtype)
+    out = []
+    for env in ("0", "1"):
+        monkeypatch.setenv("LSPCA_TN16_DIRECT", env)
+        F = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+        G = torch.zeros((k, k), dtype=torch.float64, device="cuda")
+        gpu_lib.accumulate(X, k, kind, 21, F, G, sparse_p=64 if kind == "sparse" else 0, refine=refine)
+        torch.cuda.synchronize()
+        out.append((F.cpu().numpy(), G.cpu().numpy()))
+    monkeypatch.delenv("LSPCA_TN16_DIRECT")
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.all(np.isfinite(out[1][0])) and np.abs(out[1][0]).max() > 0
+
+
 @pytest.mark.parametrize("k,knob", [(40, None), (200, None), (200, "launches")])
 def test_jacobi_sweep_limit_is_reported(gpu_lib, monkeypatch, k, knob):
     """A one-sided Jacobi run that reaches its sweep limit while its last
