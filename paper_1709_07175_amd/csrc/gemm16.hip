@@ -17,6 +17,7 @@
 //          fragment is one 16-byte read.
 #include "common.h"
 
+#include <atomic>
 #include <cstdlib>
 #include <type_traits>
 
@@ -45,6 +46,34 @@ template <> struct H16<LSPCA_F16> {
 };
 
 __device__ inline int mrow(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
+
+// ------------------------------------------------ direct copies into LDS --
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_cvoid_t;
+typedef __attribute__((address_space(3))) v4i16 lds_v4i16_t;
+
+// One copy instruction; lds_base is wave-uniform. Written as asm: the
+// compiler's own waits for such copies are a full vmcnt(0) before every LDS
+// read, which would drain the copies in flight; here the kernel waits for
+// exactly the copies it needs (wait_vmcnt) before a barrier. The copy has no
+// destination register, and its address registers are read at issue. One
+// wait state between the M0 write and the copy.
+__device__ __forceinline__ void copy16_to_lds(const void *g, uint32_t lds_base) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds_base)
+               : "memory", "m0");
+}
+__device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(uintptr_t)(lds_void_t *)p; }
+
+// Waits and barrier as asm statements that clobber memory, so that the
+// compiler moves no LDS access across them; the copies into LDS are counted
+// by vmcnt (complete once the data is in LDS).
+template <int N> __device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 
 // ------------------------------------------------------------------- NT16 --
 // Tile BM x BN x BK, WR x WC waves (2 x 2 unless chosen). VEC: 16-byte global loads (K % 8 == 0,
@@ -93,6 +122,110 @@ enum { OUT_ROWS = 0, OUT_T32 = 1, OUT_TSPLIT = 2 };
 #ifndef LSPCA_NT16_PROJ_WAVES
 #define LSPCA_NT16_PROJ_WAVES 8
 #endif
+
+// Stores one BM x BN tile of accumulators at (m0, n0) in the output mode
+// OUT; red: WR x BN floats of LDS for the column maxima (OUT_T32). LDSSYNC:
+// barriers that wait for LDS operations only (copies into LDS may stay in
+// flight), else __syncthreads.
+template <bool LDSSYNC> __device__ __forceinline__ void nt16_sync() {
+  if constexpr (LDSSYNC) lds_barrier();
+  else __syncthreads();
+}
+
+template <int DT, int BM, int BN, int OUT, int WR, int WC, bool LDSSYNC, int TM = BM / WR / 32, int TN = BN / WC / 32>
+__device__ __forceinline__ void nt16_epilogue(const f32x16 (&acc)[TM][TN], float *__restrict__ C, int64_t ldc,
+                                              int64_t M, int N, unsigned *__restrict__ colmax,
+                                              uint16_t *__restrict__ Ch, uint16_t *__restrict__ Cl,
+                                              const int64_t m0, const int n0, float *red) {
+  constexpr int NT = 64 * WR * WC;
+  constexpr int WM = BM / WR, WN = BN / WC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm0 = (wave / WC) * WM, wn0 = (wave % WC) * WN;
+  float cm[TN];
+#pragma unroll
+  for (int j = 0; j < TN; ++j) {
+    const int c = n0 + wn0 + j * 32 + (lane & 31);
+    float cmax = 0.f;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      if constexpr (OUT != OUT_ROWS) {
+        // elements v = 4q .. 4q+3 of a lane are 4 consecutive rows
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int64_t r = m0 + wm0 + i * 32 + mrow(lane, 4 * q);
+          const f32x4 w = {acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
+                           acc[i][j][4 * q + 3]};
+          if (c < N) {
+            const bool full = r + 3 < M && (ldc & 3) == 0;
+            if constexpr (OUT == OUT_T32) {
+              if (full) {
+                *(f32x4 *)(C + (int64_t)c * ldc + r) = w;
+              } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                  if (r + e < M) C[(int64_t)c * ldc + r + e] = w[e];
+              }
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                if (r + e < M) cmax = fmaxf(cmax, fabsf(w[e]));
+            } else {
+              u16x4 hv, lv;
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                hv[e] = H16<DT>::from_f32(w[e]);
+                lv[e] = H16<DT>::from_f32(w[e] - H16<DT>::to_f32(hv[e]));
+              }
+              if (full) {
+                *(u16x4 *)(Ch + (int64_t)c * ldc + r) = hv;
+                if (Cl) *(u16x4 *)(Cl + (int64_t)c * ldc + r) = lv;
+              } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                  if (r + e < M) {
+                    Ch[(int64_t)c * ldc + r + e] = hv[e];
+                    if (Cl) Cl[(int64_t)c * ldc + r + e] = lv[e];
+                  }
+              }
+            }
+          }
+        }
+      } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t r = m0 + wm0 + i * 32 + mrow(lane, v);
+          if (r < M && c < N) C[r * ldc + c] = acc[i][j][v];
+        }
+      }
+    }
+    if constexpr (OUT == OUT_T32) cm[j] = cmax;
+  }
+  if constexpr (OUT == OUT_T32) {
+    // this tile's column maxima: lanes l and l + 32 hold one column, the two
+    // waves of a column half meet in LDS; one plain store per column into
+    // the partial row of this row tile (no atomics)
+    if (colmax) {
+      nt16_sync<LDSSYNC>();
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const float mj = fmaxf(cm[j], __shfl_xor(cm[j], 32));
+        if (lane < 32) red[(wave / WC) * BN + wn0 + j * 32 + lane] = mj;
+      }
+      nt16_sync<LDSSYNC>();
+      // one row per 128 rows of A (nt16_row_tiles), the same maximum in each
+      // row this tile covers
+      for (int t = tid; t < BN; t += NT)
+        if (n0 + t < N) {
+          float m = red[t];
+#pragma unroll
+          for (int w = 1; w < WR; ++w) m = fmaxf(m, red[w * BN + t]);
+          const unsigned mv = __float_as_uint(m);
+#pragma unroll
+          for (int h = 0; h < BM / 128; ++h)
+            if (m0 + 128 * h < M) colmax[(m0 / 128 + h) * (int64_t)N + n0 + t] = mv;
+        }
+    }
+  }
+}
 
 // One BM x BN tile of C at (m0, n0); the LDS it stages through is free
 // again on return, so a workgroup may call it for several tiles in turn.
@@ -245,91 +378,8 @@ __device__ __forceinline__ void nt16_tile(const uint16_t *__restrict__ A, int64_
     __syncthreads();
   }
 
-  float cm[TN];
-#pragma unroll
-  for (int j = 0; j < TN; ++j) {
-    const int c = n0 + wn0 + j * 32 + (lane & 31);
-    float cmax = 0.f;
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-      if constexpr (OUT != OUT_ROWS) {
-        // elements v = 4q .. 4q+3 of a lane are 4 consecutive rows
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int64_t r = m0 + wm0 + i * 32 + mrow(lane, 4 * q);
-          const f32x4 w = {acc[i][j][4 * q], acc[i][j][4 * q + 1], acc[i][j][4 * q + 2],
-                           acc[i][j][4 * q + 3]};
-          if (c < N) {
-            const bool full = r + 3 < M && (ldc & 3) == 0;
-            if constexpr (OUT == OUT_T32) {
-              if (full) {
-                *(f32x4 *)(C + (int64_t)c * ldc + r) = w;
-              } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                  if (r + e < M) C[(int64_t)c * ldc + r + e] = w[e];
-              }
-#pragma unroll
-              for (int e = 0; e < 4; ++e)
-                if (r + e < M) cmax = fmaxf(cmax, fabsf(w[e]));
-            } else {
-              u16x4 hv, lv;
-#pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                hv[e] = H16<DT>::from_f32(w[e]);
-                lv[e] = H16<DT>::from_f32(w[e] - H16<DT>::to_f32(hv[e]));
-              }
-              if (full) {
-                *(u16x4 *)(Ch + (int64_t)c * ldc + r) = hv;
-                if (Cl) *(u16x4 *)(Cl + (int64_t)c * ldc + r) = lv;
-              } else {
-#pragma unroll
-                for (int e = 0; e < 4; ++e)
-                  if (r + e < M) {
-                    Ch[(int64_t)c * ldc + r + e] = hv[e];
-                    if (Cl) Cl[(int64_t)c * ldc + r + e] = lv[e];
-                  }
-              }
-            }
-          }
-        }
-      } else {
-#pragma unroll
-        for (int v = 0; v < 16; ++v) {
-          const int64_t r = m0 + wm0 + i * 32 + mrow(lane, v);
-          if (r < M && c < N) C[r * ldc + c] = acc[i][j][v];
-        }
-      }
-    }
-    if constexpr (OUT == OUT_T32) cm[j] = cmax;
-  }
-  if constexpr (OUT == OUT_T32) {
-    // this tile's column maxima: lanes l and l + 32 hold one column, the two
-    // waves of a column half meet in LDS; one plain store per column into
-    // the partial row of this row tile (no atomics)
-    if (colmax) {
-      float *red = reinterpret_cast<float *>(&As[0][0]);   // WR x BN floats
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        const float mj = fmaxf(cm[j], __shfl_xor(cm[j], 32));
-        if (lane < 32) red[(wave / WC) * BN + wn0 + j * 32 + lane] = mj;
-      }
-      __syncthreads();
-      // one row per 128 rows of A (nt16_row_tiles), the same maximum in each
-      // row this tile covers
-      for (int t = tid; t < BN; t += NT)
-        if (n0 + t < N) {
-          float m = red[t];
-#pragma unroll
-          for (int w = 1; w < WR; ++w) m = fmaxf(m, red[w * BN + t]);
-          const unsigned mv = __float_as_uint(m);
-#pragma unroll
-          for (int h = 0; h < BM / 128; ++h)
-            if (m0 + 128 * h < M) colmax[(m0 / 128 + h) * (int64_t)N + n0 + t] = mv;
-        }
-    }
-  }
+  nt16_epilogue<DT, BM, BN, OUT, WR, WC, false>(acc, C, ldc, M, N, colmax, Ch, Cl, m0, n0,
+                                              reinterpret_cast<float *>(&As[0][0]));
 }
 
 template <int DT, int BM, int BN, bool SPLITB, bool VEC, int OUT, int WR = 2, int WC = 2>
@@ -644,6 +694,166 @@ __global__ __launch_bounds__(64 * WR * WC) void k_tn16(const uint16_t *__restric
       }
 }
 
+// ------------------------------------------------------------------ NT16 v2 --
+// C = A (B_hi + B_lo)^T as k_nt16, for large M: persistent workgroups, each
+// taking row tiles blockIdx.x, + gridDim.x, ... of one column tile, the K
+// tiles of all its row tiles forming one stream through SX LDS stages. Both
+// operands are copied from global memory straight into LDS (global_load_lds),
+// one barrier per K tile; the MFMA fragments of a k step are read into
+// registers while the previous step's products run, and the first step of
+// the next K tile (of this or the next row tile) before the last products of
+// this one. The accumulation order per element of C is that of nt16_tile
+// (k steps of 16 in order; B_hi, then B_lo), so the two give the same bits.
+// A and B rows are K-contiguous in LDS, BK / 8 chunks of 16 bytes per row,
+// chunk c of row i at position c ^ ((i / rows-per-256-bytes) % chunks-per-
+// row): the 16-byte fragment reads of 16 consecutive rows cover the 64 banks
+// once. Needs 16-byte aligned rows, lda, ldb multiples of 8 and K a multiple
+// of BK; rows past M and columns past N read clamped rows and are not stored.
+template <int DT, int BM, int BN, bool SPLITB, int OUT, int WR, int WC, int BK, int SX>
+__global__ __launch_bounds__(64 * WR * WC) void k_nt16v2(const uint16_t *__restrict__ A, int64_t lda,
+                                                const uint16_t *__restrict__ Bh,
+                                                const uint16_t *__restrict__ Bl, int64_t ldb,
+                                                float *__restrict__ C, int64_t ldc, int64_t M, int N, int K,
+                                                unsigned *__restrict__ colmax, uint16_t *__restrict__ Ch,
+                                                uint16_t *__restrict__ Cl) {
+  constexpr int NB = SPLITB ? 2 : 1;
+  constexpr int NW = WR * WC;
+  constexpr int WM = BM / WR, WN = BN / WC, TM = WM / 32, TN = WN / 32;
+  constexpr int KS = BK / 16;                      // MFMA k steps per K tile
+  constexpr int CPR = BK / 8;                      // 16-byte chunks per row
+  constexpr int RPB = 16 / CPR;                    // rows per 256 bytes
+  constexpr int ABYTES = BM * BK * 2, BBYTES = NB * BN * BK * 2;
+  constexpr int STAGE = ABYTES + BBYTES;
+  constexpr int AI = ABYTES / 1024, BI = BBYTES / 1024;   // 1 KB copy instructions per stage
+  static_assert(AI % NW == 0 && BI % NW == 0, "copies split evenly over the waves");
+  static_assert(KS % 2 == 0 && CPR <= 16, "tile shape");
+  constexpr int AIW = AI / NW, BIW = BI / NW, LPW = AIW + BIW;
+  static_assert((SX - 1) * LPW < 64 && SX >= 2, "copies in flight");
+  __shared__ __align__(16) char lds[SX * STAGE];
+  __shared__ float red[OUT == OUT_T32 ? WR * BN : 1];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = (wave / WC) * WM, wn0 = (wave % WC) * WN;
+  const int n0 = blockIdx.y * BN;
+  const int64_t ntiles = (M + BM - 1) / BM;
+  const int64_t G = gridDim.x;
+  if ((int64_t)blockIdx.x >= ntiles) return;
+  const int64_t T = (ntiles - blockIdx.x + G - 1) / G;    // row tiles of this workgroup
+  const int nk = K / BK;
+  const int64_t S = T * nk;                                // K tiles of this workgroup
+  const uint32_t lds0 = lds_addr(lds);
+  const int64_t mlast = M - 1;
+  const int nlast = N - 1;
+
+  // copy cursor: the next K tile to copy (row tile crt, K tile ckt); it stops
+  // at the last one, so the copies past the end repeat it (never read; the
+  // count of copies per K tile stays uniform)
+  int64_t cs = 0, crt = blockIdx.x;
+  int ckt = 0;
+  auto issue = [&](int sl) {
+    const uint32_t st = lds0 + sl * STAGE;
+    const int64_t m0 = crt * BM;
+    const int k0 = ckt * BK;
+#pragma unroll
+    for (int q = 0; q < AIW; ++q) {
+      const int ins = wave + q * NW;
+      const int c = ins * 64 + lane;
+      const int i = c / CPR, pos = c % CPR;
+      const int kc = pos ^ ((i / RPB) % CPR);
+      const int64_t gr = m0 + i < M ? m0 + i : mlast;
+      copy16_to_lds(A + gr * lda + k0 + 8 * kc, st + ins * 1024);
+    }
+#pragma unroll
+    for (int q = 0; q < BIW; ++q) {
+      const int ins = wave + q * NW;
+      const int c = ins * 64 + lane;
+      const int part = c / (BN * CPR), cc = c % (BN * CPR);
+      const int n = cc / CPR, pos = cc % CPR;
+      const int kc = pos ^ ((n / RPB) % CPR);
+      const int gn = n0 + n < N ? n0 + n : nlast;
+      copy16_to_lds((part ? Bl : Bh) + (int64_t)gn * ldb + k0 + 8 * kc, st + ABYTES + ins * 1024);
+    }
+    if (cs + 1 < S) {
+      ++cs;
+      if (++ckt == nk) {
+        ckt = 0;
+        crt += G;
+      }
+    }
+  };
+
+  f32x16 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = {};
+
+  const int frow = lane & 31, fkh = lane >> 5;
+  u16x8 fa[2][TM], fb[2][NB][TN];
+  auto load_frag = [&](int set, int sl, int kk) {
+    const char *st = lds + sl * STAGE;
+    const int kc = (kk >> 3) + fkh;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int row = wm0 + i * 32 + frow;
+      fa[set][i] = *(const u16x8 *)(st + row * (BK * 2) + 16 * (kc ^ ((row / RPB) % CPR)));
+    }
+#pragma unroll
+    for (int part = 0; part < NB; ++part)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        const int n = wn0 + j * 32 + frow;
+        fb[set][part][j] =
+            *(const u16x8 *)(st + ABYTES + part * (BN * BK * 2) + n * (BK * 2) + 16 * (kc ^ ((n / RPB) % CPR)));
+      }
+  };
+  auto mma = [&](int set) {
+#pragma unroll
+    for (int part = 0; part < NB; ++part)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = H16<DT>::mfma(fa[set][i], fb[set][part][j], acc[i][j]);
+  };
+
+#pragma unroll
+  for (int sl = 0; sl < SX; ++sl) issue(sl);
+  wait_vmcnt<(SX - 1) * LPW>();                    // K tile 0 landed (this wave's copies)
+  lds_barrier();                                    // (every wave's)
+  load_frag(0, 0, 0);
+  int64_t rt = blockIdx.x;                          // row tile being multiplied
+  int kt = 0;
+  for (int64_t s = 0; s < S; ++s) {
+    const int sl = (int)(s % SX);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int cur = ks & 1;                       // KS is even: step 0 of each K tile in set 0
+      if (ks + 1 < KS) {
+        load_frag(cur ^ 1, sl, 16 * (ks + 1));
+      } else if (s + 1 < S) {
+        // K tile s read into registers: tile s + 1 must have landed; then
+        // stage sl is free for tile s + SX
+        wait_vmcnt<(SX - 2) * LPW>();
+        lds_barrier();
+        issue(sl);
+        load_frag(cur ^ 1, (int)((s + 1) % SX), 0);
+      }
+      mma(cur);
+    }
+    if (++kt == nk) {
+      nt16_epilogue<DT, BM, BN, OUT, WR, WC, true>(acc, C, ldc, M, N, colmax, Ch, Cl, rt * BM, n0, red);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = {};
+      kt = 0;
+      rt += G;
+    }
+  }
+  wait_vmcnt<0>();                                  // no copy may land after the workgroup ends
+}
+
 // ------------------------------------------------------------------ TN16 v2 --
 // F = Y^T X as k_tn16 (split Y, no FP32 sketch), with both operands copied
 // from global memory straight into LDS (global_load_lds, 16 bytes per lane: a
@@ -673,32 +883,6 @@ __global__ __launch_bounds__(64 * WR * WC) void k_tn16(const uint16_t *__restric
 #ifndef LSPCA_TN16V2_STAGES
 #define LSPCA_TN16V2_STAGES 3
 #endif
-
-typedef short v4i16 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(3))) void lds_void_t;
-typedef __attribute__((address_space(1))) const void gbl_cvoid_t;
-typedef __attribute__((address_space(3))) v4i16 lds_v4i16_t;
-
-// One copy instruction; lds_base is wave-uniform. Written as asm: the
-// compiler's own waits for such copies are a full vmcnt(0) before every LDS
-// read, which would drain the copies in flight; here the kernel waits for
-// exactly the copies it needs (wait_vmcnt) before a barrier. The copy has no
-// destination register, and its address registers are read at issue. One
-// wait state between the M0 write and the copy.
-__device__ __forceinline__ void copy16_to_lds(const void *g, uint32_t lds_base) {
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds_base)
-               : "memory", "m0");
-}
-__device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(uintptr_t)(lds_void_t *)p; }
-
-// Waits and barrier as asm statements that clobber memory, so that the
-// compiler moves no LDS access across them; the copies into LDS are counted
-// by vmcnt (complete once the data is in LDS).
-template <int N> __device__ __forceinline__ void wait_vmcnt() {
-  static_assert(N >= 0 && N < 64, "vmcnt");
-  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
-}
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 template <int DT, int BM, int BN, bool REFINE, int WR, int WC>
 __global__ __launch_bounds__(64 * WR * WC) void k_tn16v2(const uint16_t *__restrict__ Yh,
@@ -882,6 +1066,53 @@ __global__ __launch_bounds__(64 * WR * WC) void k_tn16v2(const uint16_t *__restr
 }
 
 // ------------------------------------------------------------- launchers --
+// The direct-to-LDS form of the NT16 sketch (k_nt16v2) for the large tiles:
+// the default; LSPCA_NT16_DIRECT=0 in the environment selects the
+// register-staged k_nt16 instead (same bits), read per call.
+#ifndef LSPCA_NT16_DIRECT_DEFAULT
+#define LSPCA_NT16_DIRECT_DEFAULT 1
+#endif
+static bool nt16_direct() {
+  const char *e = getenv("LSPCA_NT16_DIRECT");
+  return e && *e ? atoi(e) != 0 : LSPCA_NT16_DIRECT_DEFAULT != 0;
+}
+
+// K depth and LDS stages of k_nt16v2 for a tile: 64-deep K tiles where three
+// stages fit in 144 KB, else 32-deep; up to four stages.
+template <int BM, int BN, bool SPLITB> struct Nt16v2Shape {
+  static constexpr int NB = SPLITB ? 2 : 1;
+  static constexpr int BK = 3 * (BM + NB * BN) * 64 * 2 <= 147456 ? 64 : 32;
+  static constexpr int STAGE = (BM + NB * BN) * BK * 2;
+  static constexpr int SX = 147456 / STAGE > 4 ? 4 : 147456 / STAGE;
+};
+
+template <int DT, int BM, int BN, bool SPLITB, int OUT, int WR, int WC>
+static int nt16_direct_launch(const uint16_t *A, int64_t lda, const uint16_t *Bh, const uint16_t *Bl,
+                              int64_t ldb, float *C, int64_t ldc, int64_t M, int N, int K, unsigned *colmax,
+                              uint16_t *Ch, uint16_t *Cl, hipStream_t s) {
+  using Sh = Nt16v2Shape<BM, BN, SPLITB>;
+  auto kern = k_nt16v2<DT, BM, BN, SPLITB, OUT, WR, WC, Sh::BK, Sh::SX>;
+  static std::atomic<int> per_cu[64];              // resident workgroups per CU, by device
+  int dev = 0;
+  LSPCA_HIP(hipGetDevice(&dev));
+  int per = dev < 64 ? per_cu[dev].load(std::memory_order_relaxed) : 0;
+  if (per <= 0) {
+    int cus = 0, occ = 0;
+    LSPCA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    LSPCA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * WR * WC, 0));
+    per = cus * (occ > 0 ? occ : 1);
+    if (dev < 64) per_cu[dev].store(per, std::memory_order_relaxed);
+  }
+  const int64_t ntiles = (M + BM - 1) / BM;
+  const int gy = (N + BN - 1) / BN;
+  int64_t gx = (per + gy - 1) / gy;
+  gx = gx < ntiles ? gx : ntiles;
+  hipLaunchKernelGGL(kern, dim3((unsigned)gx, (unsigned)gy), dim3(64 * WR * WC), 0, s, A, lda, Bh, Bl, ldb, C,
+                     ldc, M, N, K, colmax, Ch, Cl);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
 template <int DT, int BM, int BN, bool SPLITB, int OUT, int WR = 2, int WC = 2>
 static int nt16_typed(const uint16_t *A, int64_t lda, const uint16_t *Bh, const uint16_t *Bl,
                       int64_t ldb, float *C, int64_t ldc, int64_t M, int N, int K,
@@ -889,6 +1120,14 @@ static int nt16_typed(const uint16_t *A, int64_t lda, const uint16_t *Bh, const 
   dim3 grid((unsigned)((M + BM - 1) / BM), (unsigned)((N + BN - 1) / BN));
   const bool vec = (lda % 8 == 0) && (ldb % 8 == 0) && (K % 8 == 0) && ((uintptr_t)A % 16 == 0) &&
                    ((uintptr_t)Bh % 16 == 0) && (!SPLITB || (uintptr_t)Bl % 16 == 0);
+  // the direct form for the sketch (one B part); the projection with split
+  // B measured slower in it (5% with the 128-wide B tile, and the 256 x 256
+  // tile needs more registers than eight waves have)
+  if constexpr (BM >= 128 && !SPLITB) {
+    if (vec && K >= Nt16v2Shape<BM, BN, SPLITB>::BK && K % Nt16v2Shape<BM, BN, SPLITB>::BK == 0 && nt16_direct())
+      return nt16_direct_launch<DT, BM, BN, SPLITB, OUT, WR, WC>(A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax,
+                                                                 Ch, Cl, s);
+  }
   if (vec)
     hipLaunchKernelGGL((k_nt16<DT, BM, BN, SPLITB, true, OUT, WR, WC>), grid, dim3(64 * WR * WC), 0, s, A, lda, Bh, Bl, ldb, C, ldc, M, N, K, colmax, Ch, Cl);
   else

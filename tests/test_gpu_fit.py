@@ -478,6 +478,31 @@ def test_direct_and_staged_F_products_agree_bitwise(gpu_lib, monkeypatch, dtype,
     assert np.all(np.isfinite(out[1][0])) and np.abs(out[1][0]).max() > 0
 
 
+@pytest.mark.parametrize("dtype,m,n,k", [("f16", 3001, 512, 64), ("bf16", 4099, 1024, 128),
+                                         ("bf16", 2050, 2048, 256), ("f16", 777, 512, 100),
+                                         ("f16", 20000, 2048, 128), ("bf16", 300, 64, 8)])
+def test_direct_and_staged_sketch_agree_bitwise(gpu_lib, monkeypatch, dtype, m, n, k):
+    """The dense 16-bit sketch Y = X Omega by persistent workgroups with
+    operands copied straight into LDS (the default) and by register-staged
+    tiles (LSPCA_NT16_DIRECT=0): the same MFMA chain per element of Y, so F
+    and G agree bit for bit (FP16: also the column scales from max |Y|)."""
+    import torch
+    Xs, _ = _data(m, n, min(k, 32), dtype)
+    X = to_device(Xs, dtype)
+    out = []
+    for env in ("0", "1"):
+        monkeypatch.setenv("LSPCA_NT16_DIRECT", env)
+        F = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+        G = torch.zeros((k, k), dtype=torch.float64, device="cuda")
+        gpu_lib.accumulate(X, k, "gaussian", 23, F, G, refine=1)
+        torch.cuda.synchronize()
+        out.append((F.cpu().numpy(), G.cpu().numpy()))
+    monkeypatch.delenv("LSPCA_NT16_DIRECT")
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.all(np.isfinite(out[1][0])) and np.abs(out[1][0]).max() > 0
+
+
 @pytest.mark.parametrize("k,knob", [(40, None), (200, None), (200, "launches")])
 def test_jacobi_sweep_limit_is_reported(gpu_lib, monkeypatch, k, knob):
     """A one-sided Jacobi run that reaches its sweep limit while its last
