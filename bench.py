@@ -48,8 +48,8 @@ MEASURED_TRAFFIC = {
     },
     ("f16", 4_600_000, 2048, 128, "gaussian"): {
         "sources": ["paper_1709_07175_amd/csrc/gemm16.hip", "paper_1709_07175_amd/csrc/common.h"],
-        "sha256": "413b58179c32dface25e64ab7fb86e54737938f41e05ae471e63760d7107c535",
-        "bytes": 2.2025e+10,
+        "sha256": "9d8ccf6b4cd057256f41a211ef7c1a84d2f7ad1366d47bc846e5f68852628dd7",
+        "bytes": 2.1742e+10,
     },
     ("csr", 131_072, 98_450, 500, "sparse"): {   # k_csc_block, per row-block launch
         "sources": ["paper_1709_07175_amd/csrc/csr.hip", "paper_1709_07175_amd/csrc/common.h"],
@@ -90,7 +90,8 @@ def roofline(cfg, m, n, k, xbytes, esz, sketch_ms):
                 "traffic": measured_traffic(cfg, m),
                 "algorithmic": f"2 m n k = {flops:.4g} flop per launch", "algorithmic_bytes": alg_bytes}
     achieved = alg_bytes / (sketch_ms * 1e-3) / 1e9
-    name = "k_sparse_sketch (gather-adds)" if cfg["kind"] == "sparse" else "k_nt16 (sketch Y = X Omega)"
+    name = ("k_sparse_sketch (gather-adds)" if cfg["kind"] == "sparse"
+            else "k_nt16v2 (sketch Y = X Omega; persistent, operands copied straight into LDS)")
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 3), "peak": PEAKS["hbm_GBs"],
             "unit": "GB/s", "frac": round(achieved / PEAKS["hbm_GBs"], 4),
             "traffic": measured_traffic(cfg, m),
@@ -117,7 +118,13 @@ def pass_rooflines(cfg, m, n, k, xbytes, esz, phases):
     ybytes = m * k * (8 if dt == "f64" else 4)   # Y (FP64, FP32, or the two 16-bit parts)
     f_bytes = xbytes + ybytes
     tf = flops / (f_ms * 1e-3) / 1e12
-    res["F"] = {"kernel": "k_tn16 (F = Y_hi^T X + Y_lo^T X)" if h16 else "k_tn (F = Y^T X)",
+    if not h16:
+        fname = "k_tn (F = Y^T X)"
+    elif dt == "f16" and cfg["kind"] == "gaussian":
+        fname = "k_tn16 (F = Y_hi^T X + Y_lo^T X, Y split from the FP32 sketch as loaded)"
+    else:
+        fname = "k_tn16v2 (F = Y_hi^T X + Y_lo^T X, operands copied straight into LDS)"
+    res["F"] = {"kernel": fname,
                 "ms": round(f_ms, 4), "flop": flops, "TFLOPs": round(tf, 2),
                 "mfma_peak_TFs": mfma_peak, "mfma_frac": round(tf / mfma_peak, 4),
                 "hbm_bytes_algorithmic": f_bytes,
