@@ -302,7 +302,7 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
     const int sf = tn_pick_splits(rows, k, (int)n);
     if (!pl.h16) {
       // Y_s = X_s Omega (Algorithm 4 step 2a)
-      LSPCA_TRY(launch_nt(xdt, Xs, ldx, OmT, n, Y, k, rows, k, (int)n, s));
+      LSPCA_TRY(launch_nt_sketch(xdt, Xs, ldx, OmT, n, Y, k, rows, k, (int)n, s));
       tm.mark(PH_SKETCH);
       if (hook) LSPCA_TRY((*hook)(Y, rows, k, false));
       // F += Y_s^T X_s (step 2b); G += Y_s^T Y_s

@@ -43,6 +43,37 @@ __device__ inline float f16_bits_to_f32(uint16_t b) {
   return (float)__builtin_bit_cast(_Float16, b);
 }
 
+// ------------------------------------------------ direct copies into LDS --
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) const void gbl_cvoid_t;
+
+// One copy instruction; lds_base is wave-uniform. Written as asm: the
+// compiler's own waits for such copies are a full vmcnt(0) before every LDS
+// read, which would drain the copies in flight; here the kernel waits for
+// exactly the copies it needs (wait_vmcnt) before a barrier. The copy has no
+// destination register, and its address registers are read at issue. One
+// wait state between the M0 write and the copy. M0 is a reserved register
+// (hence the silenced warning): in the kernels that use these copies no
+// other instruction reads or writes M0 (checked in their assembly), so
+// nothing the compiler keeps in it is lost.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+__device__ __forceinline__ void copy16_to_lds(const void *g, uint32_t lds_base) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds_base)
+               : "memory", "m0");
+}
+#pragma clang diagnostic pop
+__device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(uintptr_t)(lds_void_t *)p; }
+
+// Waits and barrier as asm statements that clobber memory, so that the
+// compiler moves no LDS access across them; the copies into LDS are counted
+// by vmcnt (complete once the data is in LDS).
+template <int N> __device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 // ------------------------------------------------------- XCD-aware grid ----
 // MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
 // with its own L2. For a split-over-rows product launched as a 3-D grid
@@ -152,6 +183,10 @@ int launch_omega(int64_t n, int k, int kind, uint64_t seed, uint32_t p,
 int launch_nt(lspca_dtype dt, const void *A, int64_t lda, const void *B,
               int64_t ldb, void *C, int64_t ldc, int64_t M, int N, int K,
               hipStream_t s, double alpha = 1.0, double beta = 0.0);
+// The sketch product of a stripe (C = A B^T, A the stripe's rows): the
+// streamed FP32 kernel where it applies, else launch_nt.
+int launch_nt_sketch(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                     int64_t ldc, int64_t M, int N, int K, hipStream_t s);
 int launch_tn(lspca_dtype dt, const void *A, int64_t lda, const void *B,
               int64_t ldb, void *P, int64_t M_rows, int Mi, int Nj, int splits,
               hipStream_t s, int64_t ldp = 0, double alpha = 1.0, double beta = 0.0);

@@ -15,6 +15,9 @@
 // (FP64) on fragments read from LDS. 256 threads = 4 waves of 64 lanes.
 #include "common.h"
 
+#include <atomic>
+#include <cstdlib>
+
 // K depth and register prefetch stages of the FP32 NT product tiles.
 #ifndef LSPCA_NT32_BK
 #define LSPCA_NT32_BK 32
@@ -239,6 +242,215 @@ __global__ __launch_bounds__(256) void k_nt(const T *__restrict__ A, int64_t lda
     tm = f;
   }
   nt_tile<T, BM, BN, BK, WGM, WGN, VEC, R>(A, lda, B, ldb, C, ldc, M, N, K, alpha, beta, tm * BM, (int)tn * BN);
+}
+
+// ------------------------------------------------------------ NT32 stream --
+// C = A B^T in FP32 for the sketch Y = X Omega of a large stripe: persistent
+// workgroups (one per CU) walk row tiles blockIdx.x, + gridDim.x, ...; the K
+// tiles of all their row tiles form one stream through SX LDS stages filled
+// by copies straight from global memory (global_load_lds, 16 bytes per lane,
+// one barrier per K tile, no register staging). Rows of both tiles are
+// K-contiguous in LDS, 16-byte chunk c of row r at position c ^ ((r / RPB) %
+// CPR) (RPB rows per 256 bytes, CPR chunks per row), so the 16-byte
+// fragment reads of 16 consecutive rows cover the 64 banks once. A lane reads
+// 4 consecutive k of its row at once and feeds them to 4 successive
+// v_mfma_f32_16x16x4f32 (element e of every lane's 4-vector in the e-th):
+// the e-th instruction sums k = kk + 4 g + e over the 16-lane groups g, and
+// the four together all 16 k of the step, with A and B under the same map.
+// Fragments of the next k step are read while the current one's products
+// run, and the next K tile's first step before the current tile's last
+// products. Needs 16-byte aligned rows, lda, ldb multiples of 4 and K a
+// multiple of BK; rows past M and N read clamped rows and are not stored.
+template <int BM, int BN, int WR, int WC, int BK, int SX>
+__global__ __launch_bounds__(64 * WR * WC) void k_nt32s(const float *__restrict__ A, int64_t lda,
+                                               const float *__restrict__ B, int64_t ldb,
+                                               float *__restrict__ C, int64_t ldc, int64_t M, int N,
+                                               int K) {
+  constexpr int NW = WR * WC;
+  constexpr int WM = BM / WR, WN = BN / WC, TM = WM / 16, TN = WN / 16;
+  constexpr int KS = BK / 16;                      // k steps of 16 per K tile
+  constexpr int CPR = BK / 4;                      // 16-byte chunks per row
+  constexpr int RPB = 256 / (BK * 4);              // rows per 256 bytes
+  constexpr int ABYTES = BM * BK * 4, BBYTES = BN * BK * 4;
+  constexpr int STAGE = ABYTES + BBYTES;
+  constexpr int AI = ABYTES / 1024, BI = BBYTES / 1024;
+  static_assert(AI % NW == 0 && BI % NW == 0, "copies split evenly over the waves");
+  static_assert(KS % 2 == 0 && RPB >= 1 && CPR <= 16, "tile shape");
+  constexpr int AIW = AI / NW, BIW = BI / NW, LPW = AIW + BIW;
+  static_assert((SX - 1) * LPW < 64 && SX >= 2, "copies in flight");
+  __shared__ __align__(16) char lds[SX * STAGE];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = (wave / WC) * WM, wn0 = (wave % WC) * WN;
+  const int n0 = blockIdx.y * BN;
+  const int64_t ntiles = (M + BM - 1) / BM;
+  const int64_t G = gridDim.x;
+  if ((int64_t)blockIdx.x >= ntiles) return;
+  const int64_t T = (ntiles - blockIdx.x + G - 1) / G;
+  const int nk = K / BK;
+  const int64_t S = T * nk;
+  const uint32_t lds0 = lds_addr(lds);
+  const int64_t mlast = M - 1;
+  const int nlast = N - 1;
+
+  // copy cursor (row tile crt, K tile ckt); stops at the last K tile, so the
+  // copies past the end repeat it (never read; uniform count per K tile)
+  int64_t cs = 0, crt = blockIdx.x;
+  int ckt = 0;
+  auto issue = [&](int sl) {
+    const uint32_t st = lds0 + sl * STAGE;
+    const int64_t m0 = crt * BM;
+    const int k0 = ckt * BK;
+#pragma unroll
+    for (int q = 0; q < AIW; ++q) {
+      const int ins = wave + q * NW;
+      const int c = ins * 64 + lane;
+      const int r = c / CPR, pos = c % CPR;
+      const int kc = pos ^ ((r / RPB) % CPR);
+      const int64_t gr = m0 + r < M ? m0 + r : mlast;
+      copy16_to_lds(A + gr * lda + k0 + 4 * kc, st + ins * 1024);
+    }
+#pragma unroll
+    for (int q = 0; q < BIW; ++q) {
+      const int ins = wave + q * NW;
+      const int c = ins * 64 + lane;
+      const int r = c / CPR, pos = c % CPR;
+      const int kc = pos ^ ((r / RPB) % CPR);
+      const int gn = n0 + r < N ? n0 + r : nlast;
+      copy16_to_lds(B + (int64_t)gn * ldb + k0 + 4 * kc, st + ABYTES + ins * 1024);
+    }
+    if (cs + 1 < S) {
+      ++cs;
+      if (++ckt == nk) {
+        ckt = 0;
+        crt += G;
+      }
+    }
+  };
+
+  f32x4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = {};
+
+  const int frow = lane & 15, fg = lane >> 4;
+  f32x4 fa[2][TM], fb[2][TN];
+  auto load_frag = [&](int set, int sl, int kk) {
+    const char *st = lds + sl * STAGE;
+    const int kc = (kk >> 2) + fg;
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm0 + i * 16 + frow;
+      fa[set][i] = *(const f32x4 *)(st + r * (BK * 4) + 16 * (kc ^ ((r / RPB) % CPR)));
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int r = wn0 + j * 16 + frow;
+      fb[set][j] = *(const f32x4 *)(st + ABYTES + r * (BK * 4) + 16 * (kc ^ ((r / RPB) % CPR)));
+    }
+  };
+  auto mma = [&](int set) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[set][i][e], fb[set][j][e], acc[i][j], 0, 0, 0);
+  };
+
+#pragma unroll
+  for (int sl = 0; sl < SX; ++sl) issue(sl);
+  wait_vmcnt<(SX - 1) * LPW>();
+  lds_barrier();
+  load_frag(0, 0, 0);
+  int64_t rt = blockIdx.x;
+  int kt = 0;
+  for (int64_t s = 0; s < S; ++s) {
+    const int sl = (int)(s % SX);
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int cur = ks & 1;
+      if (ks + 1 < KS) {
+        load_frag(cur ^ 1, sl, 16 * (ks + 1));
+      } else if (s + 1 < S) {
+        wait_vmcnt<(SX - 2) * LPW>();              // K tile s + 1 landed (this wave's copies)
+        lds_barrier();                              // (every wave's); stage sl is free
+        issue(sl);
+        load_frag(cur ^ 1, (int)((s + 1) % SX), 0);
+      }
+      mma(cur);
+    }
+    if (++kt == nk) {
+      const int64_t m0 = rt * BM;
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int c = n0 + wn0 + j * 16 + frow;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t r = m0 + wm0 + i * 16 + 4 * fg + v;
+            if (r < M && c < N) C[r * ldc + c] = acc[i][j][v];
+          }
+          acc[i][j] = {};
+        }
+      kt = 0;
+      rt += G;
+    }
+  }
+  wait_vmcnt<0>();                                  // no copy may land after the workgroup ends
+}
+
+// The streamed FP32 sketch for a tile width: BN = 256 (eight waves as 2 x 4)
+// above 128 columns, else 128 (four waves, 2 x 2); 32-deep K tiles, stages
+// in 144 KB.
+template <int BM, int BN, int WR, int WC>
+static int nt32s_launch(const float *A, int64_t lda, const float *B, int64_t ldb, float *C, int64_t ldc,
+                        int64_t M, int N, int K, hipStream_t s) {
+  constexpr int BK = 32, STAGE = (BM + BN) * BK * 4;
+  constexpr int SX = 147456 / STAGE > 4 ? 4 : 147456 / STAGE;
+  auto kern = k_nt32s<BM, BN, WR, WC, BK, SX>;
+  static std::atomic<int> per_dev[64];
+  int dev = 0;
+  LSPCA_HIP(hipGetDevice(&dev));
+  int per = dev < 64 ? per_dev[dev].load(std::memory_order_relaxed) : 0;
+  if (per <= 0) {
+    int cus = 0, occ = 0;
+    LSPCA_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    LSPCA_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, 64 * WR * WC, 0));
+    per = cus * (occ > 0 ? occ : 1);
+    if (dev < 64) per_dev[dev].store(per, std::memory_order_relaxed);
+  }
+  const int64_t ntiles = (M + BM - 1) / BM;
+  const int gy = (N + BN - 1) / BN;
+  int64_t gx = (per + gy - 1) / gy;
+  gx = gx < ntiles ? gx : ntiles;
+  hipLaunchKernelGGL(kern, dim3((unsigned)gx, (unsigned)gy), dim3(64 * WR * WC), 0, s, A, lda, B, ldb, C, ldc, M,
+                     N, K);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+// Environment switch of the streamed FP32 sketch: LSPCA_NT32_STREAM=0 keeps
+// the tiled k_nt (a different order of the k sums), read per call.
+static bool nt32_stream_on() {
+  const char *e = getenv("LSPCA_NT32_STREAM");
+  return !(e && *e && atoi(e) == 0);
+}
+
+int launch_nt_sketch(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+                     int64_t ldc, int64_t M, int N, int K, hipStream_t s) {
+  if (dt == LSPCA_F32 && M >= 4096 && K >= 32 && K % 32 == 0 && lda % 4 == 0 && ldb % 4 == 0 &&
+      (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 && nt32_stream_on()) {
+    if (N > 128)
+      return nt32s_launch<128, 256, 2, 4>((const float *)A, lda, (const float *)B, ldb, (float *)C, ldc, M, N, K,
+                                          s);
+    return nt32s_launch<128, 128, 2, 2>((const float *)A, lda, (const float *)B, ldb, (float *)C, ldc, M, N, K, s);
+  }
+  return launch_nt(dt, A, lda, B, ldb, C, ldc, M, N, K, s);
 }
 
 // --------------------------------------------------------------------- TN --

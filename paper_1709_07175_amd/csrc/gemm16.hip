@@ -47,32 +47,8 @@ template <> struct H16<LSPCA_F16> {
 
 __device__ inline int mrow(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
 
-// ------------------------------------------------ direct copies into LDS --
 typedef short v4i16 __attribute__((ext_vector_type(4)));
-typedef __attribute__((address_space(3))) void lds_void_t;
-typedef __attribute__((address_space(1))) const void gbl_cvoid_t;
 typedef __attribute__((address_space(3))) v4i16 lds_v4i16_t;
-
-// One copy instruction; lds_base is wave-uniform. Written as asm: the
-// compiler's own waits for such copies are a full vmcnt(0) before every LDS
-// read, which would drain the copies in flight; here the kernel waits for
-// exactly the copies it needs (wait_vmcnt) before a barrier. The copy has no
-// destination register, and its address registers are read at issue. One
-// wait state between the M0 write and the copy.
-__device__ __forceinline__ void copy16_to_lds(const void *g, uint32_t lds_base) {
-  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds_base)
-               : "memory", "m0");
-}
-__device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(uintptr_t)(lds_void_t *)p; }
-
-// Waits and barrier as asm statements that clobber memory, so that the
-// compiler moves no LDS access across them; the copies into LDS are counted
-// by vmcnt (complete once the data is in LDS).
-template <int N> __device__ __forceinline__ void wait_vmcnt() {
-  static_assert(N >= 0 && N < 64, "vmcnt");
-  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
-}
-__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 
 // ------------------------------------------------------------------- NT16 --

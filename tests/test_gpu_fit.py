@@ -28,6 +28,10 @@ PASS_CASES = [
     (4000, 512, 64, "bf16"),
     (3008, 520, 136, "f16"),
     (6000, 256, 256, "bf16"),
+    # FP32 with m >= 4096 and n a multiple of 32: the streamed sketch kernel
+    # (128 x 128 tiles for k <= 128, 128 x 256 above), ragged last row tile
+    (5003, 512, 100, "f32"),
+    (4500, 256, 200, "f32"),
 ]
 
 
@@ -501,6 +505,34 @@ def test_direct_and_staged_sketch_agree_bitwise(gpu_lib, monkeypatch, dtype, m, 
     assert np.array_equal(out[0][0], out[1][0])
     assert np.array_equal(out[0][1], out[1][1])
     assert np.all(np.isfinite(out[1][0])) and np.abs(out[1][0]).max() > 0
+
+
+@pytest.mark.parametrize("m,n,k", [(5003, 512, 100), (4500, 256, 200), (9000, 1024, 256)])
+def test_streamed_and_tiled_fp32_sketch_both_within_bound(gpu_lib, monkeypatch, m, n, k):
+    """The FP32 sketch by the streamed kernel (the default for large stripes)
+    and by the tiled k_nt (LSPCA_NT32_STREAM=0) sum the k products in
+    different orders: both F and G within the oracle's bound, and the two
+    within twice the bound of each other."""
+    import torch
+    Xs, X64 = _data(m, n, min(k, 32), "f32")
+    X = to_device(Xs, "f32")
+    om = P.omega(n, k, "gaussian", 17, dtype="f32")
+    ref = O.streaming_lazy_fit(X64, om, k)
+    bF, bG = pass_bound(X64, om, "f32")
+    got = []
+    for env in ("0", "1"):
+        monkeypatch.setenv("LSPCA_NT32_STREAM", env)
+        F = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+        G = torch.zeros((k, k), dtype=torch.float64, device="cuda")
+        gpu_lib.accumulate(X, k, "gaussian", 17, F, G)
+        torch.cuda.synchronize()
+        got.append((F.cpu().numpy(), G.cpu().numpy()))
+    monkeypatch.delenv("LSPCA_NT32_STREAM")
+    for F, G in got:
+        assert np.all(np.abs(F - ref["F"]) <= bF), float(np.max(np.abs(F - ref["F"]) / bF))
+        assert np.all(np.abs(G - ref["G"]) <= bG), float(np.max(np.abs(G - ref["G"]) / bG))
+    assert np.all(np.abs(got[0][0] - got[1][0]) <= 2 * bF)
+    assert not np.array_equal(got[0][0], got[1][0])      # the streamed kernel did run
 
 
 @pytest.mark.parametrize("k,knob", [(40, None), (200, None), (200, "launches")])
