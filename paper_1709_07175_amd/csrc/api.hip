@@ -306,7 +306,7 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
       tm.mark(PH_SKETCH);
       if (hook) LSPCA_TRY((*hook)(Y, rows, k, false));
       // F += Y_s^T X_s (step 2b); G += Y_s^T Y_s
-      LSPCA_TRY(launch_tn(xdt, Y, k, Xs, ldx, PF, rows, k, (int)n, sf, s));
+      LSPCA_TRY(launch_tn_factor(xdt, Y, k, Xs, ldx, PF, rows, k, (int)n, sf, s));
       int sg = 0;
       if (G) {
         sg = tn_pick_splits(rows, k, k);

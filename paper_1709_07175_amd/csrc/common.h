@@ -190,6 +190,11 @@ int launch_nt_sketch(lspca_dtype dt, const void *A, int64_t lda, const void *B, 
 int launch_tn(lspca_dtype dt, const void *A, int64_t lda, const void *B,
               int64_t ldb, void *P, int64_t M_rows, int Mi, int Nj, int splits,
               hipStream_t s, int64_t ldp = 0, double alpha = 1.0, double beta = 0.0);
+// F = Y^T X of a stripe: the streamed FP32 kernel where it applies (the
+// same bits as launch_tn), else launch_tn. splits > 1 writes one partial
+// per split as launch_tn.
+int launch_tn_factor(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb, void *P,
+                     int64_t rows, int Mi, int Nj, int splits, hipStream_t s);
 int tn_pick_splits(int64_t rows, int Mi, int Nj);
 // Rows summed in FP32 by one partial of a split product (at most 65,472
 // before the launchers' rounding of the chunk to 16 or 64 rows, so at most

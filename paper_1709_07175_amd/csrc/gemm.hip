@@ -17,6 +17,7 @@
 
 #include <atomic>
 #include <cstdlib>
+#include <type_traits>
 
 // K depth and register prefetch stages of the FP32 NT product tiles.
 #ifndef LSPCA_NT32_BK
@@ -679,6 +680,198 @@ int launch_tn(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t
       set_error("tn product: dtype %d not handled here", (int)dt);
       return LSPCA_ENOTSUP;
   }
+}
+
+// ------------------------------------------------------------ TN32 stream --
+// F = Y^T X in FP32 as k_tn (split over row chunks, one FP32 partial per
+// split), with both operands copied straight into LDS (global_load_lds): a
+// K tile of BK rows is BK rows of Y's BM columns and X's BN columns, row
+// after row, through SX stages, one barrier per tile. A lane of 16-lane
+// group g reads 4 consecutive columns of row kk + g of each tile (one 16-byte
+// read) and feeds them to 4 v_mfma_f32_16x16x4f32, so MFMA row m of the e-th
+// product is tile column 4 m + e: the wave's outputs are 4 x 4 interleaved
+// 16 x 16 blocks, stored back as 16-byte pieces. Every output element gets
+// the same chain as in k_tn (per 4 rows one MFMA, rows in order), so with
+// the same chunks the two give the same bits. Fragments of the next 4 rows
+// are read while the current products run. Rows past the chunk: the copies
+// read clamped rows and the last tile's fragments are zeroed there. Needs
+// 16-byte aligned rows, lda, ldb, Mi and Nj multiples of 4.
+template <int BM, int BN, int WR, int WC, int BK, int SX>
+__global__ __launch_bounds__(64 * WR * WC) void k_tn32s(const float *__restrict__ A, int64_t lda,
+                                               const float *__restrict__ B, int64_t ldb,
+                                               float *__restrict__ P, int64_t rows, int Mi, int Nj,
+                                               int64_t chunk) {
+  constexpr int NW = WR * WC;
+  constexpr int WM = BM / WR, WN = BN / WC, TA = WM / 64, TB = WN / 64;
+  constexpr int KS = BK / 4;                       // steps of 4 rows per K tile
+  constexpr int ABYTES = BK * BM * 4, BBYTES = BK * BN * 4, STAGE = ABYTES + BBYTES;
+  constexpr int AI = ABYTES / 1024, BI = BBYTES / 1024;
+  static_assert(WM % 64 == 0 && WN % 64 == 0 && KS % 2 == 0, "tile shape");
+  static_assert(AI % NW == 0 && BI % NW == 0, "copies split evenly over the waves");
+  constexpr int AIW = AI / NW, BIW = BI / NW, LPW = AIW + BIW;
+  static_assert((SX - 1) * LPW < 64 && SX >= 2, "copies in flight");
+  constexpr int CA = BM / 4, CB = BN / 4;          // 16-byte chunks per tile row
+  __shared__ __align__(16) char lds[SX * STAGE];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm0 = (wave / WC) * WM, wn0 = (wave % WC) * WN;
+  int bx, by, bz;
+  xcd_map(bx, by, bz);
+  const int j0 = bx * BN, i0 = by * BM;
+  const int64_t rbeg = (int64_t)bz * chunk;
+  const int64_t rend = rbeg + chunk < rows ? rbeg + chunk : rows;
+  const int64_t nt = rend > rbeg ? (rend - rbeg + BK - 1) / BK : 0;
+  const uint32_t lds0 = lds_addr(lds);
+
+  auto issue = [&](int sl, int64_t t) {
+    const uint32_t st = lds0 + sl * STAGE;
+    const int64_t r0 = rbeg + t * BK;
+#pragma unroll
+    for (int q = 0; q < AIW; ++q) {
+      const int ins = wave + q * NW;
+      const int c = ins * 64 + lane;
+      const int r = c / CA, cc = c % CA;
+      const int64_t gr = r0 + r < rows ? r0 + r : rows - 1;
+      const int col = i0 + 4 * cc < Mi ? i0 + 4 * cc : Mi - 4;
+      copy16_to_lds(A + gr * lda + col, st + ins * 1024);
+    }
+#pragma unroll
+    for (int q = 0; q < BIW; ++q) {
+      const int ins = wave + q * NW;
+      const int c = ins * 64 + lane;
+      const int r = c / CB, cc = c % CB;
+      const int64_t gr = r0 + r < rows ? r0 + r : rows - 1;
+      const int col = j0 + 4 * cc < Nj ? j0 + 4 * cc : Nj - 4;
+      copy16_to_lds(B + gr * ldb + col, st + ABYTES + ins * 1024);
+    }
+  };
+
+  f32x4 acc[TA * 4][TB * 4];
+#pragma unroll
+  for (int i = 0; i < TA * 4; ++i)
+#pragma unroll
+    for (int j = 0; j < TB * 4; ++j) acc[i][j] = {};
+
+  const int fc = lane & 15, fg = lane >> 4;
+  f32x4 fa[2][TA], fb[2][TB];
+  auto load_frag = [&](int set, int sl, int kk) {
+    const char *st = lds + sl * STAGE;
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+      fa[set][a] = *(const f32x4 *)(st + (kk + fg) * (BM * 4) + (wm0 + 64 * a + 4 * fc) * 4);
+#pragma unroll
+    for (int b = 0; b < TB; ++b)
+      fb[set][b] = *(const f32x4 *)(st + ABYTES + (kk + fg) * (BN * 4) + (wn0 + 64 * b + 4 * fc) * 4);
+  };
+  // TAIL: the chunk's last tile; this lane's row kk + fg zeroed in both
+  // fragments when it is at or past the chunk's end
+  auto mma = [&](int set, auto tailc, int kk, int64_t r0) {
+    constexpr bool TAIL = decltype(tailc)::value;
+    if constexpr (TAIL) {
+      if (r0 + kk + fg >= rend) {
+#pragma unroll
+        for (int a = 0; a < TA; ++a) fa[set][a] = {};
+#pragma unroll
+        for (int b = 0; b < TB; ++b) fb[set][b] = {};
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < TA; ++a)
+#pragma unroll
+      for (int ea = 0; ea < 4; ++ea)
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+#pragma unroll
+          for (int eb = 0; eb < 4; ++eb)
+            acc[4 * a + ea][4 * b + eb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                fa[set][a][ea], fb[set][b][eb], acc[4 * a + ea][4 * b + eb], 0, 0, 0);
+  };
+  auto tile = [&](int64_t t, auto tailc) {
+    constexpr bool TAIL = decltype(tailc)::value;
+    const int sl = (int)(t % SX);
+    const int64_t r0 = rbeg + t * BK;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int cur = ks & 1;
+      if (ks + 1 < KS) {
+        load_frag(cur ^ 1, sl, 4 * (ks + 1));
+      } else if constexpr (!TAIL) {
+        wait_vmcnt<(SX - 2) * LPW>();              // tile t + 1 landed (this wave's copies)
+        lds_barrier();                              // (every wave's); stage sl is free
+        issue(sl, t + SX < nt ? t + SX : nt - 1);
+        load_frag(cur ^ 1, (int)((t + 1) % SX), 0);
+      }
+      mma(cur, tailc, 4 * ks, r0);
+    }
+  };
+
+  if (nt > 0) {
+#pragma unroll
+    for (int sl = 0; sl < SX; ++sl) issue(sl, sl < nt ? sl : nt - 1);
+    wait_vmcnt<(SX - 1) * LPW>();
+    lds_barrier();
+    load_frag(0, 0, 0);
+    for (int64_t t = 0; t + 1 < nt; ++t) tile(t, std::false_type{});
+    tile(nt - 1, std::true_type{});
+  }
+  wait_vmcnt<0>();                                  // no copy may land after the workgroup ends
+
+  // acc[4a + ea][4b + eb][v] of lane (fg, fc) is output row
+  // wm0 + 64 a + 4 (4 fg + v) + ea, column wn0 + 64 b + 4 fc + eb: for fixed
+  // (a, ea, b, v) the four eb are 4 consecutive columns
+  float *Pz = P + (int64_t)bz * Mi * Nj;
+#pragma unroll
+  for (int a = 0; a < TA; ++a)
+#pragma unroll
+    for (int ea = 0; ea < 4; ++ea)
+#pragma unroll
+      for (int b = 0; b < TB; ++b)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = i0 + wm0 + 64 * a + 4 * (4 * fg + v) + ea;
+          const int c = j0 + wn0 + 64 * b + 4 * fc;
+          if (r < Mi && c < Nj) {
+            const f32x4 w = {acc[4 * a + ea][4 * b][v], acc[4 * a + ea][4 * b + 1][v],
+                             acc[4 * a + ea][4 * b + 2][v], acc[4 * a + ea][4 * b + 3][v]};
+            *(f32x4 *)(Pz + (int64_t)r * Nj + c) = w;
+          }
+        }
+}
+
+template <int BM, int BN, int WR, int WC>
+static int tn32s_launch(const float *A, int64_t lda, const float *B, int64_t ldb, float *P, int64_t rows, int Mi,
+                        int Nj, int splits, hipStream_t s) {
+  constexpr int BK = 32, STAGE = (BM + BN) * BK * 4;
+  constexpr int SX = 147456 / STAGE > 4 ? 4 : 147456 / STAGE;
+  // the chunks of k_tn (its K depth is 16), so the two give the same bits
+  int64_t chunk = (rows + splits - 1) / splits;
+  chunk = (chunk + 15) / 16 * 16;
+  dim3 grid((unsigned)((Nj + BN - 1) / BN), (unsigned)((Mi + BM - 1) / BM), (unsigned)splits);
+  hipLaunchKernelGGL((k_tn32s<BM, BN, WR, WC, BK, SX>), grid, dim3(64 * WR * WC), 0, s, A, lda, B, ldb, P, rows,
+                     Mi, Nj, chunk);
+  LSPCA_HIP(hipGetLastError());
+  return LSPCA_OK;
+}
+
+// Environment switch of the streamed FP32 F: LSPCA_TN32_STREAM=0 keeps k_tn
+// (same bits), read per call.
+static bool tn32_stream_on() {
+  const char *e = getenv("LSPCA_TN32_STREAM");
+  return !(e && *e && atoi(e) == 0);
+}
+
+int launch_tn_factor(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb, void *P,
+                     int64_t rows, int Mi, int Nj, int splits, hipStream_t s) {
+  if (dt == LSPCA_F32 && Mi % 4 == 0 && Nj % 4 == 0 && lda % 4 == 0 && ldb % 4 == 0 && (uintptr_t)A % 16 == 0 &&
+      (uintptr_t)B % 16 == 0 && Mi > 0 && Nj > 0 && splits > 0 && tn32_stream_on()) {
+    if (Mi > 128)
+      return tn32s_launch<256, 256, 4, 2>((const float *)A, lda, (const float *)B, ldb, (float *)P, rows, Mi, Nj,
+                                          splits, s);
+    return tn32s_launch<128, 256, 2, 4>((const float *)A, lda, (const float *)B, ldb, (float *)P, rows, Mi, Nj,
+                                        splits, s);
+  }
+  return launch_tn(dt, A, lda, B, ldb, P, rows, Mi, Nj, splits, s);
 }
 
 // ------------------------------------------------------ batched projection --
