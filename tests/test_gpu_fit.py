@@ -535,6 +535,30 @@ def test_streamed_and_tiled_fp32_sketch_both_within_bound(gpu_lib, monkeypatch, 
     assert not np.array_equal(got[0][0], got[1][0])      # the streamed kernel did run
 
 
+@pytest.mark.parametrize("m,n,k", [(5000, 4096, 256), (4099, 1024, 100), (70001, 512, 128), (777, 260, 12),
+                                   (3, 64, 8), (10000, 2048, 300)])
+def test_streamed_and_tiled_fp32_F_agree_bitwise(gpu_lib, monkeypatch, m, n, k):
+    """F = Y^T X in FP32 from rows copied straight into LDS (the default) and
+    from k_tn's register-staged tiles (LSPCA_TN32_STREAM=0): the same chunks
+    and the same MFMA chain per element, so the same bits (F and G, which
+    comes from F in the small stage's inputs only through the pass)."""
+    import torch
+    Xs, _ = _data(m, n, min(k, 32), "f32")
+    X = to_device(Xs, "f32")
+    out = []
+    for env in ("0", "1"):
+        monkeypatch.setenv("LSPCA_TN32_STREAM", env)
+        F = torch.zeros((k, n), dtype=torch.float64, device="cuda")
+        G = torch.zeros((k, k), dtype=torch.float64, device="cuda")
+        gpu_lib.accumulate(X, k, "gaussian", 29, F, G)
+        torch.cuda.synchronize()
+        out.append((F.cpu().numpy(), G.cpu().numpy()))
+    monkeypatch.delenv("LSPCA_TN32_STREAM")
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.all(np.isfinite(out[1][0])) and np.abs(out[1][0]).max() > 0
+
+
 @pytest.mark.parametrize("k,knob", [(40, None), (200, None), (200, "launches")])
 def test_jacobi_sweep_limit_is_reported(gpu_lib, monkeypatch, k, knob):
     """A one-sided Jacobi run that reaches its sweep limit while its last
