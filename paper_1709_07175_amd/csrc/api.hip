@@ -1128,7 +1128,7 @@ int spca_fit(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_t ldx, 
   if (h16)
     LSPCA_TRY(launch_tn16(xdt, Qh, refine ? Ql : nullptr, m, X, ldx, (float *)PF, m, k, (int)n, sf, s));
   else
-    LSPCA_TRY(launch_tn(xdt, Q, k, X, ldx, PF, m, k, (int)n, sf, s));
+    LSPCA_TRY(launch_tn_factor(xdt, Q, k, X, ldx, PF, m, k, (int)n, sf, s));
   tm.mark(PH_PASS2);
   LSPCA_TRY(launch_reduce_add(ydt, PF, sf, (int64_t)k * n, F, 0, s));
   tm.mark(PH_REDUCE);
