@@ -85,7 +85,9 @@ def roofline(cfg, m, n, k, xbytes, esz, sketch_ms):
         flops = 2.0 * m * n * k
         peak = PEAKS["fp32_mfma_TFs"] if cfg["dtype"] == "f32" else PEAKS["fp64_mfma_TFs"]
         achieved = flops / (sketch_ms * 1e-3) / 1e12
-        return {"kernel": "k_nt (sketch Y = X Omega)", "bound": "mfma", "achieved": round(achieved, 3),
+        name = ("k_nt32s (sketch Y = X Omega; persistent, operands copied straight into LDS)"
+                if cfg["dtype"] == "f32" else "k_nt (sketch Y = X Omega)")
+        return {"kernel": name, "bound": "mfma", "achieved": round(achieved, 3),
                 "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                 "traffic": measured_traffic(cfg, m),
                 "algorithmic": f"2 m n k = {flops:.4g} flop per launch", "algorithmic_bytes": alg_bytes}
@@ -118,7 +120,9 @@ def pass_rooflines(cfg, m, n, k, xbytes, esz, phases):
     ybytes = m * k * (8 if dt == "f64" else 4)   # Y (FP64, FP32, or the two 16-bit parts)
     f_bytes = xbytes + ybytes
     tf = flops / (f_ms * 1e-3) / 1e12
-    if not h16:
+    if dt == "f32":
+        fname = "k_tn32s (F = Y^T X, operands copied straight into LDS)"
+    elif not h16:
         fname = "k_tn (F = Y^T X)"
     elif dt == "f16" and cfg["kind"] == "gaussian":
         fname = "k_tn16 (F = Y_hi^T X + Y_lo^T X, Y split from the FP32 sketch as loaded)"
