@@ -302,7 +302,7 @@ static int run_pass(const void *X, lspca_dtype xdt, int64_t m, int64_t n, int64_
     const int sf = tn_pick_splits(rows, k, (int)n);
     if (!pl.h16) {
       // Y_s = X_s Omega (Algorithm 4 step 2a)
-      LSPCA_TRY(launch_nt_sketch(xdt, Xs, ldx, OmT, n, Y, k, rows, k, (int)n, s));
+      LSPCA_TRY(launch_nt_tall(xdt, Xs, ldx, OmT, n, Y, k, rows, k, (int)n, s));
       tm.mark(PH_SKETCH);
       if (hook) LSPCA_TRY((*hook)(Y, rows, k, false));
       // F += Y_s^T X_s (step 2b); G += Y_s^T Y_s
@@ -895,7 +895,7 @@ int lspca_transform(const void *X, lspca_dtype xdt, int64_t r, int64_t n, int64_
     LSPCA_TRY(launch_nt16(xdt, X, ldx, VT, VTlo, n, (float *)Z, k, r, k, (int)n, nullptr, nullptr,
                           nullptr, 0, o.stream));
   else
-    LSPCA_TRY(launch_nt(xdt, X, ldx, VT, n, Z, k, r, k, (int)n, o.stream));
+    LSPCA_TRY(launch_nt_tall(xdt, X, ldx, VT, n, Z, k, r, k, (int)n, o.stream));
   tm.mark(PH_TRANSFORM);
   if (o.timing) LSPCA_TRY(tm.finish(&g_timings));
   return LSPCA_OK;
@@ -930,7 +930,7 @@ int lspca_transform_noalloc(const void *X, lspca_dtype xdt, int64_t r, int64_t n
     LSPCA_TRY(launch_nt16(xdt, X, ldx, VT, VTlo, n, (float *)Z, k, r, k, (int)n, nullptr, nullptr,
                           nullptr, 0, o.stream));
   else
-    LSPCA_TRY(launch_nt(xdt, X, ldx, VT, n, Z, k, r, k, (int)n, o.stream));
+    LSPCA_TRY(launch_nt_tall(xdt, X, ldx, VT, n, Z, k, r, k, (int)n, o.stream));
   return LSPCA_OK;
 }
 

@@ -183,9 +183,10 @@ int launch_omega(int64_t n, int k, int kind, uint64_t seed, uint32_t p,
 int launch_nt(lspca_dtype dt, const void *A, int64_t lda, const void *B,
               int64_t ldb, void *C, int64_t ldc, int64_t M, int N, int K,
               hipStream_t s, double alpha = 1.0, double beta = 0.0);
-// The sketch product of a stripe (C = A B^T, A the stripe's rows): the
-// streamed FP32 kernel where it applies, else launch_nt.
-int launch_nt_sketch(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+// C = A B^T for a tall A (the sketch of a stripe, the projection): the
+// streamed FP32 kernel where it applies (the same bits as launch_nt), else
+// launch_nt.
+int launch_nt_tall(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                      int64_t ldc, int64_t M, int N, int K, hipStream_t s);
 int launch_tn(lspca_dtype dt, const void *A, int64_t lda, const void *B,
               int64_t ldb, void *P, int64_t M_rows, int Mi, int Nj, int splits,

@@ -73,16 +73,18 @@ __device__ __forceinline__ void nt_tile(const T *__restrict__ A, int64_t lda,
   constexpr int MB = MF::MB, KB = MF::KB;
   constexpr int WM = BM / WGM, WN = BN / WGN;
   constexpr int TM = WM / MB, TN = WN / MB;
-  // padded row of a tile: FP32 rows 2 floats apart in bank order, so the 16
-  // rows x 4 k of a fragment read fall on distinct banks per half wave
-  constexpr int LD = BK + (sizeof(T) == 4 ? 2 : 1);
+  // padded row of a tile. FP32: rows of BK + 4 floats (16-byte aligned, an
+  // odd number of 16-byte units apart), so the 16-byte fragment reads of 16
+  // rows fall on distinct banks; FP64: BK + 1.
+  constexpr int LD = BK + (sizeof(T) == 4 ? 4 : 1);
+  static_assert(sizeof(T) != 4 || BK % 16 == 0, "FP32 tiles: K depth a multiple of 16");
   constexpr int VW = VEC ? Vec16<T>::W : 1;
   constexpr int AV = BM * BK / VW / 256, BV = BN * BK / VW / 256;
   static_assert(WGM * WGN == 4, "4 waves");
   static_assert(AV * VW * 256 == BM * BK && BV * VW * 256 == BN * BK, "tile/threads");
 
-  __shared__ T As[2][BM * LD];
-  __shared__ T Bs[2][BN * LD];
+  __shared__ __align__(16) T As[2][BM * LD];
+  __shared__ __align__(16) T Bs[2][BN * LD];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm0 = (wave / WGN) * WM, wn0 = (wave % WGN) * WN;
@@ -153,17 +155,40 @@ __device__ __forceinline__ void nt_tile(const T *__restrict__ A, int64_t lda,
     for (int j = 0; j < TN; ++j) acc[i][j] = {};
 
   auto mma = [&](int cur) {
+    if constexpr (sizeof(T) == 4) {
+      // FP32: a lane reads 4 consecutive k of its row (16 bytes) and element
+      // e of every lane's 4-vector goes to the e-th of four MFMAs, which sums
+      // k = kk + 4 g + e over the 16-lane groups g (A and B under the same
+      // map): the order of k_nt32s, so the two give the same bits
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += KB) {
-      T a[TM], b[TN];
+      for (int kk = 0; kk < BK; kk += 16) {
+        f32x4 a[TM], b[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) a[i] = As[cur][(wm0 + i * MB + lane % MB) * LD + kk + lane / MB];
+        for (int i = 0; i < TM; ++i)
+          a[i] = *(const f32x4 *)&As[cur][(wm0 + i * MB + lane % MB) * LD + kk + 4 * (lane / MB)];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) b[j] = Bs[cur][(wn0 + j * MB + lane % MB) * LD + kk + lane / MB];
+        for (int j = 0; j < TN; ++j)
+          b[j] = *(const f32x4 *)&Bs[cur][(wn0 + j * MB + lane % MB) * LD + kk + 4 * (lane / MB)];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = MF::op(a[i][e], b[j][e], acc[i][j]);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += KB) {
+        T a[TM], b[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) a[i] = As[cur][(wm0 + i * MB + lane % MB) * LD + kk + lane / MB];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) b[j] = Bs[cur][(wn0 + j * MB + lane % MB) * LD + kk + lane / MB];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = MF::op(a[i], b[j], acc[i][j]);
+      }
     }
   };
 
@@ -226,7 +251,7 @@ __device__ __forceinline__ void nt_tile(const T *__restrict__ A, int64_t lda,
 }
 
 template <typename T, int BM, int BN, int BK, int WGM, int WGN, bool VEC, int R = 1>
-__global__ __launch_bounds__(256) void k_nt(const T *__restrict__ A, int64_t lda,
+__global__ __launch_bounds__(256, 2) void k_nt(const T *__restrict__ A, int64_t lda,
                                             const T *__restrict__ B, int64_t ldb,
                                             T *__restrict__ C, int64_t ldc,
                                             int64_t M, int N, int K, T alpha, T beta) {
@@ -435,14 +460,15 @@ static int nt32s_launch(const float *A, int64_t lda, const float *B, int64_t ldb
   return LSPCA_OK;
 }
 
-// Environment switch of the streamed FP32 sketch: LSPCA_NT32_STREAM=0 keeps
-// the tiled k_nt (a different order of the k sums), read per call.
+// Environment switch of the streamed FP32 product: LSPCA_NT32_STREAM=0 keeps
+// the tiled k_nt (the same order of the k sums, so the same bits), read per
+// call.
 static bool nt32_stream_on() {
   const char *e = getenv("LSPCA_NT32_STREAM");
   return !(e && *e && atoi(e) == 0);
 }
 
-int launch_nt_sketch(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
+int launch_nt_tall(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t ldb, void *C,
                      int64_t ldc, int64_t M, int N, int K, hipStream_t s) {
   if (dt == LSPCA_F32 && M >= 4096 && K >= 32 && K % 32 == 0 && lda % 4 == 0 && ldb % 4 == 0 &&
       (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 && nt32_stream_on()) {

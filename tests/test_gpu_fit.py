@@ -508,31 +508,33 @@ def test_direct_and_staged_sketch_agree_bitwise(gpu_lib, monkeypatch, dtype, m, 
 
 
 @pytest.mark.parametrize("m,n,k", [(5003, 512, 100), (4500, 256, 200), (9000, 1024, 256)])
-def test_streamed_and_tiled_fp32_sketch_both_within_bound(gpu_lib, monkeypatch, m, n, k):
-    """The FP32 sketch by the streamed kernel (the default for large stripes)
-    and by the tiled k_nt (LSPCA_NT32_STREAM=0) sum the k products in
-    different orders: both F and G within the oracle's bound, and the two
-    within twice the bound of each other."""
+def test_streamed_and_tiled_fp32_sketch_and_projection_agree_bitwise(gpu_lib, monkeypatch, m, n, k):
+    """The FP32 sketch and projection of a tall X by the streamed kernel (the
+    default) and by the tiled k_nt (LSPCA_NT32_STREAM=0) sum the products of
+    each output element in the same order: F, G and Z agree bit for bit, and
+    F and G are within the oracle's bound."""
     import torch
     Xs, X64 = _data(m, n, min(k, 32), "f32")
     X = to_device(Xs, "f32")
     om = P.omega(n, k, "gaussian", 17, dtype="f32")
     ref = O.streaming_lazy_fit(X64, om, k)
     bF, bG = pass_bound(X64, om, "f32")
+    V = torch.from_numpy(random_orthonormal_np(n, k, np.random.default_rng(8))).cuda()
     got = []
     for env in ("0", "1"):
         monkeypatch.setenv("LSPCA_NT32_STREAM", env)
         F = torch.zeros((k, n), dtype=torch.float64, device="cuda")
         G = torch.zeros((k, k), dtype=torch.float64, device="cuda")
         gpu_lib.accumulate(X, k, "gaussian", 17, F, G)
+        Z = gpu_lib.transform(X, V)
         torch.cuda.synchronize()
-        got.append((F.cpu().numpy(), G.cpu().numpy()))
+        got.append((F.cpu().numpy(), G.cpu().numpy(), Z.cpu().numpy()))
     monkeypatch.delenv("LSPCA_NT32_STREAM")
-    for F, G in got:
-        assert np.all(np.abs(F - ref["F"]) <= bF), float(np.max(np.abs(F - ref["F"]) / bF))
-        assert np.all(np.abs(G - ref["G"]) <= bG), float(np.max(np.abs(G - ref["G"]) / bG))
-    assert np.all(np.abs(got[0][0] - got[1][0]) <= 2 * bF)
-    assert not np.array_equal(got[0][0], got[1][0])      # the streamed kernel did run
+    for a, b in zip(got[0], got[1]):
+        assert np.array_equal(a, b)
+    F, G, _ = got[1]
+    assert np.all(np.abs(F - ref["F"]) <= bF), float(np.max(np.abs(F - ref["F"]) / bF))
+    assert np.all(np.abs(G - ref["G"]) <= bG), float(np.max(np.abs(G - ref["G"]) / bG))
 
 
 @pytest.mark.parametrize("m,n,k", [(5000, 4096, 256), (4099, 1024, 100), (70001, 512, 128), (777, 260, 12),
