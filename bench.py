@@ -137,7 +137,13 @@ def pass_rooflines(cfg, m, n, k, xbytes, esz, phases):
     t_ms = avg("transform_ms", 1)
     tflops = 2.0 * m * n * k * (2 if h16 else 1)
     tbytes = xbytes + m * k * (8 if dt == "f64" else 4)
-    res["projection"] = {"kernel": "k_nt16 (Z = X V_hi + X V_lo)" if h16 else "k_nt (Z = X V)",
+    if h16:
+        pname = "k_nt16 (Z = X V_hi + X V_lo)"
+    elif dt == "f32":
+        pname = "k_nt32s (Z = X V; persistent, operands copied straight into LDS)"
+    else:
+        pname = "k_nt (Z = X V)"
+    res["projection"] = {"kernel": pname,
                          "ms": round(t_ms, 4), "flop": tflops,
                          "mfma_frac": round(tflops / (t_ms * 1e-3) / 1e12 / mfma_peak, 4),
                          "hbm_frac": round(tbytes / (t_ms * 1e-3) / 1e9 / PEAKS["hbm_GBs"], 4)}

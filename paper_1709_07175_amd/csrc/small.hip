@@ -837,7 +837,10 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
   }
   const double tol = 8.0 * (double)std::max(k, 16) * 0x1p-53;
   int sweeps = 0;
-  if ((int64_t)k * (k + 1) <= kLdsAlloc) {
+  // one workgroup holding the whole matrix in LDS below k = 128; from
+  // k = 128 on the block kernel's parallel rounds are faster (2.3 against
+  // 2.5 ms for the small stage at k = 128, n = 2048)
+  if ((int64_t)k * (k + 1) <= kLdsAlloc && k < 128) {
     hipLaunchKernelGGL(k_jacobi_lds, 1, round_threads((k + 1) / 2), 0, s, Wc, k, tol, jacobi_sweep_limit(60),
                        dflag, noconv);
     LSPCA_HIP(hipGetLastError());

@@ -218,9 +218,9 @@ def test_factor_matches_oracle_svd(gpu_lib, k, n, spectrum):
     assert np.max(np.abs(V.T @ V - np.eye(k))) < 16 * max(k, 16) * U64
 
 
-@pytest.mark.parametrize("k,n", [(256, 4096), (300, 700), (520, 1100)])
+@pytest.mark.parametrize("k,n", [(128, 2048), (256, 4096), (300, 700), (520, 1100)])
 def test_factor_jacobi_cooperative_and_per_round_launches_agree(gpu_lib, monkeypatch, k, n):
-    """The block Jacobi of k > 128 runs all sweeps in one cooperative launch;
+    """The block Jacobi of k >= 128 runs all sweeps in one cooperative launch;
     LSPCA_JACOBI=launches runs the same rounds as separate launches: the
     same rotations in the same order, so the same bits."""
     import torch
@@ -561,12 +561,12 @@ def test_streamed_and_tiled_fp32_F_agree_bitwise(gpu_lib, monkeypatch, m, n, k):
     assert np.all(np.isfinite(out[1][0])) and np.abs(out[1][0]).max() > 0
 
 
-@pytest.mark.parametrize("k,knob", [(40, None), (200, None), (200, "launches")])
+@pytest.mark.parametrize("k,knob", [(40, None), (127, None), (128, None), (200, None), (200, "launches")])
 def test_jacobi_sweep_limit_is_reported(gpu_lib, monkeypatch, k, knob):
     """A one-sided Jacobi run that reaches its sweep limit while its last
     sweep still rotated is an error (LSPCA_ENOCONV), never a silent result.
     The limit is forced down to one sweep with the library's test knob; the
-    single-workgroup kernel (k <= 128), the cooperative block kernel and the
+    single-workgroup kernel (k < 128), the cooperative block kernel and the
     per-round launches are each covered."""
     import torch
     rng = np.random.default_rng(k)
