@@ -380,12 +380,12 @@ LSPCA_API int lspca_transform_csr(const int64_t *rowptr, const int32_t *colidx, 
  * and, for host requests, while the staging arena has room for X and Z.
  * Admitted requests are packed, up to 64 at a time, into one launch of
  * persistent kernels that walk the launch's row tiles across requests: for
- * BF16/FP16 data, requests of few rows (at most 4,096) take 32 x 64 tiles,
+ * BF16/FP16 data, requests of few rows (at most 8,192) take 32 x 64 tiles,
  * so many workgroups share their walk over n, and the others the standard
- * tiles. Each launch replays a HIP graph captured at creation (request-table
- * upload and the kernels) and launches rotate over several streams, so
- * requests that arrive while others are on the device are launched at once
- * and overlap them. A request is launched from lspca_server_submit itself
+ * tiles. A launch passes its request table in the kernel arguments (no
+ * upload step) and starts only the kernels of the tile classes it uses;
+ * launches rotate over several streams, so requests that arrive while others
+ * are on the device are launched at once and overlap them. A request is launched from lspca_server_submit itself
  * when a launch slot is free, else by the server's scheduler thread.
  * Every tile shape computes an output element by the same chain of
  * matrix-core steps as lspca_transform, so a result is bitwise the same

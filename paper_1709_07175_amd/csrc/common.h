@@ -352,7 +352,8 @@ int launch_transpose_f64(const double *src, int64_t rows, int cols,
 // class, request i owns tiles [req[i].tile0, req[i+1].tile0), numbered row
 // tile major, ntn_s or ntn column tiles per row tile; ntiles_s and ntiles
 // count each class's tiles. X rows are n-contiguous (ldx), Z rows
-// k-contiguous (ldz).
+// k-contiguous (ldz). The kernels take the table by value (3,104 bytes of
+// kernel arguments, within the 4 KiB limit).
 constexpr int kProjMaxReq = 64;
 struct ProjReq {
   const void *X;
@@ -365,6 +366,7 @@ struct ProjTable {
   int32_t ntiles_s, ntn_s, pad0, pad1;
   ProjReq req[kProjMaxReq];
 };
+static_assert(sizeof(ProjTable) + 64 <= 4096, "the table travels in the kernel arguments");
 // Small tiles of the 16-bit projection Z = X (V_hi + V_lo): 32 rows x 64
 // columns, two waves. Every output element is the same chain of matrix-core
 // steps (K ascending, V_hi then V_lo per step) in every tile shape, so a
@@ -381,9 +383,11 @@ int launch_proj_batch_small(lspca_dtype dt, const ProjTable *tab, const void *VT
 void proj_tile_shape(lspca_dtype dt, int k, int *BM, int *BN);
 // Workgroups that keep every CU busy for the persistent batch kernel.
 int proj_batch_grid(lspca_dtype dt, int k, bool vec, int *grid);
-// Z = X V for every request of the table in device memory; VT = V^T in the
-// compute type (16-bit: VTh + VTl), ldv = n. vec: every X row and V^T row is
-// 16-byte aligned (n a multiple of the vector width).
+// Z = X V for every request of the table; the table (host memory) is copied
+// into the launch's kernel arguments, so it may be reused as soon as the call
+// returns. VT = V^T in the compute type (16-bit: VTh + VTl), ldv = n. vec:
+// every X row and V^T row is 16-byte aligned (n a multiple of the vector
+// width).
 int launch_proj_batch(lspca_dtype dt, const ProjTable *tab, const void *VTh, const void *VTl,
                       int64_t ldv, int k, int n, bool vec, int grid, hipStream_t s);
 

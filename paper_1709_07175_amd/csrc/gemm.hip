@@ -901,20 +901,21 @@ int launch_tn_factor(lspca_dtype dt, const void *A, int64_t lda, const void *B, 
 }
 
 // ------------------------------------------------------ batched projection --
-// Persistent: workgroup b takes tiles b, b + grid, ... of the table; the
-// request of a tile is found by binary search over the tiles' first numbers.
+// Persistent: workgroup b takes tiles b, b + grid, ... of the table (passed
+// by value in the kernel arguments); the request of a tile is found by
+// binary search over the tiles' first numbers.
 template <typename T, int BM, int BN, bool VEC>
-__global__ __launch_bounds__(256) void k_proj_batch(const ProjTable *__restrict__ tab,
+__global__ __launch_bounds__(256) void k_proj_batch(const ProjTable tab,
                                                     const T *__restrict__ VT, int64_t ldv, int N, int K) {
-  const int ntiles = tab->ntiles, nreq = tab->nreq, ntn = tab->ntn;
+  const int ntiles = tab.ntiles, nreq = tab.nreq, ntn = tab.ntn;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     int lo = 0, hi = nreq - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (tab->req[mid].tile0 <= t) lo = mid;
+      if (tab.req[mid].tile0 <= t) lo = mid;
       else hi = mid - 1;
     }
-    const ProjReq &rq = tab->req[lo];
+    const ProjReq &rq = tab.req[lo];
     const int local = t - rq.tile0, mt = local / ntn;
     nt_tile<T, BM, BN, 16, 2, 2, VEC>((const T *)rq.X, rq.ldx, VT, ldv, (T *)rq.Z, rq.ldz, rq.rows, N, K,
                                       (T)1, (T)0, (int64_t)mt * BM, (local - mt * ntn) * BN);
@@ -952,7 +953,7 @@ int proj_batch_grid(lspca_dtype dt, int k, bool vec, int *grid) {
 int launch_proj_batch(lspca_dtype dt, const ProjTable *tab, const void *VTh, const void *VTl, int64_t ldv,
                       int k, int n, bool vec, int grid, hipStream_t s) {
   if (dt == LSPCA_BF16 || dt == LSPCA_F16) return launch_proj_batch16(dt, tab, VTh, VTl, ldv, k, n, vec, grid, s);
-  void *args[] = {(void *)&tab, (void *)&VTh, (void *)&ldv, (void *)&k, (void *)&n};
+  void *args[] = {(void *)tab, (void *)&VTh, (void *)&ldv, (void *)&k, (void *)&n};
   LSPCA_HIP(hipLaunchKernel(projf_kernel(dt, vec), dim3(grid), dim3(256), args, 0, s));
   return LSPCA_OK;
 }

@@ -1160,27 +1160,28 @@ int launch_nt16(lspca_dtype dt, const void *A, int64_t lda, const void *Bh, cons
 }
 
 // ------------------------------------------------------ batched projection --
-// Persistent: workgroup b takes tiles b, b + grid, ... of the table; the
-// request of a tile is found by binary search over the tiles' first numbers.
-// Eight waves per workgroup, as the projection of lspca_transform (2 x 4 for
+// Persistent: workgroup b takes tiles b, b + grid, ... of the table (passed
+// by value: it lives in the launch's kernel arguments, so no upload precedes
+// the kernel); the request of a tile is found by binary search over the
+// tiles' first numbers. Eight waves per workgroup, as the projection of lspca_transform (2 x 4 for
 // the 256-wide V tile, else 4 x 2): the same accumulation order per element.
 constexpr int kProjThreads = 512;
 template <int BN> constexpr int proj_wr() { return BN >= 256 ? 2 : 4; }
 
 template <int DT, int BM, int BN, bool VEC>
-__global__ __launch_bounds__(kProjThreads) void k_proj_batch16(const ProjTable *__restrict__ tab,
+__global__ __launch_bounds__(kProjThreads) void k_proj_batch16(const ProjTable tab,
                                                       const uint16_t *__restrict__ Vh,
                                                       const uint16_t *__restrict__ Vl, int64_t ldv,
                                                       int N, int K) {
-  const int ntiles = tab->ntiles, nreq = tab->nreq, ntn = tab->ntn;
+  const int ntiles = tab.ntiles, nreq = tab.nreq, ntn = tab.ntn;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    int lo = tab->nreq_s, hi = nreq - 1;             // the standard-tile requests
+    int lo = tab.nreq_s, hi = nreq - 1;             // the standard-tile requests
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (tab->req[mid].tile0 <= t) lo = mid;
+      if (tab.req[mid].tile0 <= t) lo = mid;
       else hi = mid - 1;
     }
-    const ProjReq &rq = tab->req[lo];
+    const ProjReq &rq = tab.req[lo];
     const int local = t - rq.tile0, mt = local / ntn;
     nt16_tile<DT, BM, BN, true, VEC, OUT_ROWS, proj_wr<BN>(), 8 / proj_wr<BN>()>(
         (const uint16_t *)rq.X, rq.ldx, Vh, Vl, ldv, (float *)rq.Z, rq.ldz, rq.rows, N, K, nullptr, nullptr,
@@ -1192,19 +1193,19 @@ __global__ __launch_bounds__(kProjThreads) void k_proj_batch16(const ProjTable *
 // two waves each (the same per-element chain as every other tile shape).
 constexpr int kProjSmallThreads = 128;
 template <int DT, bool VEC>
-__global__ __launch_bounds__(kProjSmallThreads) void k_proj_batch16s(const ProjTable *__restrict__ tab,
+__global__ __launch_bounds__(kProjSmallThreads) void k_proj_batch16s(const ProjTable tab,
                                                             const uint16_t *__restrict__ Vh,
                                                             const uint16_t *__restrict__ Vl,
                                                             int64_t ldv, int N, int K) {
-  const int ntiles = tab->ntiles_s, nreq = tab->nreq_s, ntn = tab->ntn_s;
+  const int ntiles = tab.ntiles_s, nreq = tab.nreq_s, ntn = tab.ntn_s;
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     int lo = 0, hi = nreq - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (tab->req[mid].tile0 <= t) lo = mid;
+      if (tab.req[mid].tile0 <= t) lo = mid;
       else hi = mid - 1;
     }
-    const ProjReq &rq = tab->req[lo];
+    const ProjReq &rq = tab.req[lo];
     const int local = t - rq.tile0, mt = local / ntn;
     nt16_tile<DT, kProjSmallBM, kProjSmallBN, true, VEC, OUT_ROWS, 1, 2>(
         (const uint16_t *)rq.X, rq.ldx, Vh, Vl, ldv, (float *)rq.Z, rq.ldz, rq.rows, N, K, nullptr, nullptr,
@@ -1249,7 +1250,7 @@ int launch_proj_batch_small(lspca_dtype dt, const ProjTable *tab, const void *VT
     set_error("small projection tiles: dtype %d (16-bit only)", (int)dt);
     return LSPCA_ENOTSUP;
   }
-  void *args[] = {(void *)&tab, (void *)&VTh, (void *)&VTl, (void *)&ldv, (void *)&k, (void *)&n};
+  void *args[] = {(void *)tab, (void *)&VTh, (void *)&VTl, (void *)&ldv, (void *)&k, (void *)&n};
   LSPCA_HIP(hipLaunchKernel(proj16s_kernel(dt, vec), dim3(grid), dim3(kProjSmallThreads), args, 0, s));
   return LSPCA_OK;
 }
@@ -1278,7 +1279,7 @@ int proj16_grid(lspca_dtype dt, int k, bool vec, int *grid) {
 
 int launch_proj_batch16(lspca_dtype dt, const ProjTable *tab, const void *VTh, const void *VTl, int64_t ldv,
                         int k, int n, bool vec, int grid, hipStream_t s) {
-  void *args[] = {(void *)&tab, (void *)&VTh, (void *)&VTl, (void *)&ldv, (void *)&k, (void *)&n};
+  void *args[] = {(void *)tab, (void *)&VTh, (void *)&VTl, (void *)&ldv, (void *)&k, (void *)&n};
   LSPCA_HIP(hipLaunchKernel(proj16_kernel(dt, k, vec), dim3(grid), dim3(kProjThreads), args, 0, s));
   return LSPCA_OK;
 }

@@ -7,12 +7,14 @@
 // launches. Queued requests are admitted while fewer than max_inflight are
 // unfinished and, for requests in host memory, while the staging arena has
 // room; admitted requests (up to kProjMaxReq) are packed into the request
-// table of a free launch slot. Each slot owns a pinned host table, a device table and a HIP graph
-// captured at creation (table upload + the persistent batch kernel); slots
-// rotate over several streams, so a launch made while others run overlaps
-// them on the device. Completion is seen by polling each slot's event.
+// table of a free launch slot. The table travels by value in the kernel
+// arguments (no upload before the kernels), and a launch starts only the
+// persistent batch kernel of each tile class that has tiles; slots rotate
+// over several streams, so a launch made while others run overlaps them on
+// the device. Completion is seen by polling each slot's event.
 #include "common.h"
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -91,10 +93,7 @@ class Arena {
 };
 
 struct Slot {
-  ProjTable *host_tab = nullptr;       // pinned
-  ProjTable *dev_tab = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  ProjTable tab{};                     // copied into the kernel arguments at launch
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
@@ -167,7 +166,7 @@ bool launch_one(lspca_server *S) {
       break;
     }
   if (!sl) return false;
-  ProjTable *t = sl->host_tab;
+  ProjTable *t = &sl->tab;
   // take requests in FIFO order; small-tile ones go first in the table
   int64_t tiles[2] = {0, 0};
   while (!S->ready.empty() && (int)sl->reqs.size() < kProjMaxReq) {
@@ -206,7 +205,17 @@ bool launch_one(lspca_server *S) {
     if (r->host && e == hipSuccess)
       e = hipMemcpyAsync(S->arena + r->off, r->X, (size_t)r->rows * S->n * S->esz, hipMemcpyHostToDevice,
                          sl->stream);
-  if (e == hipSuccess) e = hipGraphLaunch(sl->exec, sl->stream);
+  // the small-tile kernel first (the latency-bound requests), then the
+  // standard one; a class without tiles is not launched, and a class with
+  // fewer tiles than the persistent grid gets one workgroup per tile
+  int rc = LSPCA_OK;
+  if (e == hipSuccess && tiles[1] > 0)
+    rc = launch_proj_batch_small(S->xdt, t, S->VTh, S->VTl, S->n, S->k, (int)S->n, S->vec,
+                                 (int)std::min<int64_t>(S->grid_s, tiles[1]), sl->stream);
+  if (e == hipSuccess && rc == LSPCA_OK && tiles[0] > 0)
+    rc = launch_proj_batch(S->xdt, t, S->VTh, S->VTl, S->n, S->k, (int)S->n, S->vec,
+                           (int)std::min<int64_t>(S->grid, tiles[0]), sl->stream);
+  if (e == hipSuccess && rc != LSPCA_OK) e = hipErrorLaunchFailure;
   for (Request *r : sl->reqs)
     if (r->host && e == hipSuccess)
       e = hipMemcpyAsync(r->Z, S->arena + r->off + r->bx, (size_t)r->rows * S->k * S->zsz,
@@ -294,13 +303,8 @@ bool is_host_pointer(const void *p) {
 }
 
 void release_resources(lspca_server *S) {
-  for (Slot &sl : S->slots) {
-    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
-    if (sl.graph) (void)hipGraphDestroy(sl.graph);
+  for (Slot &sl : S->slots)
     if (sl.done) (void)hipEventDestroy(sl.done);
-    if (sl.host_tab) (void)hipHostFree(sl.host_tab);
-    if (sl.dev_tab) (void)hipFree(sl.dev_tab);
-  }
   for (hipStream_t s : S->streams)
     if (s) (void)hipStreamDestroy(s);
   if (S->VTh) (void)hipFree(S->VTh);
@@ -319,29 +323,7 @@ int create_resources(lspca_server *S, const double *V) {
   for (int i = 0; i < kSlots; ++i) {
     Slot &sl = S->slots[i];
     sl.stream = S->streams[i % kStreams];
-    LSPCA_HIP(hipHostMalloc((void **)&sl.host_tab, sizeof(ProjTable), hipHostMallocDefault));
-    std::memset(sl.host_tab, 0, sizeof(ProjTable));
-    LSPCA_HIP(hipMalloc((void **)&sl.dev_tab, sizeof(ProjTable)));
     LSPCA_HIP(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
-    LSPCA_HIP(hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipMemcpyAsync(sl.dev_tab, sl.host_tab, sizeof(ProjTable), hipMemcpyHostToDevice, sl.stream);
-    // the small-tile kernel first (the latency-bound requests), then the
-    // standard one; a class with no tiles in a launch exits at once
-    int rc = e == hipSuccess ? LSPCA_OK : LSPCA_EHIP;
-    if (rc == LSPCA_OK && S->small_rows > 0)
-      rc = launch_proj_batch_small(S->xdt, sl.dev_tab, S->VTh, S->VTl, S->n, S->k, (int)S->n, S->vec,
-                                   S->grid_s, sl.stream);
-    if (rc == LSPCA_OK)
-      rc = launch_proj_batch(S->xdt, sl.dev_tab, S->VTh, S->VTl, S->n, S->k, (int)S->n, S->vec, S->grid,
-                             sl.stream);
-    const hipError_t ee = hipStreamEndCapture(sl.stream, &sl.graph);
-    if (e != hipSuccess) {
-      set_error("server: table upload capture failed: %s", hipGetErrorString(e));
-      return LSPCA_EHIP;
-    }
-    if (rc != LSPCA_OK) return rc;
-    LSPCA_HIP(ee);
-    LSPCA_HIP(hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0));
   }
   return LSPCA_OK;
 }
