@@ -236,6 +236,30 @@ def test_factor_jacobi_cooperative_and_per_round_launches_agree(gpu_lib, monkeyp
     assert np.max(np.abs(s1.cpu().numpy() - dr) / dr) < 1e-12
 
 
+@pytest.mark.parametrize("k,n,top,knob", [(64, 1000, 1e3, None), (256, 4096, 30.0, None),
+                                          (256, 2048, 1e6, None), (200, 700, 30.0, "launches")])
+def test_jacobi_early_stop_gives_the_same_bits(gpu_lib, monkeypatch, k, n, top, knob):
+    """The Jacobi stops after a sweep whose rotated pairs were all within
+    1e-8 of orthogonal: the sweep it skips would only have confirmed
+    convergence, so V and the singular values are the same bits as with the
+    early stop turned off (LSPCA_JACOBI_EARLY=0), for the one-workgroup
+    kernel, the cooperative block kernel and the per-round launches."""
+    import torch
+    rng = np.random.default_rng(k + 7)
+    F = (random_orthonormal_np(k, k, rng) * np.geomspace(top, 1.0, k)) @ random_orthonormal_np(n, k, rng).T
+    Ft = torch.from_numpy(F).cuda()
+    if knob:
+        monkeypatch.setenv("LSPCA_JACOBI", knob)
+    V1, s1 = gpu_lib.factor(Ft)
+    monkeypatch.setenv("LSPCA_JACOBI_EARLY", "0")
+    V2, s2 = gpu_lib.factor(Ft)
+    assert torch.equal(V1, V2) and torch.equal(s1, s2)
+    # against the oracle: the QR of F^T costs relative accuracy in proportion
+    # to the condition number (about 4e-12 at 1e6)
+    Vr, dr = O.truncated_svd(F, k)
+    assert np.max(np.abs(s1.cpu().numpy() - dr) / dr) < 1e-12 * max(1.0, top / 1e3)
+
+
 @pytest.mark.parametrize("k,n", [(7, 40), (50, 1000), (130, 700), (256, 4096)])
 def test_factor_eigenvalue_route_matches_oracle_svd(gpu_lib, k, n):
     """small_route = eig (F F^T = W Lambda W^T, D = Lambda^(1/2), V = F^T W
