@@ -236,6 +236,9 @@ constexpr int kJacobiMaxSweeps = 40;
 // (the SVD of F, then Sigma^s), clear of the sweep counters at dflag + 8
 // and dflag + 64 (kJacobiMaxSweeps + 1 ints each).
 constexpr int kNoConv = 120;
+// dflag slots of small_factor's final status: an int, a spare int, then two
+// doubles (D_k, D_1) at an 8-byte aligned offset.
+constexpr int kStatus = 122;
 namespace cg = cooperative_groups;
 
 // Sum over G lanes (16: one DPP row; 32, 64: rows combined by lane
@@ -674,10 +677,37 @@ __global__ __launch_bounds__(256) void k_colmax_sign(const double *__restrict__ 
   if (t == 0) sgn[c] = V[si[0] * k + c] < 0.0 ? -1.0 : 1.0;
 }
 
-__global__ void k_flip(double *__restrict__ V, int64_t n, int k, const double *__restrict__ sgn) {
+// The checks of the small stage and, when they pass, its outputs, in one
+// launch (no host round trip between them): status = 1 if the Cholesky of G
+// failed (gflag, when Sigma^s is asked), else 2 / 3 if the Jacobi of the SVD
+// of F / of Sigma^s stopped at its sweep limit, else 4 if D_k <= thr D_1
+// (rank deficient), else 0; then, only for 0, V = Vw with the column signs
+// sgn applied, sigma = sw and sigma_x = sx. stat[0] receives the status and
+// the doubles after stat[2] (8-byte aligned) D_k and D_1.
+__global__ void k_commit(const double *__restrict__ Vw, const double *__restrict__ sgn, int64_t n, int k,
+                         const double *__restrict__ sw, const double *__restrict__ sx, const int *__restrict__ gflag,
+                         const int *__restrict__ noconv, double thr, double *__restrict__ V,
+                         double *__restrict__ sigma, double *__restrict__ sigma_x, int *__restrict__ stat) {
+  const double dk = sw[k - 1], d1 = sw[0];
+  int status = 0;
+  if (gflag && gflag[0]) status = 1;
+  else if (noconv[0]) status = 2;
+  else if (noconv[1]) status = 3;
+  else if (!(dk > thr * d1)) status = 4;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0) {
+    stat[0] = status;
+    double *dd = (double *)(stat + 2);
+    dd[0] = dk;
+    dd[1] = d1;
+  }
+  if (status) return;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * k; e += stride)
-    if (sgn[e % k] < 0.0) V[e] = -V[e];
+  for (int64_t e = tid; e < n * k; e += stride) V[e] = sgn[e % k] < 0.0 ? -Vw[e] : Vw[e];
+  for (int64_t e = tid; e < k; e += stride) {
+    sigma[e] = sw[e];
+    if (sigma_x) sigma_x[e] = sx[e];
+  }
 }
 
 size_t sign_fix_bytes(int64_t n, int k) {
@@ -685,7 +715,9 @@ size_t sign_fix_bytes(int64_t n, int k) {
   return ws_bytes<double>((size_t)chunks * k) + ws_bytes<int64_t>((size_t)chunks * k) + ws_bytes<double>(k);
 }
 
-static int sign_fix(double *V, int64_t n, int k, Workspace &ws, hipStream_t s) {
+// Column signs of V (n x k): sgn[c] = -1 where the column's entry of largest
+// magnitude is negative (the flip itself is applied by k_commit).
+static int sign_of_cols(const double *V, int64_t n, int k, double **sgn_out, Workspace &ws, hipStream_t s) {
   const int64_t chunks = (n + kSignRows - 1) / kSignRows;
   double *pv = ws.take<double>((size_t)chunks * k);
   int64_t *pi = ws.take<int64_t>((size_t)chunks * k);
@@ -694,8 +726,7 @@ static int sign_fix(double *V, int64_t n, int k, Workspace &ws, hipStream_t s) {
   LSPCA_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_colmax_sign, (unsigned)k, 256, 0, s, V, pv, pi, chunks, k, sgn);
   LSPCA_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_flip, (unsigned)std::min<int64_t>((n * k + 255) / 256, 65536), 256, 0, s, V, n, k, sgn);
-  LSPCA_HIP(hipGetLastError());
+  *sgn_out = sgn;
   return LSPCA_OK;
 }
 
@@ -1134,7 +1165,8 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
     LSPCA_TRY(trinv_t(M, k, XT, scr, s));
     LSPCA_TRY(launch_nt(LSPCA_F64, Qa, k, XT, k, Vw, k, n, k, k, s));
   }
-  LSPCA_TRY(sign_fix(Vw, n, k, ws, s));
+  double *sgn = nullptr;
+  LSPCA_TRY(sign_of_cols(Vw, n, k, &sgn, ws, s));
 
   if (sigma_x) {
     // Sigma^s = singular values of R R_G^-1, G = R_G^T R_G.
@@ -1144,40 +1176,40 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
     LSPCA_TRY(trinv_t(M, k, XT, scr, s));
     LSPCA_TRY(launch_nt(LSPCA_F64, Rall, k, XT, k, Rtmp, k, k, k, k, s));
     LSPCA_TRY(jacobi_svd(Rtmp, false, k, Wc, nullptr, sx, dflag + 64, dflag + kNoConv + 1, s));
-    LSPCA_HIP(hipMemcpyAsync(hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
-    LSPCA_HIP(hipStreamSynchronize(s));
-    if (hflag[0]) {
+  }
+
+  // Checks and outputs in one launch, then one round trip for the status:
+  // the outputs are written only when every check passed. Rank check on D:
+  // D_k <= 64 n eps D_1 means F is numerically rank deficient (the
+  // eigenvalue route squares: sqrt(64 n eps) D_1).
+  const double rel = 64.0 * (double)n * 0x1p-52;
+  int *stat = dflag + kStatus;
+  hipLaunchKernelGGL(k_commit, (unsigned)std::max<int64_t>(1, std::min<int64_t>((n * k + 255) / 256, 65536)), 256, 0,
+                     s, Vw, sgn, n, k, sw, sx, sigma_x ? dflag : nullptr, dflag + kNoConv,
+                     route == 0 ? rel : std::sqrt(rel), V, sigma, sigma_x, stat);
+  LSPCA_HIP(hipGetLastError());
+  int hstat[6] = {0, 0, 0, 0, 0, 0};
+  LSPCA_HIP(hipMemcpyAsync(hstat, stat, sizeof(hstat), hipMemcpyDeviceToHost, s));
+  LSPCA_HIP(hipStreamSynchronize(s));
+  double dd[2];
+  std::memcpy(dd, hstat + 2, sizeof(dd));
+  switch (hstat[0]) {
+    case 0:
+      return LSPCA_OK;
+    case 1:
       set_error("factor: Cholesky of G failed (the sketch U = X Omega is rank deficient)");
       *rank_flag = 1;
       return LSPCA_ERANK;
-    }
+    case 2:
+    case 3:
+      set_error("factor: one-sided Jacobi did not converge within its sweep limit (%s)",
+                hstat[0] == 2 ? "SVD of F" : "Sigma^s");
+      return LSPCA_ENOCONV;
+    default:
+      set_error("factor: F is numerically rank deficient (D_k = %g, D_1 = %g)", dd[0], dd[1]);
+      *rank_flag = 1;
+      return LSPCA_ERANK;
   }
-
-  // Rank check on D: D_k <= 64 n eps D_1 means F is numerically rank deficient
-  // (the eigenvalue route squares: sqrt(64 n eps) D_1).
-  std::vector<double> hs(k);
-  int hnc[2] = {0, 0};
-  LSPCA_HIP(hipMemcpyAsync(hs.data(), sw, k * sizeof(double), hipMemcpyDeviceToHost, s));
-  LSPCA_HIP(hipMemcpyAsync(hnc, dflag + kNoConv, sizeof(hnc), hipMemcpyDeviceToHost, s));
-  LSPCA_HIP(hipStreamSynchronize(s));
-  if (hnc[0] || hnc[1]) {
-    set_error("factor: one-sided Jacobi did not converge within its sweep limit (%s)",
-              hnc[0] ? "SVD of F" : "Sigma^s");
-    return LSPCA_ENOCONV;
-  }
-  const double rel = 64.0 * (double)n * 0x1p-52;
-  if (!(hs[k - 1] > (route == 0 ? rel : std::sqrt(rel)) * hs[0])) {
-    set_error("factor: F is numerically rank deficient (D_k = %g, D_1 = %g)", hs[k - 1], hs[0]);
-    *rank_flag = 1;
-    return LSPCA_ERANK;
-  }
-  // Outputs are written only now that every check passed.
-  LSPCA_HIP(hipMemcpyAsync(V, Vw, (size_t)n * k * sizeof(double), hipMemcpyDeviceToDevice, s));
-  LSPCA_HIP(hipMemcpyAsync(sigma, sw, k * sizeof(double), hipMemcpyDeviceToDevice, s));
-  if (sigma_x)
-    LSPCA_HIP(hipMemcpyAsync(sigma_x, sx, k * sizeof(double), hipMemcpyDeviceToDevice, s));
-  LSPCA_HIP(hipStreamSynchronize(s));
-  return LSPCA_OK;
 }
 
 }  // namespace lspca
