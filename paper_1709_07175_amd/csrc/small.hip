@@ -239,6 +239,17 @@ constexpr int kNoConv = 120;
 // dflag slots of small_factor's final status: an int, a spare int, then two
 // doubles (D_k, D_1) at an 8-byte aligned offset.
 constexpr int kStatus = 122;
+// dflag slot of the skip flag of the speculative attempt; kRedo: the
+// attempt's internal result asking for the run with host decisions.
+constexpr int kSkip = 4;
+constexpr int kRedo = 1;
+// out[0] = any of a, b, c set; out[1..3] = a, b, c.
+__global__ void k_any3(const int *a, const int *b, const int *c, int *out) {
+  out[1] = *a;
+  out[2] = *b;
+  out[3] = *c;
+  out[0] = (*a | *b | *c) != 0;
+}
 namespace cg = cooperative_groups;
 
 // Sum over G lanes (16: one DPP row; 32, 64: rows combined by lane
@@ -385,7 +396,9 @@ __device__ void lds_sweep_all(double *cols, double *nrm, int nc, int len, int ld
 // Whole k x k problem in one workgroup (k (k + 1) <= kLdsAlloc): Wc (column
 // storage, global) is loaded into LDS, swept to convergence, written back.
 __global__ __launch_bounds__(1024) void k_jacobi_lds(double *Wc, int k, double tol, double big2,
-                                                     int max_sweeps, int *sweeps_out, int *noconv) {
+                                                     int max_sweeps, int *sweeps_out, int *noconv,
+                                                     const int *skip) {
+  if (skip && *skip) return;                        // a speculative run that is redone
   __shared__ double cols[kLdsAlloc];
   __shared__ double nrm[128];
   __shared__ int counter[2];
@@ -518,7 +531,8 @@ __device__ int jacobi_block_round(double *Wc, int k, int b, int nb, int round, i
 // flag[0]: bit 0 set by a rotation, bit 1 by a rotation above sqrt(big2).
 template <int G, int ROWS>
 __global__ __launch_bounds__(1024) void k_jacobi_block(double *Wc, int k, int b, int nb, int round,
-                                                       double tol, double big2, int *flag) {
+                                                       double tol, double big2, int *flag, const int *skip) {
+  if (skip && *skip) return;
   __shared__ double cols[kBlockLdsAlloc];
   __shared__ double nrm[64];
   __shared__ int counter[2];
@@ -535,7 +549,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_block(double *Wc, int k, int b,
 template <int G, int ROWS>
 __global__ __launch_bounds__(1024) void k_jacobi_coop(double *Wc, int k, int b, int nb, double tol,
                                                       double big2, int max_sweeps, int *counts,
-                                                      int *sweeps_out, int *noconv) {
+                                                      int *sweeps_out, int *noconv, const int *skip) {
+  if (skip && *skip) return;                        // every workgroup, before any grid barrier
   __shared__ double cols[kBlockLdsAlloc];
   __shared__ double nrm[64];
   __shared__ int counter[2], total;
@@ -678,19 +693,22 @@ __global__ __launch_bounds__(256) void k_colmax_sign(const double *__restrict__ 
 }
 
 // The checks of the small stage and, when they pass, its outputs, in one
-// launch (no host round trip between them): status = 1 if the Cholesky of G
+// launch (no host round trip between them): status = 5 if skip is set (the
+// speculative plain attempt must be redone), else 1 if the Cholesky of G
 // failed (gflag, when Sigma^s is asked), else 2 / 3 if the Jacobi of the SVD
 // of F / of Sigma^s stopped at its sweep limit, else 4 if D_k <= thr D_1
 // (rank deficient), else 0; then, only for 0, V = Vw with the column signs
 // sgn applied, sigma = sw and sigma_x = sx. stat[0] receives the status and
 // the doubles after stat[2] (8-byte aligned) D_k and D_1.
 __global__ void k_commit(const double *__restrict__ Vw, const double *__restrict__ sgn, int64_t n, int k,
-                         const double *__restrict__ sw, const double *__restrict__ sx, const int *__restrict__ gflag,
+                         const double *__restrict__ sw, const double *__restrict__ sx, const int *__restrict__ skip,
+                         const int *__restrict__ gflag,
                          const int *__restrict__ noconv, double thr, double *__restrict__ V,
                          double *__restrict__ sigma, double *__restrict__ sigma_x, int *__restrict__ stat) {
   const double dk = sw[k - 1], d1 = sw[0];
   int status = 0;
-  if (gflag && gflag[0]) status = 1;
+  if (skip && skip[0]) status = 5;
+  else if (gflag && gflag[0]) status = 1;
   else if (noconv[0]) status = 2;
   else if (noconv[1]) status = 3;
   else if (!(dk > thr * d1)) status = 4;
@@ -906,7 +924,7 @@ static int jacobi_sweep_limit(int dflt) {
 // int *noconv (zeroed by the caller) when the sweep limit was reached with
 // rotations still made in the last sweep.
 int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, double *sigma,
-               int *dflag, int *noconv, hipStream_t s) {
+               int *dflag, int *noconv, hipStream_t s, const int *skip = nullptr) {
   const int64_t kk = (int64_t)k * k;
   if (cols_given)
     LSPCA_HIP(hipMemcpyAsync(Wc, A, kk * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -922,7 +940,7 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
   // 2.5 ms for the small stage at k = 128, n = 2048)
   if ((int64_t)k * (k + 1) <= kLdsAlloc && k < 128) {
     hipLaunchKernelGGL(k_jacobi_lds, 1, round_threads((k + 1) / 2), 0, s, Wc, k, tol, big2,
-                       jacobi_sweep_limit(60), dflag, noconv);
+                       jacobi_sweep_limit(60), dflag, noconv, skip);
     LSPCA_HIP(hipGetLastError());
     if (debug_on()) {
       LSPCA_HIP(hipMemcpyAsync(&sweeps, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -951,7 +969,8 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
       int kk2 = k, bb = b, nbb = nb, ms = jacobi_sweep_limit(kJacobiMaxSweeps);
       double tl = tol, bg = big2;
       int *nc = noconv;
-      void *args[] = {&wc, &kk2, &bb, &nbb, &tl, &bg, &ms, &counts, &swo, &nc};
+      const int *sk = skip;
+      void *args[] = {&wc, &kk2, &bb, &nbb, &tl, &bg, &ms, &counts, &swo, &nc, &sk};
       const void *fn = G == 16 ? (const void *)k_jacobi_coop<16, 16>
                                : G == 32 ? (const void *)k_jacobi_coop<32, 16> : (const void *)k_jacobi_coop<64, 0>;
       const hipError_t e = hipLaunchCooperativeKernel(fn, dim3(nb / 2), dim3(G * b), args, 0, s);
@@ -972,11 +991,14 @@ int jacobi_svd(const double *A, bool cols_given, int k, double *Wc, double *UT, 
       LSPCA_TRY(zero_i32(dflag, 1, s));
       for (int round = 0; round < nb - 1; ++round) {
         if (G == 16)
-          hipLaunchKernelGGL((k_jacobi_block<16, 16>), nb / 2, G * b, 0, s, Wc, k, b, nb, round, tol, big2, dflag);
+          hipLaunchKernelGGL((k_jacobi_block<16, 16>), nb / 2, G * b, 0, s, Wc, k, b, nb, round, tol, big2, dflag,
+                             skip);
         else if (G == 32)
-          hipLaunchKernelGGL((k_jacobi_block<32, 16>), nb / 2, G * b, 0, s, Wc, k, b, nb, round, tol, big2, dflag);
+          hipLaunchKernelGGL((k_jacobi_block<32, 16>), nb / 2, G * b, 0, s, Wc, k, b, nb, round, tol, big2, dflag,
+                             skip);
         else
-          hipLaunchKernelGGL((k_jacobi_block<64, 0>), nb / 2, G * b, 0, s, Wc, k, b, nb, round, tol, big2, dflag);
+          hipLaunchKernelGGL((k_jacobi_block<64, 0>), nb / 2, G * b, 0, s, Wc, k, b, nb, round, tol, big2, dflag,
+                             skip);
         LSPCA_HIP(hipGetLastError());
       }
       LSPCA_HIP(hipMemcpyAsync(&hflag, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -1034,10 +1056,24 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
   double *prebuf = ws.take<double>(4 * kk);
   double *sw = ws.take<double>(k);
   int *dflag = ws.take<int>(kSmallFlags);
+  const size_t ws_mark = ws.used;
+
+  // Route 0 runs first as mode kSpec: the plain Cholesky QR attempt without
+  // its host round trip; the Jacobi on R runs unless a Cholesky failed or R
+  // is graded (a device flag the Jacobi kernels read), and the closing commit
+  // reports that case. Then the stage runs again with the host decisions:
+  // from the start (kFull) after a failed Cholesky, or from the
+  // preconditioner with the attempt's Q and R (kGraded).
+  enum { kSpec, kFull, kGraded };
+  const double *q_spec = nullptr;
+  auto run = [&](int mode) -> int {
+  const bool spec = mode == kSpec;
   int hflag[4];
+  int *skip = spec ? dflag + kSkip : nullptr;
+  ws.used = ws_mark;
 
   LSPCA_TRY(zero_i32(dflag + kNoConv, 2, s));
-  LSPCA_TRY(launch_transpose_f64(F, k, (int)n, Ft, s));   // F (k x n) -> F^T (n x k)
+  if (mode != kGraded) LSPCA_TRY(launch_transpose_f64(F, k, (int)n, Ft, s));   // F (k x n) -> F^T (n x k)
 
   if (route == 0) {
     // Cholesky QR passes on F^T: Q <- Q R_p^-1, R <- R_p R. Each pass's
@@ -1048,8 +1084,9 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
     const double *Qin = Ft;
     double *Qout = Qa;
     bool shifted = false;
-    bool graded = false;
-    int passes = 0;
+    bool graded = mode == kGraded;
+    int passes = mode == kGraded ? 2 : 0;
+    if (mode == kGraded) Qin = q_spec;
     for (int attempt = 0; attempt < 2 && passes == 0; ++attempt) {
       const int npass = shifted ? 3 : 2;
       Qin = Ft;
@@ -1080,6 +1117,15 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
       if (!shifted) {
         hipLaunchKernelGGL(k_diag_graded, 1, 256, 0, s, Rall, k, kPrecondRatio, dflag + 3);
         LSPCA_HIP(hipGetLastError());
+      }
+      if (spec) {
+        // skip = a Cholesky of the attempt failed or R is graded (the three
+        // flags kept beside it for the host)
+        hipLaunchKernelGGL(k_any3, 1, 1, 0, s, dflag, dflag + 1, dflag + 3, skip);
+        LSPCA_HIP(hipGetLastError());
+        passes = npass;
+        q_spec = Qin;
+        break;
       }
       LSPCA_HIP(hipMemcpyAsync(hflag, dflag, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
       LSPCA_HIP(hipStreamSynchronize(s));
@@ -1135,7 +1181,7 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
       // the rows of R2 are the columns of R2^T: column storage as is
       if (pre) LSPCA_TRY(jacobi_svd(R2, true, k, Wc, UT, sw, dflag + 8, dflag + kNoConv, s));
     }
-    if (!pre) LSPCA_TRY(jacobi_svd(Rall, false, k, Wc, UT, sw, dflag + 8, dflag + kNoConv, s));
+    if (!pre) LSPCA_TRY(jacobi_svd(Rall, false, k, Wc, UT, sw, dflag + 8, dflag + kNoConv, s, skip));
     LSPCA_TRY(launch_nt(LSPCA_F64, Q, k, UT, k, Vw, k, n, k, k, s));
   } else {
     // The route of the caption of the algorithm table: F F^T = W Lambda W^T
@@ -1185,7 +1231,7 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
   const double rel = 64.0 * (double)n * 0x1p-52;
   int *stat = dflag + kStatus;
   hipLaunchKernelGGL(k_commit, (unsigned)std::max<int64_t>(1, std::min<int64_t>((n * k + 255) / 256, 65536)), 256, 0,
-                     s, Vw, sgn, n, k, sw, sx, sigma_x ? dflag : nullptr, dflag + kNoConv,
+                     s, Vw, sgn, n, k, sw, sx, skip, sigma_x ? dflag : nullptr, dflag + kNoConv,
                      route == 0 ? rel : std::sqrt(rel), V, sigma, sigma_x, stat);
   LSPCA_HIP(hipGetLastError());
   int hstat[6] = {0, 0, 0, 0, 0, 0};
@@ -1196,6 +1242,8 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
   switch (hstat[0]) {
     case 0:
       return LSPCA_OK;
+    case 5:
+      return kRedo;
     case 1:
       set_error("factor: Cholesky of G failed (the sketch U = X Omega is rank deficient)");
       *rank_flag = 1;
@@ -1210,6 +1258,15 @@ int small_factor(const double *F, const double *G, int k, int64_t n, double *V, 
       *rank_flag = 1;
       return LSPCA_ERANK;
   }
+  };
+  if (route != 0) return run(kFull);
+  const int rc = run(kSpec);
+  if (rc != kRedo) return rc;
+  int fl[3];
+  LSPCA_HIP(hipMemcpyAsync(fl, dflag + kSkip + 1, sizeof(fl), hipMemcpyDeviceToHost, s));
+  LSPCA_HIP(hipStreamSynchronize(s));
+  if (debug_on()) fprintf(stderr, "[lspca] small stage: plain attempt %s\n", fl[0] | fl[1] ? "failed" : "graded");
+  return run(fl[0] | fl[1] ? kFull : kGraded);
 }
 
 }  // namespace lspca
