@@ -655,6 +655,13 @@ int tn_pick_splits(int64_t rows, int Mi, int Nj) {
   int64_t want = (2048 + tiles - 1) / tiles;
   int64_t maxs = (rows + 127) / 128;
   int64_t s = want < maxs ? want : maxs;
+  // the partials (Mi Nj per split) written and reduced again stay within
+  // 1/16 of the operands' bytes (rows (Mi + Nj)) once the launch has a
+  // workgroup per CU: short and wide products (20,000 x 1,000 with k = 50)
+  // otherwise move more partial bytes than they compute with
+  const int64_t lean = std::max<int64_t>((256 + tiles - 1) / tiles,
+                                         rows * (int64_t)(Mi + Nj) / (16 * (int64_t)Mi * Nj));
+  if (s > lean) s = lean;
   if (s >= 8) s = s / 8 * 8;                 // multiple of 8 for the XCD map
   // accuracy contract: each FP32 partial sums at most kTnMaxDepth rows (the
   // launchers round the chunk up to a multiple of 64 at most, which keeps it
