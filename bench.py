@@ -37,7 +37,7 @@ PEAKS = {  # MI355X published dense peaks
 MEASURED_TRAFFIC = {
     ("f32", 1_000_000, 4096, 256, "gaussian"): {
         "sources": ["paper_1709_07175_amd/csrc/gemm.hip", "paper_1709_07175_amd/csrc/common.h"],
-        "sha256": "2009971ce95dd680860d7a5184bd8e84be1c7fb150a84bb7089a0f3b585e6cac",
+        "sha256": "e1496bba4dd3126d8fa6fdcc2b9a81479d7b0ca4e8d024c1e72888c7f91b2028",
         "bytes": 1.8461e+10,
     },
     ("bf16", 1_000_000, 4096, 256, "sparse"): {
