@@ -639,6 +639,12 @@ int launch_nt(lspca_dtype dt, const void *A, int64_t lda, const void *B, int64_t
           (const float *)A, lda, (const float *)B, ldb, (float *)C, ldc, M, N, K, (float)alpha,
           (float)beta, s);
     case LSPCA_F64:
+      // narrow products with few 64-row tiles (a 20,000-row sketch with
+      // k = 50: 313 tiles for 256 CUs) balance better with 32-row tiles (the
+      // same 16 x 16 blocks and K order per output element)
+      if (N <= 64 && (M + 63) / 64 < 512 && M > 4096)
+        return nt_typed<double, 32, 64, 16, 2, 2>((const double *)A, lda, (const double *)B, ldb,
+                                                  (double *)C, ldc, M, N, K, alpha, beta, s);
       return nt_typed<double, 64, 64, 16, 2, 2>((const double *)A, lda, (const double *)B, ldb,
                                                 (double *)C, ldc, M, N, K, alpha, beta, s);
     default:
