@@ -187,7 +187,10 @@ LSPCA_API int lspca_accumulate(const void *X, lspca_dtype xdt, int64_t m, int64_
  *  (D_k <= 64 * n * eps * D_1) or, when sigma_x is requested, if chol(G)
  *  fails (Lemma of the footnote to Corollary 1 assumes rank(U) = k),
  *  ENOCONV if a one-sided Jacobi run stopped at its sweep limit (60 for
- *  k < 128, else 40) while its last sweep still rotated. Synchronous.
+ *  k < 128, else 40) while its last sweep still rotated a column pair
+ *  further than 1e-8 (relative to the column norms) from orthogonal (a
+ *  sweep whose rotations all stay within that ends the run: the next one
+ *  would not rotate). Synchronous.
  */
 LSPCA_API int lspca_factor(const double *F, const double *G, int32_t k, int64_t n,
                  const lspca_opts *opts, double *V, double *sigma,

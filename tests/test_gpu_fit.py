@@ -588,7 +588,8 @@ def test_streamed_and_tiled_fp32_F_agree_bitwise(gpu_lib, monkeypatch, m, n, k):
 @pytest.mark.parametrize("k,knob", [(40, None), (127, None), (128, None), (200, None), (200, "launches")])
 def test_jacobi_sweep_limit_is_reported(gpu_lib, monkeypatch, k, knob):
     """A one-sided Jacobi run that reaches its sweep limit while its last
-    sweep still rotated is an error (LSPCA_ENOCONV), never a silent result.
+    sweep still rotated a pair further than 1e-8 from orthogonal is an error
+    (LSPCA_ENOCONV), never a silent result.
     The limit is forced down to one sweep with the library's test knob; the
     single-workgroup kernel (k < 128), the cooperative block kernel and the
     per-round launches are each covered."""
